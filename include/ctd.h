@@ -1,0 +1,208 @@
+/*
+ * ctd.h -- C-ABI of the MI355X convolution-tensor-decomposition (CTD) solver
+ * for the Allen-Cahn equation (Lu, Yuan, Guo, arXiv 2410.15519).
+ *
+ * One time step of the stabilized semi-implicit scheme (Sec. 2.5,
+ * eq. AC-discrete-semi-stable-K) is solved in separated form (Sec. 3.1,
+ * eq. CTD): the new field is a sum of rank-one products of 1D convolution-FE
+ * functions (Sec. 3.2, App. B/C), built by greedy enrichment with alternating
+ * fixed-point sweeps over the directions (Sec. 3.3; directional systems
+ * eq. ux/KxQx, derived in App. D).  All arithmetic of a step runs in HIP
+ * kernels for gfx950; the host only builds the 1D CFE tables at init and
+ * sequences launches.
+ *
+ * Conventions
+ *   - Every function returns an int status: CTD_OK (0) or a negative code.
+ *     Nothing aborts or throws; ctd_last_error() gives a message.
+ *   - Host arrays passed in are copied during the call; the caller keeps
+ *     ownership.  Device memory is owned by the library (hipMalloc) and
+ *     released by ctd_destroy / ctd_batch_destroy.
+ *   - All device work of a handle is ordered on the HIP stream given at
+ *     creation (NULL = the null stream).  One host thread at a time per handle.
+ *   - Factor matrices are column-major: column m (one mode) is contiguous,
+ *     element (i, m) at [m * nodes + i].  Nodal coefficients equal nodal
+ *     values (Kronecker-delta property, Sec. 3.2).
+ *   - Dense nodal grids are C-ordered: axis 0 slowest.
+ */
+#ifndef CTD_H
+#define CTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CTD_ABI_VERSION 1
+
+enum {
+  CTD_OK = 0,
+  CTD_EINVAL = -1,        /* invalid parameter; nothing allocated           */
+  CTD_ENOMEM = -2,        /* device or host allocation failed               */
+  CTD_EDEVICE = -3,       /* HIP runtime error                              */
+  CTD_ENONFINITE = -4,    /* a mode amplitude became NaN/Inf                */
+  CTD_ESTATE = -5,        /* call not valid in the handle's current state   */
+  CTD_EUNSUPPORTED = -6,  /* valid but outside what this build supports      */
+  CTD_EAGAIN = -7         /* server: not finished / no free slot            */
+};
+
+enum { CTD_PREC_FP64 = 0, CTD_PREC_MIXED = 1 };
+enum { CTD_SCHED_ADAPTIVE = 0, CTD_SCHED_REPLAY = 1 };
+enum { CTD_INIT_HASH = 0, CTD_INIT_WARM = 1 };
+enum { CTD_DTYPE_F64 = 0, CTD_DTYPE_F32 = 1 };
+
+/*
+ * Problem statement (Sec. 2.1-2.5, Sec. 3.2 parameters p, a, s; Sec. 3.3
+ * tolerances eps1, eps2 and the adaptive mode cap M_c).
+ *
+ * Coefficients: either the paper form (L, kappa, a0, alpha) or, when all four
+ * are NaN, the epsilon form u_t = eps^2 Lap u - (u^3 - u) with stabilizer S,
+ * read as L = 1, kappa = eps^2, a0 = 1/4, alpha = S.
+ * Mesh: uniform, nodes[d] >= 2*patch_s + 2 nodes on [lo[d], hi[d]].
+ * CFE space: patch size patch_s >= 1, reproduction order 0 <= poly_p <=
+ *   patch_s, dilation a in natural element units (element = [-1, 1]),
+ *   gauss_points Gauss-Legendre points per element for every integral.
+ * Stopping: fixed-point sweeps stop when the relative Frobenius change of the
+ *   nodal rank-one term is <= fp_tol (from the second sweep) or after
+ *   fp_max_iter sweeps; enrichment stops once a mode's nodal max is
+ *   <= enrich_tol, or at max_modes (the cap of the adaptive variant).
+ * Zero values of dilation_a, gauss_points, fp_tol, fp_max_iter select the
+ * defaults 12, 5, 1e-2, 20 (ctd_problem_default fills everything).
+ */
+typedef struct ctd_problem {
+  int32_t abi_version;      /* CTD_ABI_VERSION */
+  int32_t dim;              /* 2 or 3 */
+  int64_t nodes[3];
+  double lo[3], hi[3];
+  double eps, S, dt;
+  double L, kappa, a0, alpha;
+  int32_t patch_s, poly_p;
+  double dilation_a;
+  int32_t gauss_points;
+  int32_t fp_max_iter;
+  double fp_tol;
+  double enrich_tol;
+  int32_t max_modes;
+  int32_t precision;        /* CTD_PREC_FP64 | CTD_PREC_MIXED */
+  int32_t schedule;         /* CTD_SCHED_ADAPTIVE | CTD_SCHED_REPLAY */
+  int32_t init_mode;        /* CTD_INIT_HASH | CTD_INIT_WARM */
+  int32_t energy_each_step; /* nonzero: ctd_step fills info.energy */
+  int32_t reserved;
+  uint64_t seed;            /* keys the counter-based mode initialisation */
+} ctd_problem;
+
+/* Per-step report of ctd_step. */
+typedef struct ctd_step_info {
+  int32_t modes;            /* modes of u^{k+1} */
+  int32_t sweeps;           /* fixed-point sweeps summed over modes */
+  int32_t capped;           /* 1 if max_modes ended the enrichment */
+  int32_t fp_unconverged;   /* modes that hit fp_max_iter */
+  int32_t zero_mode;        /* 1 if a zero-amplitude mode ended the step */
+  int32_t energy_increase;  /* 1 if energy rose by more than 1e-12 relative */
+  double energy;            /* E(u^{k+1}) if energy_each_step, else NaN */
+  double last_term_max;     /* nodal max of the last appended mode */
+  double ms;                /* wall time of the step on the host clock */
+} ctd_step_info;
+
+typedef struct ctd_solver ctd_solver;
+
+/* Fill *p with defaults: dim 2, 64 nodes on [0,1], eps 0.02, S 2, dt 1e-3,
+ * s = 2, p = 2, a = 12, 5 Gauss points, fp_tol 1e-2, 20 sweeps,
+ * enrich_tol 1e-8, 64 modes, FP64, adaptive, hash init. */
+int ctd_problem_default(ctd_problem* p);
+
+/* Validate the problem, build the 1D CFE tables (App. B/C, eq. KxxMxx) on the
+ * host in FP64, allocate device memory and load the initial field
+ *   u0 = sum_m amp[m] prod_d init[d][:, m]     (eq. CTD),
+ * init[d]: host, nodes[d] x m0 column-major; amp: host, m0 values or NULL
+ * (all ones).  hip_stream: hipStream_t or NULL.  On error *out stays NULL. */
+int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
+             const double* amp, void* hip_stream, ctd_solver** out);
+
+/* Advance nsteps time steps (Sec. 3.3 algorithm per step).  info: host array
+ * of nsteps entries or NULL.  Synchronises the stream before returning. */
+int ctd_step(ctd_solver* s, int32_t nsteps, ctd_step_info* info);
+
+/* Discrete energy E(u^k) = int a0 (u^2-1)^2 + kappa/2 |grad u|^2 (Sec. 2.1)
+ * on the separated tensor Gauss rule, FP64. */
+int ctd_energy(ctd_solver* s, double* E);
+
+/* Dense nodal field into a caller buffer (C order, axis 0 slowest), dtype
+ * CTD_DTYPE_F64 or CTD_DTYPE_F32; on_device != 0: out is device memory,
+ * else host memory of prod(nodes) elements. */
+int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device);
+
+/* Current separated field: *m modes; amp (cap values) and out[d]
+ * (nodes[d] x cap, column-major), host buffers; any may be NULL to query *m. */
+int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out,
+                  int32_t cap);
+
+/* Time-step counter (keys the mode initialisation); settable for resume. */
+int ctd_get_step_index(ctd_solver* s, int64_t* k);
+int ctd_set_step_index(ctd_solver* s, int64_t k);
+
+/* Decision log of the last ctd_step call: per step, the number of modes
+ * followed by the sweep count of each mode, concatenated.  *len = ints
+ * written (or needed, if cap is too small -> CTD_EINVAL). */
+int ctd_get_decisions(ctd_solver* s, int32_t* buf, int64_t cap, int64_t* len);
+
+/* Decisions for the next ctd_step call in CTD_SCHED_REPLAY mode, same
+ * format; the step then takes no threshold decision of its own. */
+int ctd_set_decisions(ctd_solver* s, const int32_t* buf, int64_t len);
+
+/* Message of the last error on this handle (or of the last failed
+ * ctd_init when s is NULL); never NULL. */
+const char* ctd_last_error(const ctd_solver* s);
+
+void ctd_destroy(ctd_solver* s);   /* NULL-safe; synchronises the stream */
+
+/* ---------------------------------------------------------------------- *
+ * Batched execution: many independent instances stepped together, their
+ * launches fused per phase (one grid covers every instance's work items).
+ * ---------------------------------------------------------------------- */
+typedef struct ctd_batch ctd_batch;
+
+/* problems[i], m0[i], inits[i] (dim pointers), amps[i] (or NULL) as in
+ * ctd_init.  All instances share the stream. */
+int ctd_batch_create(int32_t count, const ctd_problem* problems,
+                     const int32_t* m0, const double* const* const* inits,
+                     const double* const* amps, void* hip_stream,
+                     ctd_batch** out);
+/* Advance every instance nsteps steps; info: count * nsteps entries
+ * (instance-major) or NULL. */
+int ctd_batch_step(ctd_batch* b, int32_t nsteps, ctd_step_info* info);
+int ctd_batch_get_modes(ctd_batch* b, int32_t i, int32_t* m, double* amp,
+                        double* const* out, int32_t cap);
+int ctd_batch_reconstruct(ctd_batch* b, int32_t i, void* out, int32_t dtype,
+                          int32_t on_device);
+const char* ctd_batch_last_error(const ctd_batch* b);
+void ctd_batch_destroy(ctd_batch* b);
+
+/* ---------------------------------------------------------------------- *
+ * Low-level kernel entry points on caller device memory (tests, tuning).
+ * ---------------------------------------------------------------------- */
+
+/* Symmetric positive definite banded solve, FP64: count independent systems
+ * A_k x_k = b_k, A_k = alpha[k] Mb + beta[k] Kb with Mb, Kb in lower band
+ * storage ((bw+1) x n, row t holds A[i+t, i] at [t*n + i]).  b, x: device,
+ * count x n.  alpha/beta: device, count values. */
+int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
+                          const double* Kb, const double* alpha,
+                          const double* beta, const double* b, double* x,
+                          int32_t count, void* hip_stream);
+
+/* Nonlinear load of the directional system for direction d (the M_xy u_y
+ * term of eq. KxQx and its 3D analogue), on the handle's current u^k:
+ *   out[i] = int N~_i(x_d) prod_{e != d} u_e(x_e) L w(u^k) dOmega,
+ * evaluated by the same kernels as ctd_step (2D: M_xy product; 3D: separated
+ * cubic contraction plus the linear part through M X^k).  u: dim host
+ * pointers, u[e] of nodes[e] values for e != d (u[d] ignored); out: host,
+ * nodes[d] values.  Uses the handle's step scratch; call between steps. */
+int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u,
+                       double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTD_H */

@@ -1,0 +1,141 @@
+// Internal declarations shared by the host orchestration and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ctd.h"
+
+namespace ctd {
+
+constexpr int kMaxDim = 3;
+constexpr int kTile = 16;          // mode tile of the cubic contractions
+constexpr int kTileSq = kTile * kTile;
+
+// Host FP64 tables of one axis (built by build_axis).
+struct AxisTables {
+  int n = 0, ne = 0, ng = 0, nq = 0, s = 0, p = 0, SW = 0, B = 0;
+  double a = 0, lo = 0, hi = 0, h = 0;
+  std::vector<double> phi, dphi;  // nq x SW
+  std::vector<double> w;          // nq
+  std::vector<double> Mb, Kb;     // (B+1) x n lower band
+};
+
+int build_axis(int64_t n, double lo, double hi, int s, int p, double a, int ng,
+               AxisTables& ax, std::string& err);
+void gauss_legendre(int ng, std::vector<double>& x, std::vector<double>& w);
+
+// Device buffers of one axis of one instance.
+struct DevAxis {
+  int n, nq, ng, SW, B, s;
+  double* phi;      // nq x SW
+  float* phif;
+  double* w;        // nq
+  double* Mb;       // (B+1) x n
+  double* Kb;
+  double* Xk;       // n x Mcap, factors of u^k
+  double* MXk;      // n x Mcap, M X^k
+  double* Xh;       // nq x ldh, Phi X^k sigma^(1/D) (row-major)
+  float* Xhf;
+  double* X;        // n x Mcap, factors of u^{k+1}
+  double* MX;
+  double* KX;
+  double* u;        // n, current mode factor (unit M-norm after finalize)
+  double* up;       // n, same factor one sweep earlier
+  double* Mu;       // n
+  double* Ku;       // n
+  double* rhs;      // n
+  double* F;        // n, nonlinear load (2D route)
+  double* v;        // nq, W * (Phi u)
+  float* vf;
+  double* gm;       // Mcap: u . MX[:, m]
+  double* gk;       // Mcap: u . KX[:, m]
+  double* gmk;      // Mcap: u . MXk[:, j]
+  void* g;          // cubic Gram of u (3D): ntri x 256 x 16 (T)
+};
+
+// Scalars shared by kernels of one instance (device memory).
+struct DevScalars {
+  double sigma[kMaxDim];   // amplitude after solving direction d
+  double m[kMaxDim];       // u.M.u (=1 after normalisation, up to rounding)
+  double k[kMaxDim];       // u.K.u
+  double uu[kMaxDim], uup[kMaxDim], upup[kMaxDim];
+  double umax[kMaxDim];
+  double alpha[kMaxDim], beta[kMaxDim];
+  double sigma_prev;
+  double change;
+  double term_max;
+  int32_t converged;
+  int32_t zero;
+  int32_t nonfinite;
+  int32_t nmodes;
+  int32_t stop;            // 1 tol, 2 cap
+  int32_t pad;
+};
+
+// Everything a kernel may need about one instance, passed by value.
+struct DevInst {
+  int dim;
+  int Mk;            // modes of u^k
+  int Mkp;           // Mk rounded up to kTile (ldh of Xh)
+  int nb;            // Mkp / kTile
+  int ntri;          // tile triples A <= B <= C
+  int Mcap;          // capacity of factor matrices
+  int mixed;
+  double c, lam, omega, a0, kappa;
+  double fp_tol, enrich_tol;
+  int max_modes;
+  uint64_t seed;
+  double* sk;        // sigma of u^k (Mcap)
+  double* sn;        // sigma of u^{k+1} (Mcap)
+  DevScalars* sc;
+  DevAxis ax[kMaxDim];
+  // cubic route (3D)
+  const int4* tri;   // (A, B, C, weight) per triple, C-major order
+  void* gpart;       // nsplit_g x ntri x 4096 (T)
+  void* S;           // ntri x 4096 (T), weighted g_e * g_f
+  double* hpart;     // nsplit_h x nqmax
+  int nsplit_g, nsplit_h;
+  // 2D route
+  double* T1;        // n0 x nq1
+  void* Mxy;         // n0 x n1 (T), row-major
+  void* MxyT;        // n1 x n0 (T)
+};
+
+// ---------------------------------------------------------------- kernels
+// (defined in kernels.hip; host wrappers launch them on a stream)
+hipError_t launch_quad_eval(const DevInst& I, int d, hipStream_t st);
+hipError_t launch_band_mv(const DevAxis& A, const double* band, const double* X,
+                          double* Y, int ncols, hipStream_t st);
+hipError_t launch_init_mode(const DevInst& I, int64_t step, int mode, int warm,
+                            hipStream_t st);
+hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
+                           hipStream_t st);
+hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
+hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
+hipError_t launch_solve(const DevInst& I, int d, int sweep, hipStream_t st);
+hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
+hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
+hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st);
+hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st);
+hipError_t launch_mxy_build(const DevInst& I, hipStream_t st);
+hipError_t launch_gemv(const DevInst& I, int d, hipStream_t st);
+hipError_t launch_reset_scalars(const DevInst& I, hipStream_t st);
+hipError_t launch_energy(const DevInst& I, double* partial, int* npartial,
+                         hipStream_t st);
+hipError_t launch_energy_grams(const DevInst& I, int M, double* partial,
+                               hipStream_t st);
+hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
+                              hipStream_t st);
+hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
+                                   const double* Kb, const double* alpha,
+                                   const double* beta, const double* b,
+                                   double* x, int count, hipStream_t st);
+int solve_lds_max_n(int B);
+hipError_t configure_kernels();
+int max_lds_bytes();
+
+}  // namespace ctd

@@ -1,0 +1,661 @@
+// Host orchestration of the CTD step and the C-ABI entry points.
+//
+// One time step (Sec. 3.3): freeze u^k (Gauss-point tables, 2D: M_xy), then
+// for each new mode: initialise, sweep the directions with the directional
+// solves of eq. (ux)/(KxQx) (3D analogue), test the fixed point, append, test
+// the enrichment stop.  All arithmetic runs in the kernels of kernels.hip; the
+// host sequences launches on the handle's stream and reads back a few scalars
+// per sweep to take the threshold decisions (adaptive schedule) or follows a
+// given decision log (replay schedule).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "ctd_internal.h"
+
+using namespace ctd;
+
+namespace {
+
+thread_local std::string g_init_error = "no error";
+
+struct DeviceArena {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  hipError_t alloc(void** p, size_t n) {
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(p, n);
+    if (e == hipSuccess) {
+      ptrs.push_back(*p);
+      bytes += n;
+      e = hipMemset(*p, 0, n);
+    }
+    return e;
+  }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+};
+
+int tri_count(int nb) { return nb * (nb + 1) * (nb + 2) / 6; }
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+struct ctd_solver {
+  ctd_problem P{};
+  int dim = 0;
+  double L = 0, kappa = 0, a0 = 0, alpha = 0;
+  double c = 0, lam = 0, omega = 0;
+  hipStream_t stream = nullptr;
+  AxisTables ax[kMaxDim];
+  DeviceArena arena;
+  DevInst I{};
+  DevScalars* sc_host = nullptr;   // pinned
+  double* KXk[kMaxDim] = {};       // K X^k (energy of u^k)
+  int Mk = 0, Mcap = 0, Mkp_max = 0, ntri_max = 0;
+  int nsplit_g_cap = 0;
+  int64_t step_index = 0;
+  std::vector<int32_t> decisions_last, decisions_next;
+  std::string err = "no error";
+  double energy_prev = std::numeric_limits<double>::quiet_NaN();
+  double* energy_partial = nullptr;
+  size_t energy_partial_cap = 0;
+  std::vector<double> host_tmp;
+
+  int fail(int code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  int hip_fail(hipError_t e, const char* where) {
+    err = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
+    return CTD_EDEVICE;
+  }
+};
+
+#define HIPCHK(s, expr)                                   \
+  do {                                                    \
+    hipError_t _e = (expr);                               \
+    if (_e != hipSuccess) return (s)->hip_fail(_e, #expr); \
+  } while (0)
+
+namespace {
+
+int validate(const ctd_problem* p, std::string& err) {
+  if (!p) { err = "problem is NULL"; return CTD_EINVAL; }
+  if (p->abi_version != CTD_ABI_VERSION) { err = "abi_version mismatch"; return CTD_EINVAL; }
+  if (p->dim != 2 && p->dim != 3) { err = "dim must be 2 or 3"; return CTD_EINVAL; }
+  if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { err = "dt must be positive"; return CTD_EINVAL; }
+  if (p->max_modes < 1 || p->max_modes > 1024) { err = "max_modes must be in [1, 1024]"; return CTD_EINVAL; }
+  if (p->fp_max_iter < 0 || p->fp_tol < 0.0) { err = "negative fixed-point settings"; return CTD_EINVAL; }
+  if (!(p->enrich_tol >= 0.0)) { err = "enrich_tol must be >= 0"; return CTD_EINVAL; }
+  if (p->precision != CTD_PREC_FP64 && p->precision != CTD_PREC_MIXED) { err = "bad precision"; return CTD_EINVAL; }
+  if (p->schedule != CTD_SCHED_ADAPTIVE && p->schedule != CTD_SCHED_REPLAY) { err = "bad schedule"; return CTD_EINVAL; }
+  if (p->init_mode != CTD_INIT_HASH && p->init_mode != CTD_INIT_WARM) { err = "bad init_mode"; return CTD_EINVAL; }
+  const bool paper = std::isfinite(p->L) || std::isfinite(p->kappa) || std::isfinite(p->a0) || std::isfinite(p->alpha);
+  if (paper) {
+    if (!(p->L > 0) || !(p->kappa >= 0) || !(p->a0 >= 0) || !(p->alpha >= 0)) {
+      err = "paper-form coefficients must all be given: L > 0, kappa >= 0, a0 >= 0, alpha >= 0";
+      return CTD_EINVAL;
+    }
+  } else {
+    if (!(p->eps > 0) || !std::isfinite(p->eps)) { err = "eps must be positive"; return CTD_EINVAL; }
+    if (!(p->S >= 0) || !std::isfinite(p->S)) { err = "S must be >= 0"; return CTD_EINVAL; }
+  }
+  if (p->patch_s < 1 || p->patch_s > 3) { err = "patch_s must be 1, 2 or 3"; return CTD_EINVAL; }
+  if (p->poly_p < 0 || p->poly_p > p->patch_s) { err = "need 0 <= poly_p <= patch_s"; return CTD_EINVAL; }
+  for (int d = 0; d < p->dim; ++d) {
+    if (p->nodes[d] < 2 * p->patch_s + 2) { err = "need nodes >= 2*patch_s+2 on every axis"; return CTD_EINVAL; }
+    if (!(p->hi[d] > p->lo[d])) { err = "need hi > lo on every axis"; return CTD_EINVAL; }
+  }
+  return CTD_OK;
+}
+
+// Tile triples A <= B <= C in C-major order with multiplicities.
+std::vector<int4> make_triples(int nb) {
+  std::vector<int4> t;
+  for (int C = 0; C < nb; ++C)
+    for (int B = 0; B <= C; ++B)
+      for (int A = 0; A <= B; ++A) {
+        int w = (A == B && B == C) ? 1 : ((A == B || B == C) ? 3 : 6);
+        t.push_back(int4{A, B, C, w});
+      }
+  return t;
+}
+
+void update_view(ctd_solver* s) {
+  DevInst& I = s->I;
+  I.Mk = s->Mk;
+  I.Mkp = std::max(kTile, round_up(s->Mk, kTile));
+  I.nb = I.Mkp / kTile;
+  I.ntri = tri_count(I.nb);
+  if (s->dim == 3) {
+    int nqmin = 1 << 30;
+    for (int d = 0; d < 3; ++d) nqmin = std::min(nqmin, I.ax[d].nq);
+    int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
+    ng = std::min(ng, s->nsplit_g_cap / I.ntri);
+    I.nsplit_g = std::max(1, ng);
+    int nqt = (nqmin + 63) / 64;
+    I.nsplit_h = std::max(1, std::min(I.ntri, (1024 + nqt - 1) / nqt));
+  }
+}
+
+int alloc_instance(ctd_solver* s, int m0) {
+  DeviceArena& A = s->arena;
+  DevInst& I = s->I;
+  const bool mixed = s->P.precision == CTD_PREC_MIXED;
+  s->Mcap = std::max(s->P.max_modes, m0);
+  s->Mkp_max = std::max(kTile, round_up(s->Mcap, kTile));
+  const int nbmax = s->Mkp_max / kTile;
+  s->ntri_max = tri_count(nbmax);
+  s->nsplit_g_cap = 1024 + s->ntri_max;
+  const size_t Tsz = mixed ? sizeof(float) : sizeof(double);
+  I.dim = s->dim;
+  I.Mcap = s->Mcap;
+  I.mixed = mixed;
+  I.c = s->c; I.lam = s->lam; I.omega = s->omega; I.a0 = s->a0; I.kappa = s->kappa;
+  I.fp_tol = s->P.fp_tol;
+  I.enrich_tol = s->P.enrich_tol;
+  I.max_modes = s->P.max_modes;
+  I.seed = s->P.seed;
+#define AL(ptr, bytes) HIPCHK(s, A.alloc((void**)&(ptr), (bytes)))
+  AL(I.sk, sizeof(double) * s->Mcap);
+  AL(I.sn, sizeof(double) * s->Mcap);
+  AL(I.sc, sizeof(DevScalars));
+  int nqmax = 0;
+  for (int d = 0; d < s->dim; ++d) {
+    const AxisTables& T = s->ax[d];
+    DevAxis& X = I.ax[d];
+    X.n = T.n; X.nq = T.nq; X.ng = T.ng; X.SW = T.SW; X.B = T.B; X.s = T.s;
+    nqmax = std::max(nqmax, T.nq);
+    const size_t n = T.n, nq = T.nq, M = s->Mcap;
+    AL(X.phi, sizeof(double) * nq * T.SW);
+    AL(X.phif, sizeof(float) * nq * T.SW);
+    AL(X.w, sizeof(double) * nq);
+    AL(X.Mb, sizeof(double) * (T.B + 1) * n);
+    AL(X.Kb, sizeof(double) * (T.B + 1) * n);
+    AL(X.Xk, sizeof(double) * n * M);
+    AL(X.MXk, sizeof(double) * n * M);
+    AL(s->KXk[d], sizeof(double) * n * M);
+    AL(X.Xh, sizeof(double) * nq * s->Mkp_max);
+    if (mixed) AL(X.Xhf, sizeof(float) * nq * s->Mkp_max);
+    AL(X.X, sizeof(double) * n * M);
+    AL(X.MX, sizeof(double) * n * M);
+    AL(X.KX, sizeof(double) * n * M);
+    AL(X.u, sizeof(double) * n);
+    AL(X.up, sizeof(double) * n);
+    AL(X.Mu, sizeof(double) * n);
+    AL(X.Ku, sizeof(double) * n);
+    AL(X.rhs, sizeof(double) * n);
+    AL(X.F, sizeof(double) * n);
+    AL(X.v, sizeof(double) * nq);
+    if (mixed) AL(X.vf, sizeof(float) * nq);
+    AL(X.gm, sizeof(double) * M);
+    AL(X.gk, sizeof(double) * M);
+    AL(X.gmk, sizeof(double) * M);
+    if (s->dim == 3) AL(X.g, Tsz * (size_t)s->ntri_max * kTileSq * kTile);
+    std::vector<float> pf(T.phi.begin(), T.phi.end());
+    HIPCHK(s, hipMemcpy(X.phi, T.phi.data(), sizeof(double) * nq * T.SW, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(X.phif, pf.data(), sizeof(float) * nq * T.SW, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(X.w, T.w.data(), sizeof(double) * nq, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(X.Mb, T.Mb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
+    HIPCHK(s, hipMemcpy(X.Kb, T.Kb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
+  }
+  if (s->dim == 3) {
+    std::vector<int4> tri = make_triples(nbmax);
+    int4* td;
+    AL(td, sizeof(int4) * tri.size());
+    HIPCHK(s, hipMemcpy(td, tri.data(), sizeof(int4) * tri.size(), hipMemcpyHostToDevice));
+    I.tri = td;
+    AL(I.gpart, Tsz * (size_t)s->nsplit_g_cap * kTileSq * kTile);
+    AL(I.S, Tsz * (size_t)s->ntri_max * kTileSq * kTile);
+    const int nqt = (nqmax + 63) / 64;
+    const int nsh_cap = std::max(1, std::min(s->ntri_max, (1024 + nqt - 1) / nqt)) + 1;
+    AL(I.hpart, sizeof(double) * (size_t)(s->ntri_max + nsh_cap) * nqmax);
+  } else {
+    const size_t n0 = s->ax[0].n, n1 = s->ax[1].n, nq1 = s->ax[1].nq;
+    AL(I.T1, sizeof(double) * n0 * nq1);
+    AL(I.Mxy, Tsz * n0 * n1);
+    AL(I.MxyT, Tsz * n0 * n1);
+  }
+  const int nbmx = nbmax;
+  const int npt = nbmx * (nbmx + 1) / 2;
+  s->energy_partial_cap = std::max<size_t>((size_t)npt * (npt + 1) / 2 * 16, 2 * (size_t)s->Mcap) + 16;
+  AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
+#undef AL
+  HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  return CTD_OK;
+}
+
+// Gauss-point tables of u^k and, on the 2D route, M_xy (frozen for the step).
+int precompute(ctd_solver* s) {
+  update_view(s);
+  for (int d = 0; d < s->dim; ++d) HIPCHK(s, launch_quad_eval(s->I, d, s->stream));
+  if (s->dim == 2) HIPCHK(s, launch_mxy_build(s->I, s->stream));
+  return CTD_OK;
+}
+
+int read_scalars(ctd_solver* s) {
+  HIPCHK(s, hipMemcpyAsync(s->sc_host, s->I.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CTD_OK;
+}
+
+// g_d of the freshly finalised factor u_d and S for the next solve direction.
+int cubic_after(ctd_solver* s, int d, int next) {
+  if (s->dim != 3) return CTD_OK;
+  int other = -1;
+  if (next >= 0)
+    for (int e = 0; e < 3; ++e)
+      if (e != d && e != next) other = e;
+  HIPCHK(s, launch_cubic_g(s->I, d, s->stream));
+  HIPCHK(s, launch_cubic_gred(s->I, d, other, s->stream));
+  return CTD_OK;
+}
+
+int energy_of_uk(ctd_solver* s, double* E) {
+  // view on u^k: factor buffers X^k, M X^k, K X^k and amplitudes sk
+  DevInst V = s->I;
+  for (int d = 0; d < s->dim; ++d) {
+    V.ax[d].X = s->I.ax[d].Xk;
+    V.ax[d].MX = s->I.ax[d].MXk;
+    V.ax[d].KX = s->KXk[d];
+  }
+  V.sn = s->I.sk;
+  const int M = s->Mk;
+  HIPCHK(s, launch_energy_grams(V, M, s->energy_partial, s->stream));
+  std::vector<double> g2((size_t)2 * M);
+  HIPCHK(s, hipMemcpyAsync(g2.data(), s->energy_partial, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  double u2 = 0, gr = 0;
+  for (int a = 0; a < M; ++a) { u2 += g2[2 * a]; gr += g2[2 * a + 1]; }
+  int np = 0;
+  HIPCHK(s, launch_energy(V, s->energy_partial, &np, s->stream));
+  std::vector<double> part(np);
+  if (np) {
+    HIPCHK(s, hipMemcpyAsync(part.data(), s->energy_partial, sizeof(double) * np, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  double u4 = 0;
+  for (int i = 0; i < np; ++i) u4 += part[i];
+  double vol = 1.0;
+  for (int d = 0; d < s->dim; ++d) vol *= s->ax[d].hi - s->ax[d].lo;
+  *E = s->a0 * (u4 - 2.0 * u2 + vol) + 0.5 * s->kappa * gr;
+  return CTD_OK;
+}
+
+// End of step: the new modes become u^k.
+int finish_step(ctd_solver* s, int M) {
+  DevInst& I = s->I;
+  for (int d = 0; d < s->dim; ++d) {
+    std::swap(I.ax[d].Xk, I.ax[d].X);
+    std::swap(I.ax[d].MXk, I.ax[d].MX);
+    std::swap(s->KXk[d], I.ax[d].KX);
+  }
+  std::swap(I.sk, I.sn);
+  s->Mk = M;
+  return precompute(s);
+}
+
+int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info* info,
+             std::vector<int32_t>& log) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int D = s->dim;
+  const bool adaptive = replay == nullptr;
+  const int max_modes = adaptive ? s->P.max_modes : replay_len;
+  if (!adaptive && replay_len > s->Mcap) return s->fail(CTD_EINVAL, "replay needs more modes than allocated");
+  const int warm = s->P.init_mode == CTD_INIT_WARM;
+  int M = 0, sweeps = 0, unconv = 0, zero = 0, capped = 0;
+  double last_term = 0.0;
+  std::vector<int32_t> iters;
+  for (int mode = 0; mode < max_modes; ++mode) {
+    HIPCHK(s, launch_reset_scalars(s->I, s->stream));
+    HIPCHK(s, launch_init_mode(s->I, s->step_index, mode, warm, s->stream));
+    for (int d = 0; d < D; ++d) HIPCHK(s, launch_finalize(s->I, d, 0, 1, s->stream));
+    for (int d = 0; d < D; ++d) HIPCHK(s, launch_signature(s->I, d, M, s->stream));
+    if (D == 3) {
+      int rc = cubic_after(s, 1, -1);
+      if (rc) return rc;
+      rc = cubic_after(s, 2, 0);
+      if (rc) return rc;
+    }
+    const int nsw = adaptive ? std::max(1, s->P.fp_max_iter) : replay[mode];
+    if (nsw < 1) return s->fail(CTD_EINVAL, "replayed sweep count must be >= 1");
+    int it = 0;
+    bool conv = false;
+    for (it = 1; it <= nsw; ++it) {
+      for (int d = 0; d < D; ++d) {
+        if (D == 3) HIPCHK(s, launch_cubic_h(s->I, d, s->stream));
+        else HIPCHK(s, launch_gemv(s->I, d, s->stream));
+        HIPCHK(s, launch_rhs(s->I, d, M, s->stream));
+        HIPCHK(s, launch_solve(s->I, d, it, s->stream));
+        if (d < D - 1) {
+          HIPCHK(s, launch_signature(s->I, d, M, s->stream));
+          int rc = cubic_after(s, d, d + 1);
+          if (rc) return rc;
+        }
+      }
+      bool last = it == nsw;
+      if (adaptive) {
+        int rc = read_scalars(s);
+        if (rc) return rc;
+        if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
+        if (s->sc_host->zero) { zero = 1; break; }
+        conv = s->sc_host->converged != 0 && it >= 2;
+        if (conv) last = true;
+      }
+      if (!last) {
+        HIPCHK(s, launch_signature(s->I, D - 1, M, s->stream));
+        int rc = cubic_after(s, D - 1, 0);
+        if (rc) return rc;
+      } else {
+        break;
+      }
+    }
+    if (zero) break;
+    if (it > nsw) it = nsw;
+    sweeps += it;
+    if (adaptive && !conv) ++unconv;
+    HIPCHK(s, launch_append(s->I, M, s->stream));
+    ++M;
+    iters.push_back(it);
+    if (adaptive) {
+      // enrichment decision from the scalars of the last sweep
+      double pu = 1.0;
+      for (int d = 0; d < D; ++d) pu *= s->sc_host->umax[d];
+      last_term = s->sc_host->sigma[D - 1] * pu;
+      if (last_term <= s->P.enrich_tol) break;
+      if (M >= s->P.max_modes) { capped = 1; break; }
+    }
+  }
+  if (!adaptive) {
+    int rc = read_scalars(s);
+    if (rc) return rc;
+    if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
+    last_term = s->sc_host->term_max;
+  }
+  int rc = finish_step(s, M);   // M == 0: the zero field
+  if (rc) return rc;
+  ++s->step_index;
+  log.push_back(M);
+  for (int v : iters) log.push_back(v);
+  if (info) {
+    info->modes = M;
+    info->sweeps = sweeps;
+    info->capped = capped;
+    info->fp_unconverged = unconv;
+    info->zero_mode = zero;
+    info->last_term_max = last_term;
+    info->energy = std::numeric_limits<double>::quiet_NaN();
+    info->energy_increase = 0;
+  }
+  if (s->P.energy_each_step) {
+    double E;
+    rc = energy_of_uk(s, &E);
+    if (rc) return rc;
+    if (info) {
+      info->energy = E;
+      info->energy_increase = std::isfinite(s->energy_prev) && E > s->energy_prev * (1.0 + 1e-12) + 1e-300;
+    }
+    s->energy_prev = E;
+  } else {
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+  }
+  if (info) {
+    auto t1 = std::chrono::steady_clock::now();
+    info->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  }
+  return CTD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ctd_problem_default(ctd_problem* p) {
+  if (!p) return CTD_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->abi_version = CTD_ABI_VERSION;
+  p->dim = 2;
+  for (int d = 0; d < 3; ++d) { p->nodes[d] = 64; p->lo[d] = 0.0; p->hi[d] = 1.0; }
+  p->eps = 0.02; p->S = 2.0; p->dt = 1e-3;
+  const double nan = std::numeric_limits<double>::quiet_NaN();
+  p->L = nan; p->kappa = nan; p->a0 = nan; p->alpha = nan;
+  p->patch_s = 2; p->poly_p = 2; p->dilation_a = 12.0; p->gauss_points = 5;
+  p->fp_max_iter = 20; p->fp_tol = 1e-2; p->enrich_tol = 1e-8; p->max_modes = 64;
+  p->precision = CTD_PREC_FP64; p->schedule = CTD_SCHED_ADAPTIVE; p->init_mode = CTD_INIT_HASH;
+  p->energy_each_step = 0; p->seed = 0;
+  return CTD_OK;
+}
+
+int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
+             const double* amp, void* hip_stream, ctd_solver** out) {
+  if (!out) { g_init_error = "out is NULL"; return CTD_EINVAL; }
+  *out = nullptr;
+  std::string err;
+  int rc = validate(p, err);
+  if (rc) { g_init_error = err; return rc; }
+  if (m0 < 1 || !init) { g_init_error = "need m0 >= 1 initial modes"; return CTD_EINVAL; }
+  {
+    hipError_t ce = configure_kernels();
+    if (ce != hipSuccess) { g_init_error = hipGetErrorString(ce); return CTD_EDEVICE; }
+    for (int d = 0; d < p->dim; ++d)
+      if (p->nodes[d] > solve_lds_max_n(2 * p->patch_s + 1)) {
+        g_init_error = "nodes per axis exceed the LDS-resident banded solve";
+        return CTD_EUNSUPPORTED;
+      }
+  }
+  for (int d = 0; d < p->dim; ++d)
+    if (!init[d]) { g_init_error = "init factor pointer is NULL"; return CTD_EINVAL; }
+  ctd_solver* s = new (std::nothrow) ctd_solver();
+  if (!s) { g_init_error = "out of host memory"; return CTD_ENOMEM; }
+  s->P = *p;
+  if (s->P.dilation_a == 0.0) s->P.dilation_a = 12.0;
+  if (s->P.gauss_points == 0) s->P.gauss_points = 5;
+  if (s->P.fp_tol == 0.0) s->P.fp_tol = 1e-2;
+  if (s->P.fp_max_iter == 0) s->P.fp_max_iter = 20;
+  s->dim = p->dim;
+  if (std::isfinite(p->L)) {
+    s->L = p->L; s->kappa = p->kappa; s->a0 = p->a0; s->alpha = p->alpha;
+  } else {
+    s->L = 1.0; s->kappa = p->eps * p->eps; s->a0 = 0.25; s->alpha = p->S;
+  }
+  s->c = 1.0 / p->dt + s->alpha * s->L;
+  s->lam = s->L * s->kappa;
+  s->omega = 4.0 * s->a0 * s->L;
+  s->stream = (hipStream_t)hip_stream;
+  for (int d = 0; d < s->dim; ++d) {
+    rc = build_axis(p->nodes[d], p->lo[d], p->hi[d], p->patch_s, p->poly_p,
+                    s->P.dilation_a, s->P.gauss_points, s->ax[d], err);
+    if (rc) { g_init_error = err; delete s; return rc; }
+  }
+  rc = alloc_instance(s, m0);
+  if (rc) { g_init_error = s->err; s->arena.release(); if (s->sc_host) (void)hipHostFree(s->sc_host); delete s; return rc; }
+  // initial modes: fold amplitude signs into axis 0, |amp| into sk
+  std::vector<double> sk(m0);
+  std::vector<double> col;
+  for (int d = 0; d < s->dim; ++d) {
+    const size_t n = s->ax[d].n;
+    std::vector<double> buf(init[d], init[d] + n * (size_t)m0);
+    if (d == 0)
+      for (int m = 0; m < m0; ++m) {
+        double a = amp ? amp[m] : 1.0;
+        if (a < 0) for (size_t i = 0; i < n; ++i) buf[(size_t)m * n + i] = -buf[(size_t)m * n + i];
+      }
+    hipError_t e = hipMemcpy(s->I.ax[d].Xk, buf.data(), sizeof(double) * n * m0, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { g_init_error = hipGetErrorString(e); ctd_destroy(s); return CTD_EDEVICE; }
+  }
+  for (int m = 0; m < m0; ++m) {
+    double a = amp ? amp[m] : 1.0;
+    if (!std::isfinite(a)) { g_init_error = "non-finite amplitude"; ctd_destroy(s); return CTD_EINVAL; }
+    sk[m] = std::fabs(a);
+  }
+  hipError_t e = hipMemcpy(s->I.sk, sk.data(), sizeof(double) * m0, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { g_init_error = hipGetErrorString(e); ctd_destroy(s); return CTD_EDEVICE; }
+  s->Mk = m0;
+  for (int d = 0; d < s->dim; ++d) {
+    e = launch_band_mv(s->I.ax[d], s->I.ax[d].Mb, s->I.ax[d].Xk, s->I.ax[d].MXk, m0, s->stream);
+    if (e == hipSuccess) e = launch_band_mv(s->I.ax[d], s->I.ax[d].Kb, s->I.ax[d].Xk, s->KXk[d], m0, s->stream);
+    if (e != hipSuccess) { g_init_error = hipGetErrorString(e); ctd_destroy(s); return CTD_EDEVICE; }
+  }
+  rc = precompute(s);
+  if (rc == CTD_OK) {
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) { s->err = hipGetErrorString(e); rc = CTD_EDEVICE; }
+  }
+  if (rc) { g_init_error = s->err; ctd_destroy(s); return rc; }
+  *out = s;
+  return CTD_OK;
+}
+
+int ctd_step(ctd_solver* s, int32_t nsteps, ctd_step_info* info) {
+  if (!s) return CTD_EINVAL;
+  if (nsteps < 0) return s->fail(CTD_EINVAL, "nsteps < 0");
+  std::vector<int32_t> log;
+  size_t pos = 0;
+  const bool replay = s->P.schedule == CTD_SCHED_REPLAY;
+  for (int k = 0; k < nsteps; ++k) {
+    const int32_t* rp = nullptr;
+    int rl = 0;
+    if (replay) {
+      if (pos >= s->decisions_next.size()) return s->fail(CTD_ESTATE, "replay log exhausted");
+      rl = s->decisions_next[pos];
+      if (rl < 1 || pos + 1 + rl > s->decisions_next.size()) return s->fail(CTD_EINVAL, "malformed replay log");
+      rp = s->decisions_next.data() + pos + 1;
+      pos += 1 + rl;
+    }
+    int rc = one_step(s, rp, rl, info ? info + k : nullptr, log);
+    if (rc) return rc;
+  }
+  if (replay) s->decisions_next.erase(s->decisions_next.begin(), s->decisions_next.begin() + pos);
+  s->decisions_last.swap(log);
+  return CTD_OK;
+}
+
+int ctd_energy(ctd_solver* s, double* E) {
+  if (!s || !E) return CTD_EINVAL;
+  return energy_of_uk(s, E);
+}
+
+int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device) {
+  if (!s || !out) return CTD_EINVAL;
+  if (dtype != CTD_DTYPE_F64 && dtype != CTD_DTYPE_F32) return s->fail(CTD_EINVAL, "bad dtype");
+  DevInst V = s->I;
+  for (int d = 0; d < s->dim; ++d) V.ax[d].X = s->I.ax[d].Xk;
+  V.sn = s->I.sk;
+  size_t total = 1;
+  for (int d = 0; d < s->dim; ++d) total *= (size_t)s->ax[d].n;
+  const size_t bytes = total * (dtype == CTD_DTYPE_F32 ? 4 : 8);
+  void* dst = out;
+  void* tmp = nullptr;
+  if (!on_device) {
+    HIPCHK(s, hipMalloc(&tmp, bytes));
+    dst = tmp;
+  }
+  hipError_t e = launch_reconstruct(V, s->Mk, dst, dtype, s->stream);
+  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return s->hip_fail(e, "reconstruct");
+  return CTD_OK;
+}
+
+int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out, int32_t cap) {
+  if (!s || !m) return CTD_EINVAL;
+  *m = s->Mk;
+  if (cap < s->Mk) return (amp || out) ? s->fail(CTD_EINVAL, "cap smaller than mode count") : CTD_OK;
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  if (amp) HIPCHK(s, hipMemcpy(amp, s->I.sk, sizeof(double) * s->Mk, hipMemcpyDeviceToHost));
+  if (out)
+    for (int d = 0; d < s->dim; ++d)
+      if (out[d])
+        HIPCHK(s, hipMemcpy(out[d], s->I.ax[d].Xk, sizeof(double) * s->ax[d].n * s->Mk, hipMemcpyDeviceToHost));
+  return CTD_OK;
+}
+
+int ctd_get_step_index(ctd_solver* s, int64_t* k) {
+  if (!s || !k) return CTD_EINVAL;
+  *k = s->step_index;
+  return CTD_OK;
+}
+
+int ctd_set_step_index(ctd_solver* s, int64_t k) {
+  if (!s || k < 0) return CTD_EINVAL;
+  s->step_index = k;
+  return CTD_OK;
+}
+
+int ctd_get_decisions(ctd_solver* s, int32_t* buf, int64_t cap, int64_t* len) {
+  if (!s || !len) return CTD_EINVAL;
+  *len = (int64_t)s->decisions_last.size();
+  if (!buf) return CTD_OK;
+  if (cap < *len) return s->fail(CTD_EINVAL, "decision buffer too small");
+  std::copy(s->decisions_last.begin(), s->decisions_last.end(), buf);
+  return CTD_OK;
+}
+
+int ctd_set_decisions(ctd_solver* s, const int32_t* buf, int64_t len) {
+  if (!s || (len > 0 && !buf) || len < 0) return CTD_EINVAL;
+  s->decisions_next.assign(buf, buf + len);
+  return CTD_OK;
+}
+
+const char* ctd_last_error(const ctd_solver* s) {
+  return s ? s->err.c_str() : g_init_error.c_str();
+}
+
+void ctd_destroy(ctd_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  s->arena.release();
+  if (s->sc_host) (void)hipHostFree(s->sc_host);
+  delete s;
+}
+
+int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb, const double* Kb,
+                          const double* alpha, const double* beta, const double* b,
+                          double* x, int32_t count, void* hip_stream) {
+  if (n < bw + 1 || (bw != 3 && bw != 5 && bw != 7) || count < 0) return CTD_EINVAL;
+  if (!Mb || !Kb || !alpha || !beta || !b || !x) return CTD_EINVAL;
+  if (n > solve_lds_max_n(bw)) return CTD_EUNSUPPORTED;
+  if (count == 0) return CTD_OK;
+  if (configure_kernels() != hipSuccess) return CTD_EDEVICE;
+  hipError_t e = launch_band_solve_batch(n, bw, Mb, Kb, alpha, beta, b, x, count, (hipStream_t)hip_stream);
+  return e == hipSuccess ? CTD_OK : CTD_EDEVICE;
+}
+
+}  // extern "C"
+
+extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u, double* out) {
+  if (!s || !u || !out || d < 0 || d >= s->dim) return CTD_EINVAL;
+  const int D = s->dim;
+  for (int e = 0; e < D; ++e) {
+    if (e == d) continue;
+    if (!u[e]) return s->fail(CTD_EINVAL, "u[e] is NULL");
+    HIPCHK(s, hipMemcpyAsync(s->I.ax[e].u, u[e], sizeof(double) * s->ax[e].n, hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, launch_signature(s->I, e, 0, s->stream));
+  }
+  if (D == 3) {
+    int e1 = -1, e2 = -1;
+    for (int e = 0; e < 3; ++e)
+      if (e != d) { if (e1 < 0) e1 = e; else e2 = e; }
+    int rc = cubic_after(s, e1, -1);
+    if (rc) return rc;
+    rc = cubic_after(s, e2, d);
+    if (rc) return rc;
+    HIPCHK(s, launch_cubic_h(s->I, d, s->stream));
+  } else {
+    HIPCHK(s, launch_gemv(s->I, d, s->stream));
+  }
+  HIPCHK(s, launch_rhs(s->I, d, 0, s->stream, 1));
+  HIPCHK(s, hipMemcpyAsync(out, s->I.ax[d].rhs, sizeof(double) * s->ax[d].n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return CTD_OK;
+}

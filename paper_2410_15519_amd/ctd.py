@@ -1,0 +1,331 @@
+"""Python binding of libctd.so (ctypes; argument marshalling only).
+
+Every step of the CTD solve runs in the HIP library; this module only builds
+the problem struct, passes host arrays and torch device buffers/streams, and
+unpacks results.  Importing it fails loudly if the library was not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctd.so")
+
+CTD_OK = 0
+ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE",
+          -5: "ESTATE", -6: "EUNSUPPORTED", -7: "EAGAIN"}
+PREC = {"fp64": 0, "mixed": 1}
+SCHED = {"adaptive": 0, "replay": 1}
+INIT = {"hash": 0, "warm": 1}
+DTYPE = {"f64": 0, "f32": 1}
+
+
+class CtdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("dim", C.c_int32),
+        ("nodes", C.c_int64 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+        ("eps", C.c_double), ("S", C.c_double), ("dt", C.c_double),
+        ("L", C.c_double), ("kappa", C.c_double), ("a0", C.c_double), ("alpha", C.c_double),
+        ("patch_s", C.c_int32), ("poly_p", C.c_int32),
+        ("dilation_a", C.c_double),
+        ("gauss_points", C.c_int32), ("fp_max_iter", C.c_int32),
+        ("fp_tol", C.c_double), ("enrich_tol", C.c_double),
+        ("max_modes", C.c_int32), ("precision", C.c_int32),
+        ("schedule", C.c_int32), ("init_mode", C.c_int32),
+        ("energy_each_step", C.c_int32), ("reserved", C.c_int32),
+        ("seed", C.c_uint64),
+    ]
+
+
+class StepInfo(C.Structure):
+    _fields_ = [
+        ("modes", C.c_int32), ("sweeps", C.c_int32), ("capped", C.c_int32),
+        ("fp_unconverged", C.c_int32), ("zero_mode", C.c_int32),
+        ("energy_increase", C.c_int32), ("energy", C.c_double),
+        ("last_term_max", C.c_double), ("ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    vp = C.c_void_p
+    sig = {
+        "ctd_problem_default": (C.c_int, [P(Problem)]),
+        "ctd_init": (C.c_int, [P(Problem), C.c_int32, P(P(C.c_double)), P(C.c_double), vp, P(vp)]),
+        "ctd_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
+        "ctd_energy": (C.c_int, [vp, P(C.c_double)]),
+        "ctd_reconstruct": (C.c_int, [vp, vp, C.c_int32, C.c_int32]),
+        "ctd_get_modes": (C.c_int, [vp, P(C.c_int32), P(C.c_double), P(P(C.c_double)), C.c_int32]),
+        "ctd_get_step_index": (C.c_int, [vp, P(C.c_int64)]),
+        "ctd_set_step_index": (C.c_int, [vp, C.c_int64]),
+        "ctd_get_decisions": (C.c_int, [vp, P(C.c_int32), C.c_int64, P(C.c_int64)]),
+        "ctd_set_decisions": (C.c_int, [vp, P(C.c_int32), C.c_int64]),
+        "ctd_last_error": (C.c_char_p, [vp]),
+        "ctd_destroy": (None, [vp]),
+        "ctd_batch_create": (C.c_int, [C.c_int32, P(Problem), P(C.c_int32), P(P(P(C.c_double))),
+                                       P(P(C.c_double)), vp, P(vp)]),
+        "ctd_batch_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
+        "ctd_batch_get_modes": (C.c_int, [vp, C.c_int32, P(C.c_int32), P(C.c_double),
+                                          P(P(C.c_double)), C.c_int32]),
+        "ctd_batch_reconstruct": (C.c_int, [vp, C.c_int32, vp, C.c_int32, C.c_int32]),
+        "ctd_batch_last_error": (C.c_char_p, [vp]),
+        "ctd_batch_destroy": (None, [vp]),
+        "ctd_kernel_band_solve": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
+                                            C.c_int32, vp]),
+        "ctd_nonlinear_load": (C.c_int, [vp, C.c_int32, P(P(C.c_double)), P(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+LIB = _load()
+
+
+def current_stream():
+    """hipStream_t of torch's current stream (None when torch has no GPU)."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash",
+                 energy=False, **over) -> Problem:
+    """ctd_problem from a workloads.Instance (epsilon form) plus overrides."""
+    p = Problem()
+    rc = LIB.ctd_problem_default(C.byref(p))
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_problem_default")
+    if inst is not None:
+        p.dim = inst.dim
+        for d in range(inst.dim):
+            p.nodes[d] = int(inst.nodes[d])
+            p.lo[d] = float(inst.lo[d])
+            p.hi[d] = float(inst.hi[d])
+        p.eps, p.S, p.dt = float(inst.eps), float(inst.S), float(inst.dt)
+        p.patch_s, p.poly_p = int(inst.patch_s), int(inst.poly_p)
+        p.dilation_a = float(inst.dilation_a)
+        p.gauss_points = int(inst.gauss_points)
+        p.fp_tol, p.fp_max_iter = float(inst.fp_tol), int(inst.fp_max_iter)
+        p.enrich_tol, p.max_modes = float(inst.enrich_tol), int(inst.max_modes)
+        p.seed = int(inst.seed)
+    p.precision = PREC[precision]
+    p.schedule = SCHED[schedule]
+    p.init_mode = INIT[init]
+    p.energy_each_step = 1 if energy else 0
+    for k, v in over.items():
+        if k in ("nodes", "lo", "hi"):
+            for d, x in enumerate(v):
+                getattr(p, k)[d] = x
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def _factor_ptrs(factors):
+    arrs = [np.asfortranarray(np.asarray(f, dtype=np.float64)) for f in factors]
+    ptrs = (C.POINTER(C.c_double) * 3)()
+    for d, a in enumerate(arrs):
+        ptrs[d] = a.ctypes.data_as(C.POINTER(C.c_double))
+    return arrs, ptrs
+
+
+class Solver:
+    """One CTD instance on the GPU (handle around ctd_init / ctd_step ...)."""
+
+    def __init__(self, inst, stream=None, **kw):
+        self.inst = inst
+        self.problem = make_problem(inst, **kw)
+        self.dim = inst.dim
+        self.nodes = tuple(int(n) for n in inst.nodes[: inst.dim])
+        arrs, ptrs = _factor_ptrs(inst.factors)
+        amp = np.ascontiguousarray(inst.amp, dtype=np.float64)
+        self._stream = stream if stream is not None else current_stream()
+        h = C.c_void_p()
+        rc = LIB.ctd_init(C.byref(self.problem), len(amp), ptrs,
+                          amp.ctypes.data_as(C.POINTER(C.c_double)), self._stream, C.byref(h))
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_last_error(self.h).decode())
+
+    def step(self, nsteps=1):
+        info = (StepInfo * max(nsteps, 1))()
+        self._check(LIB.ctd_step(self.h, nsteps, info))
+        return [info[i].as_dict() for i in range(nsteps)]
+
+    def energy(self):
+        e = C.c_double()
+        self._check(LIB.ctd_energy(self.h, C.byref(e)))
+        return e.value
+
+    def reconstruct(self, dtype="f64", out=None):
+        """Dense nodal field.  out: optional torch device tensor (filled in place)."""
+        if out is not None:
+            self._check(LIB.ctd_reconstruct(self.h, C.c_void_p(out.data_ptr()), DTYPE[dtype], 1))
+            return out
+        arr = np.empty(self.nodes, dtype=np.float64 if dtype == "f64" else np.float32)
+        self._check(LIB.ctd_reconstruct(self.h, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0))
+        return arr
+
+    def modes(self):
+        m = C.c_int32()
+        self._check(LIB.ctd_get_modes(self.h, C.byref(m), None, None, 0))
+        M = m.value
+        amp = np.empty(M)
+        outs = [np.empty((n, M), order="F") for n in self.nodes]
+        ptrs = (C.POINTER(C.c_double) * 3)()
+        for d, a in enumerate(outs):
+            ptrs[d] = a.ctypes.data_as(C.POINTER(C.c_double))
+        self._check(LIB.ctd_get_modes(self.h, C.byref(m), amp.ctypes.data_as(C.POINTER(C.c_double)),
+                                      ptrs, M))
+        return amp, outs
+
+    def nonlinear_load(self, d, u):
+        """F_d[i] = int N~_i prod_{e!=d} u_e L w(u^k) on the current u^k (GPU kernels)."""
+        arrs = [np.ascontiguousarray(np.asarray(v if v is not None else np.zeros(n)), dtype=np.float64)
+                for v, n in zip(u, self.nodes)]
+        ptrs = (C.POINTER(C.c_double) * 3)()
+        for e, a in enumerate(arrs):
+            ptrs[e] = a.ctypes.data_as(C.POINTER(C.c_double))
+        out = np.empty(self.nodes[d])
+        self._check(LIB.ctd_nonlinear_load(self.h, d, ptrs, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def decisions(self):
+        n = C.c_int64()
+        self._check(LIB.ctd_get_decisions(self.h, None, 0, C.byref(n)))
+        buf = (C.c_int32 * max(n.value, 1))()
+        self._check(LIB.ctd_get_decisions(self.h, buf, n.value, C.byref(n)))
+        flat = list(buf[: n.value])
+        steps, i = [], 0
+        while i < len(flat):
+            m = flat[i]
+            steps.append(flat[i + 1: i + 1 + m])
+            i += 1 + m
+        return steps
+
+    def set_decisions(self, steps):
+        flat = []
+        for it in steps:
+            flat.append(len(it))
+            flat.extend(int(x) for x in it)
+        buf = (C.c_int32 * max(len(flat), 1))(*flat)
+        self._check(LIB.ctd_set_decisions(self.h, buf, len(flat)))
+
+    @property
+    def step_index(self):
+        k = C.c_int64()
+        self._check(LIB.ctd_get_step_index(self.h, C.byref(k)))
+        return k.value
+
+    @step_index.setter
+    def step_index(self, k):
+        self._check(LIB.ctd_set_step_index(self.h, int(k)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.ctd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+class Batch:
+    """Many independent instances stepped together (ctd_batch_*)."""
+
+    def __init__(self, insts, stream=None, **kw):
+        self.insts = list(insts)
+        cnt = len(self.insts)
+        probs = (Problem * cnt)()
+        m0 = (C.c_int32 * cnt)()
+        inits = (C.POINTER(C.POINTER(C.c_double)) * cnt)()
+        amps = (C.POINTER(C.c_double) * cnt)()
+        self._keep = []
+        for i, inst in enumerate(self.insts):
+            probs[i] = make_problem(inst, **kw)
+            arrs, ptrs = _factor_ptrs(inst.factors)
+            amp = np.ascontiguousarray(inst.amp, dtype=np.float64)
+            self._keep += [arrs, ptrs, amp]
+            m0[i] = len(amp)
+            inits[i] = C.cast(ptrs, C.POINTER(C.POINTER(C.c_double)))
+            amps[i] = amp.ctypes.data_as(C.POINTER(C.c_double))
+        h = C.c_void_p()
+        st = stream if stream is not None else current_stream()
+        rc = LIB.ctd_batch_create(cnt, probs, m0, inits, amps, st, C.byref(h))
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(None).decode())
+        self.h = h
+
+    def step(self, nsteps=1):
+        n = len(self.insts)
+        info = (StepInfo * max(n * nsteps, 1))()
+        rc = LIB.ctd_batch_step(self.h, nsteps, info)
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
+        return [[info[i * nsteps + k].as_dict() for k in range(nsteps)] for i in range(n)]
+
+    def reconstruct(self, i, dtype="f64"):
+        inst = self.insts[i]
+        arr = np.empty(tuple(inst.nodes[: inst.dim]), dtype=np.float64 if dtype == "f64" else np.float32)
+        rc = LIB.ctd_batch_reconstruct(self.h, i, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0)
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
+        return arr
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.ctd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def band_solve(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):
+    """ctd_kernel_band_solve on torch device tensors (float64)."""
+    rc = LIB.ctd_kernel_band_solve(n, bw, C.c_void_p(Mb.data_ptr()), C.c_void_p(Kb.data_ptr()),
+                                   C.c_void_p(alpha.data_ptr()), C.c_void_p(beta.data_ptr()),
+                                   C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), count,
+                                   stream if stream is not None else current_stream())
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_kernel_band_solve")
