@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark: CTD time steps per second for 3D Allen-Cahn at 1024 nodes per axis.
+
+One "step" is one time step of the stabilized semi-implicit scheme solved in
+separated form by the HIP library (greedy enrichment, alternating fixed-point
+sweeps, banded 1D solves, cubic contractions, energy on the separated
+quadrature), on seeded synthetic cosine initial data held on the GPU.
+
+Legs (rank 0, one GPU):
+  1. mixed precision (FP32 MFMA contractions, FP64 solves/decisions), adaptive:
+     W warmup steps, then K timed steps bracketed by device synchronisation;
+     per-kernel HIP-event timing inside the library gives the roofline of
+     the dominant kernel.
+  2. plain FP64, adaptive: same protocol (context: the mixed path must beat it).
+  3. accuracy: FP64 replay of leg 1's decisions; relative nodal l2 of the
+     mixed field against it after the same steps.
+  4. CPU baseline: the oracle (numpy/scipy FP64) timed on a bounded sample of
+     the same workload on the host cores.
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True):
+    import torch
+    sched = "replay" if decisions is not None else "adaptive"
+    s = ctd.Solver(inst, precision=precision, schedule=sched, energy=True)
+    if decisions is not None:
+        s.set_decisions(decisions)
+    dec = []
+    for k in range(warmup):
+        info = s.step(1)[0]
+        dec += s.decisions()
+        log(f"  [{precision}/{sched}] warmup {k}: {info['ms']:.0f} ms modes={info['modes']} "
+            f"sweeps={info['sweeps']}")
+    if profile:
+        s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for k in range(steps):
+        info = s.step(1)[0]
+        dec += s.decisions()
+        infos.append(info)
+        log(f"  [{precision}/{sched}] step {k}: {info['ms']:.0f} ms modes={info['modes']} "
+            f"sweeps={info['sweeps']} E={info['energy']:.9e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile_read() if profile else {}
+    return s, infos, t1 - t0, prof, dec
+
+
+def roofline_of(prof, precision):
+    # dominant kernel = largest summed device time
+    name, v = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = v["ms"] / v["launches"]
+    if name in ("cubic_g", "cubic_h", "energy", "mxy_build"):
+        peak = PEAK["fp32_mfma"] if (precision == "mixed" and name != "energy") else PEAK["fp64_mfma"]
+        per_launch = v["flops"] / v["launches"]
+        achieved = per_launch / (avg_ms * 1e-3)
+        return name, {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                      "kernel": name, "avg_launch_us": avg_ms * 1e3,
+                      "algorithmic_per_launch": per_launch}
+    per_launch = v["bytes"] / v["launches"]
+    achieved = per_launch / (avg_ms * 1e-3)
+    return name, {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
+                  "unit": "GB/s", "frac": achieved / PEAK["hbm"], "traffic": None,
+                  "kernel": name, "avg_launch_us": avg_ms * 1e3,
+                  "algorithmic_per_launch": per_launch}
+
+
+def cpu_baseline(inst, sweeps_per_step, budget_s=20.0):
+    """Oracle directional solves at the steady-state shape (M_k = max_modes).
+
+    The cost of a directional solve does not depend on the data values, so the
+    sample uses a seeded random u^k with the workload's mode cap; steps/s =
+    1 / (seconds per directional solve * directional solves per step).
+    """
+    import numpy as np
+    from oracle.ctd import SeparatedNonlinear, State, solve_direction
+    from oracle.scheme import problem_from_instance
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    pr = problem_from_instance(inst)
+    rng = np.random.default_rng(11)
+    Mk = inst.max_modes
+    st_k = State(rng.uniform(0.01, 0.1, Mk),
+                 [rng.uniform(-1, 1, (n, Mk)) for n in inst.nodes])
+    new = State(rng.uniform(0.01, 0.1, Mk // 2),
+                [rng.uniform(-1, 1, (n, Mk // 2)) for n in inst.nodes])
+    F = SeparatedNonlinear(pr, st_k)
+    u = [rng.uniform(-1, 1, n) for n in inst.nodes]
+    t0 = time.perf_counter()
+    done = 0
+    while True:
+        d = done % inst.dim
+        u[d] = solve_direction(pr, d, u, new, st_k, F)
+        u[d] /= np.sqrt(u[d] @ (pr.axes[d].M @ u[d]))
+        done += 1
+        el = time.perf_counter() - t0
+        log(f"  [cpu oracle] directional solve {done}: {el:.1f} s")
+        if el > budget_s or done >= 3 * inst.dim:
+            break
+    per_solve = el / done
+    steps_per_s = 1.0 / (per_solve * sweeps_per_step * inst.dim)
+    return {"value": steps_per_s, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"{done} oracle directional solves at M_k={Mk}, {Mk // 2} earlier modes, "
+                       f"nodes={inst.nodes[0]}^{inst.dim} ({per_solve:.2f} s each), scaled by "
+                       f"{sweeps_per_step:.0f} sweeps x {inst.dim} directions per step measured on the GPU")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ac3d_n1024")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the CTD step of one instance is not sharded "
+              "across GPUs in this build (see DESIGN.md for how it would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2410_15519_amd import ctd
+    from workloads import make_instance
+
+    inst = make_instance(args.workload)
+    log(f"workload {args.workload}: dim={inst.dim} nodes={inst.nodes} eps={inst.eps} dt={inst.dt} "
+        f"max_modes={inst.max_modes}")
+
+    # leg 1: mixed, adaptive (the headline)
+    s_mix, infos, elapsed, prof, dec_all = run_leg(ctd, inst, "mixed", args.warmup, args.steps)
+    value = args.steps / elapsed
+    dom, roof = roofline_of(prof, "mixed")
+    sweeps_per_step = float(np.mean([i["sweeps"] for i in infos]))
+    extra = {"kernels": {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
+                             "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
+                         for k, v in prof.items()},
+             "modes_per_step": float(np.mean([i["modes"] for i in infos])),
+             "sweeps_per_step": sweeps_per_step,
+             "energy_last": infos[-1]["energy"]}
+    fp64 = None
+    if not args.no_fp64:
+        # leg 2: FP64 adaptive
+        s64, infos64, el64, prof64, _ = run_leg(ctd, inst, "fp64", args.warmup, args.steps)
+        fp64 = {"steps_per_s": args.steps / el64,
+                "dominant": roofline_of(prof64, "fp64")[1]}
+        s64.close()
+        # leg 3: FP64 replay of the mixed run's decisions -> accuracy of the mixed field
+        n = int(np.prod(inst.nodes))
+        Umix = torch.empty(n, dtype=torch.float64, device="cuda")
+        s_mix.reconstruct("f64", out=Umix)
+        s_mix.close()
+        del s_mix
+        sref, _, _, _, _ = run_leg(ctd, inst, "fp64", 0, args.warmup + args.steps,
+                                   decisions=dec_all, profile=False)
+        Uref = torch.empty(n, dtype=torch.float64, device="cuda")
+        sref.reconstruct("f64", out=Uref)
+        sref.close()
+        rel = float(torch.linalg.norm(Umix - Uref) / torch.linalg.norm(Uref))
+        fp64["rel_l2_mixed_vs_fp64"] = rel
+        del Umix, Uref
+        torch.cuda.empty_cache()
+    cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
+    out = {
+        "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",
+        "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 / value, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32-mfma+fp64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "dim": inst.dim, "nodes": list(inst.nodes),
+                   "eps": inst.eps, "S": inst.S, "dt": inst.dt, "max_modes": inst.max_modes,
+                   "precision": "mixed", "init_modes": int(len(inst.amp)), "s": inst.patch_s,
+                   "p": inst.poly_p, "a": inst.dilation_a},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64": fp64,
+        "detail": extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

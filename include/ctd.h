@@ -192,6 +192,30 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
                           const double* beta, const double* b, double* x,
                           int32_t count, void* hip_stream);
 
+/* Per-kernel timing of the handle's launches with HIP events recorded on the
+ * handle's stream (enable resets the counters).  For each kernel class:
+ * launches, summed device time (ms), and the summed algorithmic flops and
+ * bytes of those launches (the minimal work of the operation, counted from
+ * the shapes, not the executed instruction count). */
+enum {
+  CTD_K_CUBIC_G = 0,   /* cubic Gram g_e of a fresh factor (3D, MFMA)     */
+  CTD_K_CUBIC_GRED,    /* split-K reduction of g, S = w g_e g_f          */
+  CTD_K_CUBIC_H,       /* cubic evaluation h_d at the Gauss points (MFMA)*/
+  CTD_K_RHS,           /* right-hand side assembly + nonlinear projection */
+  CTD_K_SOLVE,         /* banded LDL^T solve + normalisation              */
+  CTD_K_SIGNATURE,     /* Grams of a fresh factor, Gauss-point values     */
+  CTD_K_GEMV,          /* M_xy products (2D)                              */
+  CTD_K_MXY,           /* M_xy build (2D, once per step)                  */
+  CTD_K_ENERGY,        /* separated energy                                */
+  CTD_K_QUAD,          /* Gauss-point tables of u^k (once per step)       */
+  CTD_K_OTHER,         /* init/append/reset                               */
+  CTD_K_FACTOR,        /* banded LDL^T factorisation (second stream)      */
+  CTD_K_COUNT
+};
+int ctd_profile_enable(ctd_solver* s, int32_t on);
+int ctd_profile_read(ctd_solver* s, int32_t kernel, int64_t* launches,
+                     double* ms, double* flops, double* bytes);
+
 /* Nonlinear load of the directional system for direction d (the M_xy u_y
  * term of eq. KxQx and its 3D analogue), on the handle's current u^k:
  *   out[i] = int N~_i(x_d) prod_{e != d} u_e(x_e) L w(u^k) dOmega,

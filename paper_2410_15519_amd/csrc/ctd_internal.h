@@ -48,6 +48,7 @@ struct DevAxis {
   double* Mu;       // n
   double* Ku;       // n
   double* rhs;      // n
+  double* rpart;    // (chunks + 1) x n partial right-hand sides
   double* F;        // n, nonlinear load (2D route)
   double* v;        // nq, W * (Phi u)
   float* vf;
@@ -116,7 +117,10 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
                            hipStream_t st);
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
-hipError_t launch_solve(const DevInst& I, int d, int sweep, hipStream_t st);
+hipError_t launch_factor(const DevInst& I, int d, double* fac, hipStream_t st);
+hipError_t launch_solve(const DevInst& I, int d, int sweep, int M, const double* fac, hipStream_t st);
+hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
+int rhs_chunks(const DevInst& I, int M, int load_only);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
 hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st);
@@ -135,6 +139,8 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
 int solve_lds_max_n(int B);
+bool bcr_fits(int n, int B);
+hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();
 

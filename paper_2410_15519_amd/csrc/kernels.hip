@@ -308,173 +308,265 @@ hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st) {
 // Right-hand side of the directional system (eq. KxQx and its 3D analogue):
 //   Q_d = ck MXk (sk * a^k) - MX (sn (c a + lam b)) - lam KX (sn a) - F_d,
 // ck = c with the 2D M_xy load (which contains the full w), ck = c + omega
-// with the 3D cubic load F_d = omega Phi^T W h.  Also alpha_d, beta_d of
-// K_d = alpha_d M_d + beta_d K_d.
-__global__ void k_rhs(DevInst I, int d, int M, int load_only) {
-  extern __shared__ double sm[];
-  double* ak = sm;                  // Mk
-  double* cX = ak + I.Mk;           // M
-  double* cK = cX + M;              // M
-  double* part = cK + M;            // 4 x 64
+// with the 3D cubic load F_d = omega Phi^T W h.
+// Grid: row blocks of 64 x (column chunks of 64 over [MXk | MX | KX], plus
+// one chunk for -F_d).  Each block writes its partial sums to
+// rpart[chunk][row]; the solve kernel adds the chunks in fixed order.
+__device__ __forceinline__ int rhs_columns(const DevInst& I, int M, int load_only) {
+  return load_only ? (I.dim == 3 ? I.Mk : 0) : I.Mk + 2 * M;
+}
+
+__global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
+  extern __shared__ double hl[];
+  __shared__ double coef[64];
+  __shared__ double part[256];
   DevAxis& A = I.ax[d];
   const int n = A.n;
-  const int tid = threadIdx.x;
-  for (int j = tid; j < I.Mk; j += blockDim.x) {
-    double v = I.sk[j];
-    for (int e = 0; e < I.dim; ++e)
-      if (e != d) v *= I.ax[e].gmk[j];
-    ak[j] = v;
-  }
-  for (int m = tid; m < M; m += blockDim.x) {
-    double am = 1.0, bm = 0.0;
-    for (int e = 0; e < I.dim; ++e) {
-      if (e == d) continue;
-      am *= I.ax[e].gm[m];
-      double t = I.ax[e].gk[m];
-      for (int f = 0; f < I.dim; ++f)
-        if (f != d && f != e) t *= I.ax[f].gm[m];
-      bm += t;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int r0 = blockIdx.x * 64, i = r0 + l;
+  const int y = blockIdx.y;
+  if (y < nchunk) {
+    const int ctot = rhs_columns(I, M, load_only);
+    const double ck = load_only ? -I.omega : (I.dim == 3 ? I.c + I.omega : I.c);
+    if (tid < 64) {
+      const int c = y * 64 + tid;
+      double v = 0.0;
+      if (c < I.Mk) {
+        v = ck * I.sk[c];
+        for (int e = 0; e < I.dim; ++e)
+          if (e != d) v *= I.ax[e].gmk[c];
+      } else if (c < ctot) {
+        const int m = (c - I.Mk) % M;
+        double am = 1.0, bm = 0.0;
+        for (int e = 0; e < I.dim; ++e) {
+          if (e == d) continue;
+          am *= I.ax[e].gm[m];
+          double t = I.ax[e].gk[m];
+          for (int f = 0; f < I.dim; ++f)
+            if (f != d && f != e) t *= I.ax[f].gm[m];
+          bm += t;
+        }
+        v = (c - I.Mk < M) ? -I.sn[m] * (I.c * am + I.lam * bm) : -I.lam * I.sn[m] * am;
+      }
+      coef[tid] = v;
     }
-    cX[m] = I.sn[m] * (I.c * am + I.lam * bm);
-    cK[m] = I.lam * I.sn[m] * am;
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    double pm = 1.0, grad = 0.0;
-    for (int e = 0; e < I.dim; ++e)
-      if (e != d) pm *= I.sc->m[e];
-    for (int e = 0; e < I.dim; ++e) {
-      if (e == d) continue;
-      double t = I.sc->k[e];
-      for (int f = 0; f < I.dim; ++f)
-        if (f != d && f != e) t *= I.sc->m[f];
-      grad += t;
+    __syncthreads();
+    double acc = 0.0;
+    if (i < n) {
+#pragma unroll 4
+      for (int cc = 0; cc < 16; ++cc) {
+        const int c = y * 64 + w * 16 + cc;
+        if (c >= ctot) break;
+        const double* col = c < I.Mk ? A.MXk + (size_t)c * n
+                                     : (c < I.Mk + M ? A.MX + (size_t)(c - I.Mk) * n
+                                                     : A.KX + (size_t)(c - I.Mk - M) * n);
+        acc += coef[w * 16 + cc] * col[i];
+      }
     }
-    I.sc->alpha[d] = I.c * pm + I.lam * grad;
-    I.sc->beta[d] = I.lam * pm;
+    part[tid] = acc;
+    __syncthreads();
+    if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
+    return;
   }
-  __syncthreads();
-  const int w = tid >> 6, l = tid & 63;
-  const int i = blockIdx.x * 64 + l;
-  const double ck = load_only ? (I.dim == 3 ? -I.omega : 0.0)
-                              : (I.dim == 3 ? I.c + I.omega : I.c);
-  double acc = 0.0;
-  if (i < n && !load_only) {
-    for (int j = w; j < I.Mk; j += 4) acc += ck * A.MXk[(size_t)j * n + i] * ak[j];
-    for (int m = w; m < M; m += 4)
-      acc -= A.MX[(size_t)m * n + i] * cX[m] + A.KX[(size_t)m * n + i] * cK[m];
-  } else if (i < n && I.dim == 3) {
-    // load only, 3D: linear part -omega M X^k (sk * a^k) of the full load
-    for (int j = w; j < I.Mk; j += 4) acc += ck * A.MXk[(size_t)j * n + i] * ak[j];
-  }
-  part[w * 64 + l] = acc;
-  __syncthreads();
-  if (w == 0 && i < n) {
-    double q = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
-    double F;
-    if (I.dim == 3) {
-      F = 0.0;
-      const int ne = n - 1;
+  // chunk nchunk: the projected nonlinear load
+  double F = 0.0;
+  if (I.dim == 3) {
+    const int ne = n - 1;
+    const int e_lo = r0 - A.SW > 0 ? r0 - A.SW : 0;
+    const int e_hi = r0 + 63 + A.SW < ne - 1 ? r0 + 63 + A.SW : ne - 1;
+    const int q_lo = e_lo * A.ng, qcount = (e_hi - e_lo + 1) * A.ng;
+    for (int idx = tid; idx < qcount; idx += blockDim.x) {
+      const int q = q_lo + idx;
+      double h = 0.0;
+      for (int sp = 0; sp < I.nsplit_h; ++sp) h += I.hpart[(size_t)sp * A.nq + q];
+      hl[idx] = h * A.w[q];
+    }
+    __syncthreads();
+    if (w == 0 && i < n) {
       int e0 = i - A.SW;
-      e0 = e0 < 0 ? 0 : e0;
+      e0 = e0 < e_lo ? e_lo : e0;
       int e1 = i + A.SW;
-      e1 = e1 > ne - 1 ? ne - 1 : e1;
+      e1 = e1 > e_hi ? e_hi : e1;
       for (int e = e0; e <= e1; ++e) {
         const int st = elem_start(e, A.s, n, A.SW);
         const int jj = i - st;
         if (jj < 0 || jj >= A.SW) continue;
         for (int g = 0; g < A.ng; ++g) {
           const int qq = e * A.ng + g;
-          double h = 0.0;
-          for (int sp = 0; sp < I.nsplit_h; ++sp) h += I.hpart[(size_t)sp * A.nq + qq];
-          F += A.phi[(size_t)qq * A.SW + jj] * A.w[qq] * h;
+          F += A.phi[(size_t)qq * A.SW + jj] * hl[qq - q_lo];
         }
       }
       F *= I.omega;
-    } else {
-      F = A.F[i];
     }
-    A.rhs[i] = load_only ? q + F : q - F;
+  } else if (i < n) {
+    F = A.F[i];
   }
+  if (w == 0 && i < n) A.rpart[(size_t)nchunk * n + i] = load_only ? F : -F;
+}
+
+int rhs_chunks(const DevInst& I, int M, int load_only) {
+  const int ctot = load_only ? (I.dim == 3 ? I.Mk : 0) : I.Mk + 2 * M;
+  return (ctot + 63) / 64;
 }
 
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only) {
-  const int n = I.ax[d].n;
-  size_t shm = sizeof(double) * (I.Mk + 2 * M + 256);
-  k_rhs<<<(n + 63) / 64, 256, shm, st>>>(I, d, M, load_only);
+  const DevAxis& A = I.ax[d];
+  const int nchunk = rhs_chunks(I, M, load_only);
+  dim3 grid((A.n + 63) / 64, nchunk + 1);
+  const size_t shm = sizeof(double) * (size_t)(64 + 2 * A.SW + 2) * A.ng;
+  k_rhs<<<grid, 256, shm, st>>>(I, d, M, load_only, nchunk);
+  return hipGetLastError();
+}
+
+// rhs[i] = sum of the chunk partials (fixed order)
+__device__ __forceinline__ double rhs_at(const DevAxis& A, int i, int nchunk) {
+  double v = 0.0;
+  for (int y = 0; y <= nchunk; ++y) v += A.rpart[(size_t)y * A.n + i];
+  return v;
+}
+
+__global__ void k_rhs_sum(DevInst I, int d, int nchunk) {
+  DevAxis& A = I.ax[d];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.n) A.rhs[i] = rhs_at(A, i, nchunk);
+}
+
+hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st) {
+  k_rhs_sum<<<(I.ax[d].n + 255) / 256, 256, 0, st>>>(I, d, rhs_chunks(I, M, load_only));
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------ band solve
-// SPD banded solve (alpha M + beta K) x = b by LDL^T, half-bandwidth B.
-// The band and the right-hand side are staged in LDS; one thread runs the
-// factorisation with forward substitution fused, keeping the active
-// (B+1) x (B+1) window in registers, then the back substitution.
+// SPD banded systems (alpha M + beta K) x = b, half-bandwidth B, by LDL^T.
+// Factorisation and substitution are separate kernels: the factorisation
+// depends only on (alpha, beta), so the host launches it on a second stream
+// where it overlaps the nonlinear contraction; the substitution and the
+// normalisation stay on the critical path.  Both recurrences are sequential
+// in the row index and run in one thread with the active window in
+// registers and the band staged in LDS; the recurrences are ordered so that
+// each step depends on the previous one through a single FMA.
+// Factor layout ((B+1) x n, global or LDS): [j] = 1/D_j, [t*n + j] = L_{j+t,j}.
+
+__device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 template <int B>
-__device__ void ldlt_lds(int n, double* band, double* x) {
-  // band: (B+1) x n in LDS, [t*n + j] = A[j+t][j]; overwritten by L (t>=1)
-  // and D (t=0).  x: LDS rhs in, solution out.
+__device__ void ldlt_factor(int n, double* band) {
   double w[B + 1][B + 1];
-  double bw[B + 1];
 #pragma unroll
-  for (int r = 0; r <= B; ++r) {
+  for (int r = 0; r <= B; ++r)
 #pragma unroll
-    for (int c = 0; c <= r; ++c)
-      w[r][c] = (r < n) ? band[(r - c) * n + c] : (r == c ? 1.0 : 0.0);
-    bw[r] = r < n ? x[r] : 0.0;
-  }
+    for (int c = 0; c <= r; ++c) w[r][c] = band[(r - c) * n + c];
+  double nr[B + 1];
+#pragma unroll
+  for (int c = 0; c <= B; ++c)
+    nr[c] = (B + 1 < n) ? band[(B - c) * n + (1 + c)] : (c == B ? 1.0 : 0.0);
   for (int j = 0; j < n; ++j) {
-    // prefetch the row entering the window
-    const int inew = j + 1 + B;
-    double nr[B + 1];
-    double nb;
-    if (inew < n) {
-#pragma unroll
-      for (int c = 0; c <= B; ++c) nr[c] = band[(B - c) * n + (j + 1 + c)];
-      nb = x[inew];
-    } else {
-#pragma unroll
-      for (int c = 0; c <= B; ++c) nr[c] = (c == B) ? 1.0 : 0.0;
-      nb = 0.0;
-    }
     const double dj = w[0][0];
-    const double rd = 1.0 / dj;
+    const double sq = w[1][0] * w[1][0];
+    const double rd = recip(dj);
     double l[B + 1];
 #pragma unroll
     for (int t = 1; t <= B; ++t) l[t] = w[t][0] * rd;
-    const double yj = bw[0];
-    band[j] = dj;
+    double wn[B + 1][B + 1];
+    wn[0][0] = fma(-sq, rd, w[1][1]);
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int c = 0; c <= r; ++c)
+        if (r > 0 || c > 0) wn[r][c] = fma(-w[r + 1][0], l[c + 1], w[r + 1][c + 1]);
+#pragma unroll
+    for (int c = 0; c <= B; ++c) wn[B][c] = nr[c];
+    // prefetch the row entering at the next step
+    const int inew = j + 2 + B;
+#pragma unroll
+    for (int c = 0; c <= B; ++c)
+      nr[c] = (inew < n) ? band[(B - c) * n + (j + 2 + c)] : (c == B ? 1.0 : 0.0);
+    band[j] = rd;
 #pragma unroll
     for (int t = 1; t <= B; ++t) band[t * n + j] = l[t];
-    x[j] = yj * rd;
 #pragma unroll
-    for (int r = 0; r < B; ++r) {
+    for (int r = 0; r <= B; ++r)
 #pragma unroll
-      for (int c = 0; c <= r; ++c) w[r][c] = w[r + 1][c + 1] - w[r + 1][0] * l[c + 1];
-      bw[r] = bw[r + 1] - l[r + 1] * yj;
+      for (int c = 0; c <= r; ++c) w[r][c] = wn[r][c];
+  }
+}
+
+template <int B>
+__device__ void ldlt_subst(int n, const double* fac, double* x) {
+  double yw[B];
+#pragma unroll
+  for (int t = 0; t < B; ++t) yw[t] = 0.0;
+  double pb = x[0], pr = fac[0];
+  double pl[B + 1];
+#pragma unroll
+  for (int t = 1; t <= B; ++t) pl[t] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double bj = pb, rj = pr;
+    double lj[B + 1];
+#pragma unroll
+    for (int t = 1; t <= B; ++t) lj[t] = pl[t];
+    if (j + 1 < n) {
+      pb = x[j + 1];
+      pr = fac[j + 1];
+#pragma unroll
+      for (int t = 1; t <= B; ++t) pl[t] = (j + 1 - t >= 0) ? fac[t * n + j + 1 - t] : 0.0;
     }
+    double part = bj;
 #pragma unroll
-    for (int c = 0; c <= B; ++c) w[B][c] = nr[c];
-    bw[B] = nb;
+    for (int t = B; t >= 2; --t) part = fma(-lj[t], yw[t - 1], part);
+    const double yj = fma(-lj[1], yw[0], part);
+    x[j] = yj * rj;
+#pragma unroll
+    for (int t = B - 1; t > 0; --t) yw[t] = yw[t - 1];
+    yw[0] = yj;
   }
   double xw[B];
 #pragma unroll
   for (int t = 0; t < B; ++t) xw[t] = 0.0;
-  for (int j = n - 1; j >= 0; --j) {
-    double s = x[j];
+  double pz = x[n - 1];
 #pragma unroll
-    for (int t = 1; t <= B; ++t) s -= band[t * n + j] * xw[t - 1];
-    x[j] = s;
+  for (int t = 1; t <= B; ++t) pl[t] = fac[t * n + n - 1];
+  for (int j = n - 1; j >= 0; --j) {
+    const double zj = pz;
+    double lj[B + 1];
+#pragma unroll
+    for (int t = 1; t <= B; ++t) lj[t] = pl[t];
+    if (j > 0) {
+      pz = x[j - 1];
+#pragma unroll
+      for (int t = 1; t <= B; ++t) pl[t] = fac[t * n + j - 1];
+    }
+    double part = zj;
+#pragma unroll
+    for (int t = B; t >= 2; --t) part = fma(-lj[t], xw[t - 1], part);
+    const double xj = fma(-lj[1], xw[0], part);
+    x[j] = xj;
 #pragma unroll
     for (int t = B - 1; t > 0; --t) xw[t] = xw[t - 1];
-    xw[0] = s;
+    xw[0] = xj;
   }
 }
 
-__device__ void run_ldlt(int B, int n, double* band, double* x) {
+__device__ void run_factor(int B, int n, double* band) {
   switch (B) {
-    case 3: ldlt_lds<3>(n, band, x); break;
-    case 5: ldlt_lds<5>(n, band, x); break;
-    case 7: ldlt_lds<7>(n, band, x); break;
+    case 3: ldlt_factor<3>(n, band); break;
+    case 5: ldlt_factor<5>(n, band); break;
+    case 7: ldlt_factor<7>(n, band); break;
+    default: break;
+  }
+}
+
+__device__ void run_subst(int B, int n, const double* fac, double* x) {
+  switch (B) {
+    case 3: ldlt_subst<3>(n, fac, x); break;
+    case 5: ldlt_subst<5>(n, fac, x); break;
+    case 7: ldlt_subst<7>(n, fac, x); break;
     default: break;
   }
 }
@@ -485,30 +577,541 @@ int solve_lds_max_n(int B) {
   return (int)(budget / (sizeof(double) * (B + 2)));
 }
 
-__global__ __launch_bounds__(256) void k_solve(DevInst I, int d, int sweep) {
+// alpha_d, beta_d of K_d = alpha_d M_d + beta_d K_d (eq. KxQx, 3D analogue)
+// from the fixed factors' m_e = u_e.M.u_e, k_e = u_e.K.u_e; then the factor.
+__global__ __launch_bounds__(64) void k_factor(DevInst I, int d, double* fac) {
+  extern __shared__ double sm[];
+  DevAxis& A = I.ax[d];
+  const int n = A.n, B = A.B;
+  __shared__ double ab[2];
+  if (threadIdx.x == 0) {
+    double pm = 1.0, grad = 0.0;
+    for (int e = 0; e < I.dim; ++e)
+      if (e != d) pm *= I.sc->m[e];
+    for (int e = 0; e < I.dim; ++e) {
+      if (e == d) continue;
+      double t = I.sc->k[e];
+      for (int f = 0; f < I.dim; ++f)
+        if (f != d && f != e) t *= I.sc->m[f];
+      grad += t;
+    }
+    ab[0] = I.c * pm + I.lam * grad;
+    ab[1] = I.lam * pm;
+    I.sc->alpha[d] = ab[0];
+    I.sc->beta[d] = ab[1];
+  }
+  __syncthreads();
+  const double al = ab[0], be = ab[1];
+  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x)
+    sm[idx] = al * A.Mb[idx] + be * A.Kb[idx];
+  __syncthreads();
+  if (threadIdx.x == 0) run_factor(B, n, sm);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x) fac[idx] = sm[idx];
+}
+
+hipError_t launch_factor(const DevInst& I, int d, double* fac, hipStream_t st) {
+  const DevAxis& A = I.ax[d];
+  size_t shm = sizeof(double) * ((size_t)(A.B + 1) * A.n);
+  k_factor<<<1, 64, shm, st>>>(I, d, fac);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_solve(DevInst I, int d, int sweep, const double* fac, int nchunk) {
   extern __shared__ double sm[];
   __shared__ double red[16];
   DevAxis& A = I.ax[d];
   const int n = A.n, B = A.B;
-  double* band = sm;
+  double* f = sm;
   double* x = sm + (size_t)(B + 1) * n;
-  const double al = I.sc->alpha[d], be = I.sc->beta[d];
-  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x)
-    band[idx] = al * A.Mb[idx] + be * A.Kb[idx];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = A.rhs[i];
+  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x) f[idx] = fac[idx];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = rhs_at(A, i, nchunk);
   __syncthreads();
-  if (threadIdx.x == 0) run_ldlt(B, n, band, x);
+  if (threadIdx.x == 0) run_subst(B, n, f, x);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) A.u[i] = x[i];
   __syncthreads();
   finalize_body(I, d, sweep, 0, red);
 }
 
-hipError_t launch_solve(const DevInst& I, int d, int sweep, hipStream_t st) {
+hipError_t launch_solve(const DevInst& I, int d, int sweep, int M, const double* fac, hipStream_t st) {
   const DevAxis& A = I.ax[d];
   size_t shm = sizeof(double) * ((size_t)(A.B + 2) * A.n);
-  k_solve<<<1, 256, shm, st>>>(I, d, sweep);
+  k_solve<<<1, 256, shm, st>>>(I, d, sweep, fac, rhs_chunks(I, M, 0));
   return hipGetLastError();
+}
+
+// ---- block cyclic reduction (all sizes whose block data fit in LDS) ----
+// The band matrix is block tridiagonal with B x B blocks: D_I (diagonal),
+// L_I = A[block I, block I-1] (upper triangular at the start).  At level
+// l (stride s = 2^l) the active blocks are I = s-1 + k s; those with even k
+// are eliminated, the odd ones receive the Schur complements
+//   D_I -= L_I D_J1^-1 L_I^T + L_J2^T D_J2^-1 L_J2,   L_I <- -L_I D_J1^-1 L_J1,
+//   b_I -= L_I D_J1^-1 b_J1 + L_J2^T D_J2^-1 b_J2     (J1 = I-s, J2 = I+s),
+// formed through the Cholesky factors G of the eliminated D_J.  The
+// back substitution walks the levels down: x_J = D_J^-1 (b_J - L_J x_{J-s}
+// - L_{J+s}^T x_{J+s}).  One thread per block, barriers between phases.
+// LDS is block-major with an odd stride in doubles so that the threads of
+// a level read different banks; per block: packed G/D
+// (B(B+1)/2, G keeps 1/g on its diagonal), L (B^2), copy of L_{J+s} (B^2),
+// b/x (B).
+template <int B>
+struct Bcr {
+  static constexpr int NP = B * (B + 1) / 2;
+  static constexpr int OL = NP, OLN = NP + B * B, OB = NP + 2 * B * B;
+  // odd stride in doubles: consecutive blocks fall in different LDS banks
+  static constexpr int STRIDE = (NP + 2 * B * B + B) | 1;
+  __device__ static constexpr int pk(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
+  // Cholesky of a packed SPD block; diagonal stored as 1/g
+  __device__ static void chol(double* D) {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      double s = D[pk(j, j)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= D[pk(j, k)] * D[pk(j, k)];
+      // 1/sqrt(s): hardware estimate refined by two Newton steps
+      double rg = __builtin_amdgcn_rsq(s);
+      rg = rg * fma(-0.5 * s * rg, rg, 1.5);
+      rg = rg * fma(-0.5 * s * rg, rg, 1.5);
+      D[pk(j, j)] = rg;
+#pragma unroll
+      for (int i = j + 1; i < B; ++i) {
+        double t = D[pk(i, j)];
+#pragma unroll
+        for (int k = 0; k < j; ++k) t -= D[pk(i, k)] * D[pk(j, k)];
+        D[pk(i, j)] = t * rg;
+      }
+    }
+  }
+  __device__ static void fwd(const double* G, double* v) {   // v <- G^-1 v
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      double t = v[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) t -= G[pk(i, k)] * v[k];
+      v[i] = t * G[pk(i, i)];
+    }
+  }
+  __device__ static void bwd(const double* G, double* v) {   // v <- G^-T v
+#pragma unroll
+    for (int i = B - 1; i >= 0; --i) {
+      double t = v[i];
+#pragma unroll
+      for (int k = i + 1; k < B; ++k) t -= G[pk(k, i)] * v[k];
+      v[i] = t * G[pk(i, i)];
+    }
+  }
+};
+
+template <int B>
+__device__ void bcr_solve(int n, const double* Mb, const double* Kb, double al, double be,
+                          const double* rpart, int nchunk, double* out, double* sm) {
+  typedef Bcr<B> T;
+  const int N = (n + B - 1) / B;
+  const int tid = threadIdx.x, nt = blockDim.x;
+#define BCR(e, I) sm[(size_t)(I) * T::STRIDE + (e)]
+  for (int idx = tid; idx < N * T::STRIDE; idx += nt) sm[idx] = 0.0;
+  __syncthreads();
+  // band entries (t, j) = A[j+t][j] scattered into D_I (same block) or L_I
+  // (next block); coalesced over j
+  for (int idx = tid; idx < (B + 1) * n; idx += nt) {
+    const int t = idx / n, j = idx - t * n, i = j + t;
+    if (i >= n) continue;
+    const double v = al * Mb[idx] + be * Kb[idx];
+    const int I = i / B, r = i - I * B, J = j / B, c = j - J * B;
+    if (I == J) BCR(T::pk(r, c), I) = v;
+    else BCR(T::OL + r * B + c, I) = v;
+  }
+  // identity padding rows and the right-hand side (sum of chunk partials)
+  for (int i = tid; i < N * B; i += nt) {
+    const int I = i / B, r = i - I * B;
+    if (i >= n) BCR(T::pk(r, r), I) = 1.0;
+    double v = 0.0;
+    if (i < n)
+      for (int y = 0; y <= nchunk; ++y) v += rpart[(size_t)y * n + i];
+    BCR(T::OB + r, I) = v;
+  }
+  __syncthreads();
+  int top = 1;
+  for (int s = 1;; s <<= 1) {
+    const int first = s - 1;
+    if (first >= N) break;
+    const int count = (N - first + s - 1) / s;
+    top = s;
+    // phase A: eliminated blocks factor their diagonal block, keep L_{J+s}
+    for (int k = 2 * tid; k < count; k += 2 * nt) {
+      const int J = first + k * s;
+      double D[T::NP];
+#pragma unroll
+      for (int e = 0; e < T::NP; ++e) D[e] = BCR(e, J);
+      T::chol(D);
+#pragma unroll
+      for (int e = 0; e < T::NP; ++e) BCR(e, J) = D[e];
+      const bool has = J + s < N;
+#pragma unroll
+      for (int e = 0; e < B * B; ++e) BCR(T::OLN + e, J) = has ? BCR(T::OL + e, J + s) : 0.0;
+    }
+    __syncthreads();
+    // phase B: kept blocks take the Schur complements.  The columns of
+    // V = G^-1 (coupling) are staged in the block's idle L_{J+s} slot.
+    for (int k = 2 * tid + 1; k < count; k += 2 * nt) {
+      const int I = first + k * s;
+      const int J1 = I - s, J2 = I + s;
+#pragma unroll 1
+      for (int side = 0; side < 2; ++side) {
+        const int J = side == 0 ? J1 : J2;
+        if (J >= N) break;
+        double G[T::NP];
+#pragma unroll
+        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
+        // V[:, c]: side 0 uses L_I^T (coupling I -> J1), side 1 uses L_J2
+#pragma unroll 1
+        for (int c = 0; c < B; ++c) {
+          double col[B];
+#pragma unroll
+          for (int r = 0; r < B; ++r)
+            col[r] = side == 0 ? BCR(T::OL + c * B + r, I) : BCR(T::OL + r * B + c, J);
+          T::fwd(G, col);
+#pragma unroll
+          for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = col[r];
+        }
+        double u[B];
+#pragma unroll
+        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J);
+        T::fwd(G, u);
+#pragma unroll 1
+        for (int r = 0; r < B; ++r) {
+          double vr[B];
+#pragma unroll
+          for (int q = 0; q < B; ++q) vr[q] = BCR(T::OLN + r * B + q, I);
+          double t = 0.0;
+#pragma unroll
+          for (int q = 0; q < B; ++q) t += vr[q] * u[q];
+          BCR(T::OB + r, I) -= t;
+#pragma unroll 1
+          for (int c = 0; c <= r; ++c) {
+            double z = 0.0;
+#pragma unroll
+            for (int q = 0; q < B; ++q) z += vr[q] * BCR(T::OLN + c * B + q, I);
+            BCR(T::pk(r, c), I) -= z;
+          }
+        }
+        if (side == 0) {
+          // new coupling to I - 2s: -L_I D_J1^-1 L_J1 = -V^T (G^-1 L_J1)
+#pragma unroll 1
+          for (int c = 0; c < B; ++c) {
+            double wc[B];
+#pragma unroll
+            for (int r = 0; r < B; ++r) wc[r] = BCR(T::OL + r * B + c, J);
+            T::fwd(G, wc);
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+              double z = 0.0;
+#pragma unroll
+              for (int q = 0; q < B; ++q) z += BCR(T::OLN + r * B + q, I) * wc[q];
+              BCR(T::OL + r * B + c, I) = -z;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (count == 1) break;
+  }
+  // back substitution, top level down; x overwrites b of each block
+  for (int s = top; s >= 1; s >>= 1) {
+    const int first = s - 1;
+    const int count = first < N ? (N - first + s - 1) / s : 0;
+    for (int k = 2 * tid; k < count; k += 2 * nt) {
+      const int J = first + k * s;
+      double v[B], G[T::NP];
+#pragma unroll
+      for (int r = 0; r < B; ++r) v[r] = BCR(T::OB + r, J);
+#pragma unroll
+      for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
+      if (J - s >= 0) {
+        double xm[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) xm[c] = BCR(T::OB + c, J - s);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int c = 0; c < B; ++c) v[r] -= BCR(T::OL + r * B + c, J) * xm[c];
+      }
+      if (J + s < N) {
+        double xp[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) xp[c] = BCR(T::OB + c, J + s);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int c = 0; c < B; ++c) v[r] -= BCR(T::OLN + c * B + r, J) * xp[c];
+      }
+      T::fwd(G, v);
+      T::bwd(G, v);
+#pragma unroll
+      for (int r = 0; r < B; ++r) BCR(T::OB + r, J) = v[r];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) {
+    const int I = i / B, r = i - I * B;
+    out[i] = BCR(T::OB + r, I);
+  }
+  __syncthreads();
+#undef BCR
+}
+
+// Column-parallel variant: a group of 8 lanes per block, lane c owning
+// column c of every B x B operation (B <= 8), so each level's dependency
+// chain is that of one column instead of a whole block.
+template <int B>
+__device__ void bcr_solve_par(int n, const double* Mb, const double* Kb, double al, double be,
+                              const double* rpart, int nchunk, double* out, double* sm) {
+  typedef Bcr<B> T;
+  static_assert(B <= 8, "group of 8 lanes per block");
+  const int N = (n + B - 1) / B;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int grp = tid >> 3, c = tid & 7, ngrp = nt >> 3;
+  const bool lane_ok = c < B;
+#define BCR(e, I) sm[(size_t)(I) * T::STRIDE + (e)]
+  for (int idx = tid; idx < N * T::STRIDE; idx += nt) sm[idx] = 0.0;
+  __syncthreads();
+  for (int idx = tid; idx < (B + 1) * n; idx += nt) {
+    const int t = idx / n, j = idx - t * n, i = j + t;
+    if (i >= n) continue;
+    const double v = al * Mb[idx] + be * Kb[idx];
+    const int I = i / B, r = i - I * B, J = j / B, cc = j - J * B;
+    if (I == J) BCR(T::pk(r, cc), I) = v;
+    else BCR(T::OL + r * B + cc, I) = v;
+  }
+  for (int i = tid; i < N * B; i += nt) {
+    const int I = i / B, r = i - I * B;
+    if (i >= n) BCR(T::pk(r, r), I) = 1.0;
+    double v = 0.0;
+    if (i < n)
+      for (int y = 0; y <= nchunk; ++y) v += rpart[(size_t)y * n + i];
+    BCR(T::OB + r, I) = v;
+  }
+  __syncthreads();
+  int top = 1;
+  for (int s = 1;; s <<= 1) {
+    const int first = s - 1;
+    if (first >= N) break;
+    const int count = (N - first + s - 1) / s;
+    top = s;
+    const int nelim = (count + 1) / 2, nkept = count / 2;
+    // phase A: eliminated blocks: Cholesky (lane 0), copy of L_{J+s} (column per lane)
+    for (int g = grp; g < nelim; g += ngrp) {
+      const int J = first + 2 * g * s;
+      if (c == 0) {
+        double D[T::NP];
+#pragma unroll
+        for (int e = 0; e < T::NP; ++e) D[e] = BCR(e, J);
+        T::chol(D);
+#pragma unroll
+        for (int e = 0; e < T::NP; ++e) BCR(e, J) = D[e];
+      }
+      if (lane_ok) {
+        const bool has = J + s < N;
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+          BCR(T::OLN + r * B + c, J) = has ? BCR(T::OL + r * B + c, J + s) : 0.0;
+      }
+    }
+    __syncthreads();
+    // phase B, side J1 = I - s: V = G^-1 L_I^T staged in the kept block's
+    // idle L_{J+s} slot (column per lane), then Schur updates per column
+    const int rounds = (nkept + ngrp - 1) / ngrp;
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int g = grp + rd * ngrp;
+      const bool act = lane_ok && g < nkept;
+      const int I = first + (2 * g + 1) * s;
+      const int J1 = I - s, J2 = I + s;
+      double G[T::NP], w[B], u[B];
+      if (act) {
+#pragma unroll
+        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J1);
+        double v[B];
+#pragma unroll
+        for (int r = 0; r < B; ++r) v[r] = BCR(T::OL + c * B + r, I);   // L_I^T column c
+        T::fwd(G, v);
+#pragma unroll
+        for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = v[r];
+#pragma unroll
+        for (int r = 0; r < B; ++r) w[r] = BCR(T::OL + r * B + c, J1);  // L_J1 column c
+        T::fwd(G, w);
+#pragma unroll
+        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J1);
+        T::fwd(G, u);
+      }
+      __syncthreads();
+      if (act) {
+        double vc[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) vc[q] = BCR(T::OLN + c * B + q, I);
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          double vr[B];
+#pragma unroll
+          for (int q = 0; q < B; ++q) vr[q] = BCR(T::OLN + r * B + q, I);
+          if (r >= c) {
+            double z = 0.0;
+#pragma unroll
+            for (int q = 0; q < B; ++q) z += vr[q] * vc[q];
+            BCR(T::pk(r, c), I) -= z;
+          }
+          double z = 0.0;
+#pragma unroll
+          for (int q = 0; q < B; ++q) z += vr[q] * w[q];
+          BCR(T::OL + r * B + c, I) = -z;   // coupling to I - 2s
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) t += vc[q] * u[q];
+        BCR(T::OB + c, I) -= t;
+      }
+      __syncthreads();
+      // side J2 = I + s
+      const bool act2 = act && J2 < N;
+      if (act2) {
+#pragma unroll
+        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J2);
+        double v[B];
+#pragma unroll
+        for (int r = 0; r < B; ++r) v[r] = BCR(T::OL + r * B + c, J2);  // L_J2 column c
+        T::fwd(G, v);
+#pragma unroll
+        for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = v[r];
+#pragma unroll
+        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J2);
+        T::fwd(G, u);
+      }
+      __syncthreads();
+      if (act2) {
+        double vc[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) vc[q] = BCR(T::OLN + c * B + q, I);
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          if (r < c) continue;
+          double z = 0.0;
+#pragma unroll
+          for (int q = 0; q < B; ++q) z += BCR(T::OLN + r * B + q, I) * vc[q];
+          BCR(T::pk(r, c), I) -= z;
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < B; ++q) t += vc[q] * u[q];
+        BCR(T::OB + c, I) -= t;
+      }
+      __syncthreads();
+    }
+    if (count == 1) break;
+  }
+  // back substitution, top level down (lane 0 of each group)
+  for (int s = top; s >= 1; s >>= 1) {
+    const int first = s - 1;
+    const int count = first < N ? (N - first + s - 1) / s : 0;
+    const int nelim = (count + 1) / 2;
+    for (int g = grp; g < nelim; g += ngrp) {
+      if (c != 0) continue;
+      const int J = first + 2 * g * s;
+      double v[B], G[T::NP];
+#pragma unroll
+      for (int r = 0; r < B; ++r) v[r] = BCR(T::OB + r, J);
+#pragma unroll
+      for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
+      if (J - s >= 0) {
+        double xm[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) xm[q] = BCR(T::OB + q, J - s);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int q = 0; q < B; ++q) v[r] -= BCR(T::OL + r * B + q, J) * xm[q];
+      }
+      if (J + s < N) {
+        double xp[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) xp[q] = BCR(T::OB + q, J + s);
+#pragma unroll
+        for (int r = 0; r < B; ++r)
+#pragma unroll
+          for (int q = 0; q < B; ++q) v[r] -= BCR(T::OLN + q * B + r, J) * xp[q];
+      }
+      T::fwd(G, v);
+      T::bwd(G, v);
+#pragma unroll
+      for (int r = 0; r < B; ++r) BCR(T::OB + r, J) = v[r];
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nt) {
+    const int I = i / B, r = i - I * B;
+    out[i] = BCR(T::OB + r, I);
+  }
+  __syncthreads();
+#undef BCR
+}
+
+size_t bcr_lds_bytes(int n, int B) {
+  const int N = (n + B - 1) / B;
+  const int stride = (B * (B + 1) / 2 + 2 * B * B + B) | 1;
+  return sizeof(double) * (size_t)N * stride;
+}
+
+bool bcr_fits(int n, int B) { return bcr_lds_bytes(n, B) + 1024 <= (size_t)max_lds_bytes(); }
+
+// Directional solve by block cyclic reduction: alpha_d, beta_d from the
+// fixed factors, solve, then normalisation and the fixed-point test.
+template <int B>
+__global__ __launch_bounds__(512) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk) {
+  extern __shared__ double sm[];
+  __shared__ double red[16];
+  __shared__ double ab[2];
+  DevAxis& A = I.ax[d];
+  if (threadIdx.x == 0) {
+    double pm = 1.0, grad = 0.0;
+    for (int e = 0; e < I.dim; ++e)
+      if (e != d) pm *= I.sc->m[e];
+    for (int e = 0; e < I.dim; ++e) {
+      if (e == d) continue;
+      double t = I.sc->k[e];
+      for (int f = 0; f < I.dim; ++f)
+        if (f != d && f != e) t *= I.sc->m[f];
+      grad += t;
+    }
+    ab[0] = I.c * pm + I.lam * grad;
+    ab[1] = I.lam * pm;
+    I.sc->alpha[d] = ab[0];
+    I.sc->beta[d] = ab[1];
+  }
+  __syncthreads();
+  bcr_solve_par<B>(A.n, A.Mb, A.Kb, ab[0], ab[1], A.rpart, nchunk, A.u, sm);
+  finalize_body(I, d, sweep, 0, red);
+}
+
+hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st) {
+  const DevAxis& A = I.ax[d];
+  const size_t shm = bcr_lds_bytes(A.n, A.B);
+  const int nchunk = rhs_chunks(I, M, 0);
+  switch (A.B) {
+    case 3: k_solve_bcr<3><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
+    case 5: k_solve_bcr<5><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
+    case 7: k_solve_bcr<7><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int B>
+__global__ __launch_bounds__(512) void k_band_solve_bcr(int n, const double* Mb, const double* Kb,
+                                                        const double* alpha, const double* beta,
+                                                        const double* b, double* x) {
+  extern __shared__ double sm[];
+  const int k = blockIdx.x;
+  bcr_solve_par<B>(n, Mb, Kb, alpha[k], beta[k], b + (size_t)k * n, 0, x + (size_t)k * n, sm);
 }
 
 __global__ __launch_bounds__(64) void k_band_solve_batch(int n, int B, const double* Mb, const double* Kb,
@@ -523,7 +1126,10 @@ __global__ __launch_bounds__(64) void k_band_solve_batch(int n, int B, const dou
     band[idx] = al * Mb[idx] + be * Kb[idx];
   for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = b[(size_t)k * n + i];
   __syncthreads();
-  if (threadIdx.x == 0) run_ldlt(B, n, band, xs);
+  if (threadIdx.x == 0) {
+    run_factor(B, n, band);
+    run_subst(B, n, band, xs);
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) x[(size_t)k * n + i] = xs[i];
 }
@@ -532,6 +1138,16 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* Kb, const double* alpha,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st) {
+  if (bcr_fits(n, bw)) {
+    const size_t shm = bcr_lds_bytes(n, bw);
+    switch (bw) {
+      case 3: k_band_solve_bcr<3><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
+      case 5: k_band_solve_bcr<5><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
+      case 7: k_band_solve_bcr<7><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   size_t shm = sizeof(double) * ((size_t)(bw + 2) * n);
   k_band_solve_batch<<<count, 64, shm, st>>>(n, bw, Mb, Kb, alpha, beta, b, x);
   return hipGetLastError();
@@ -1067,7 +1683,10 @@ hipError_t configure_kernels() {
   if (e != hipSuccess) return e;
   g_max_lds = lds;
   // Raising the limit is best effort: launches check their own LDS needs.
-  const void* ks[] = {(const void*)k_solve, (const void*)k_band_solve_batch,
+  const void* ks[] = {(const void*)k_solve, (const void*)k_band_solve_batch, (const void*)k_factor,
+                      (const void*)k_solve_bcr<3>, (const void*)k_solve_bcr<5>,
+                      (const void*)k_solve_bcr<7>, (const void*)k_band_solve_bcr<3>,
+                      (const void*)k_band_solve_bcr<5>, (const void*)k_band_solve_bcr<7>,
                       (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);

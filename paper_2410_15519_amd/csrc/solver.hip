@@ -43,6 +43,52 @@ struct DeviceArena {
   }
 };
 
+// Launch timing with HIP events on the handle's stream.
+struct Profiler {
+  bool on = false;
+  struct Pending { int id; int ev; double flops, bytes; };
+  std::vector<hipEvent_t> pool;
+  std::vector<Pending> pending;
+  int used = 0;
+  int64_t launches[CTD_K_COUNT] = {};
+  double ms[CTD_K_COUNT] = {}, flops[CTD_K_COUNT] = {}, bytes[CTD_K_COUNT] = {};
+  hipError_t event_pair(int& idx) {
+    while ((int)pool.size() < used + 2) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      pool.push_back(e);
+    }
+    idx = used;
+    used += 2;
+    return hipSuccess;
+  }
+  // after a stream synchronisation: fold pending launches into the totals
+  hipError_t collect() {
+    for (const Pending& p : pending) {
+      float t = 0.f;
+      hipError_t r = hipEventElapsedTime(&t, pool[p.ev], pool[p.ev + 1]);
+      if (r != hipSuccess) return r;
+      launches[p.id] += 1;
+      ms[p.id] += t;
+      flops[p.id] += p.flops;
+      bytes[p.id] += p.bytes;
+    }
+    pending.clear();
+    used = 0;
+    return hipSuccess;
+  }
+  void reset() {
+    pending.clear();
+    used = 0;
+    for (int i = 0; i < CTD_K_COUNT; ++i) { launches[i] = 0; ms[i] = flops[i] = bytes[i] = 0; }
+  }
+  void release() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
 int tri_count(int nb) { return nb * (nb + 1) * (nb + 2) / 6; }
 
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -69,6 +115,12 @@ struct ctd_solver {
   double* energy_partial = nullptr;
   size_t energy_partial_cap = 0;
   std::vector<double> host_tmp;
+  Profiler prof;
+  // second stream for the banded factorisations (default priority)
+  hipStream_t fstream = nullptr;
+  hipEvent_t ev_fixed = nullptr, ev_fac = nullptr;
+  double* fac = nullptr;   // (B+1) x nmax LDL^T factor of the current direction
+  bool use_bcr = false;    // every axis fits the LDS-resident cyclic reduction
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -86,7 +138,68 @@ struct ctd_solver {
     if (_e != hipSuccess) return (s)->hip_fail(_e, #expr); \
   } while (0)
 
+// Launch `expr` (a hipError_t-returning launcher); when profiling, bracket it
+// with events and book it under kernel class `id` with algorithmic work.
+#define LAUNCH_ON(s, st, id, fl, by, expr)                                   \
+  do {                                                                       \
+    if ((s)->prof.on) {                                                      \
+      int _ev = 0;                                                           \
+      HIPCHK(s, (s)->prof.event_pair(_ev));                                  \
+      HIPCHK(s, hipEventRecord((s)->prof.pool[_ev], (st)));                  \
+      HIPCHK(s, expr);                                                       \
+      HIPCHK(s, hipEventRecord((s)->prof.pool[_ev + 1], (st)));              \
+      (s)->prof.pending.push_back({(id), _ev, (double)(fl), (double)(by)});  \
+    } else {                                                                 \
+      HIPCHK(s, expr);                                                       \
+    }                                                                        \
+  } while (0)
+#define LAUNCH(s, id, fl, by, expr) LAUNCH_ON(s, (s)->stream, id, fl, by, expr)
+
 namespace {
+
+hipError_t sync_collect(ctd_solver* s) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess && s->fstream) e = hipStreamSynchronize(s->fstream);
+  if (e == hipSuccess && s->prof.on) e = s->prof.collect();
+  return e;
+}
+
+// Algorithmic work of each launch (minimal operation counts from shapes).
+struct Work { double flops, bytes; };
+double tsz(const ctd_solver* s) { return s->I.mixed ? 4.0 : 8.0; }
+double symT(int M) { return (double)M * (M + 1) * (M + 2) / 6.0; }
+Work w_cubic(const ctd_solver* s, int d) {   // g or h: one FMA per (q, a<=b<=c)
+  const double nq = s->I.ax[d].nq, M = s->I.Mk;
+  return {2.0 * nq * symT(s->I.Mk), tsz(s) * (nq * M + symT(s->I.Mk)) + 8.0 * nq};
+}
+Work w_gred(const ctd_solver* s) {
+  return {0.0, tsz(s) * (double)(s->I.nsplit_g + 3) * s->I.ntri * kTileSq * kTile};
+}
+Work w_rhs(const ctd_solver* s, int d, int M) {
+  const double n = s->I.ax[d].n, c = s->I.Mk + 2.0 * M;
+  return {2.0 * n * c, 8.0 * n * (c + 2)};
+}
+Work w_solve(const ctd_solver* s, int d) {
+  const double n = s->I.ax[d].n, B = s->I.ax[d].B;
+  return {n * (B * B + 6 * B + 8 * B), 8.0 * n * (2 * (B + 1) + 6)};
+}
+Work w_sig(const ctd_solver* s, int d, int M) {
+  const double n = s->I.ax[d].n, nq = s->I.ax[d].nq, c = s->I.Mk + 2.0 * M;
+  const double v = s->dim == 3 ? nq : 0.0;
+  return {2.0 * n * c + 2.0 * v * s->I.ax[d].SW, 8.0 * n * (c + 1) + 8.0 * v};
+}
+Work w_gemv(const ctd_solver* s, int d) {
+  const double a = s->I.ax[d].n, b = s->I.ax[1 - d].n;
+  return {2.0 * a * b, tsz(s) * a * b};
+}
+Work w_mxy(const ctd_solver* s) {
+  const double q0 = s->I.ax[0].nq, q1 = s->I.ax[1].nq, n0 = s->I.ax[0].n, n1 = s->I.ax[1].n;
+  return {2.0 * q0 * q1 * (s->I.Mk + 2.0 * s->I.ax[0].SW), 2.0 * tsz(s) * n0 * n1};
+}
+Work w_quad(const ctd_solver* s, int d) {
+  const double nq = s->I.ax[d].nq, n = s->I.ax[d].n, M = s->I.Mk;
+  return {2.0 * nq * s->I.ax[d].SW * M, 8.0 * n * M + (8.0 + (s->I.mixed ? 4.0 : 0.0)) * nq * M};
+}
 
 int validate(const ctd_problem* p, std::string& err) {
   if (!p) { err = "problem is NULL"; return CTD_EINVAL; }
@@ -194,6 +307,7 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.Mu, sizeof(double) * n);
     AL(X.Ku, sizeof(double) * n);
     AL(X.rhs, sizeof(double) * n);
+    AL(X.rpart, sizeof(double) * n * (size_t)((3 * s->Mcap + 63) / 64 + 1));
     AL(X.F, sizeof(double) * n);
     AL(X.v, sizeof(double) * nq);
     if (mixed) AL(X.vf, sizeof(float) * nq);
@@ -230,21 +344,40 @@ int alloc_instance(ctd_solver* s, int m0) {
   s->energy_partial_cap = std::max<size_t>((size_t)npt * (npt + 1) / 2 * 16, 2 * (size_t)s->Mcap) + 16;
   AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
 #undef AL
+  {
+    int nmax = 0, bmax = 0;
+    for (int d = 0; d < s->dim; ++d) {
+      nmax = std::max(nmax, s->ax[d].n);
+      bmax = std::max(bmax, s->ax[d].B);
+    }
+    HIPCHK(s, A.alloc((void**)&s->fac, sizeof(double) * (size_t)(bmax + 1) * nmax));
+    s->use_bcr = true;
+    for (int d = 0; d < s->dim; ++d) s->use_bcr = s->use_bcr && bcr_fits(s->ax[d].n, s->ax[d].B);
+  }
   HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  HIPCHK(s, hipStreamCreateWithFlags(&s->fstream, hipStreamNonBlocking));
+  HIPCHK(s, hipEventCreateWithFlags(&s->ev_fixed, hipEventDisableTiming));
+  HIPCHK(s, hipEventCreateWithFlags(&s->ev_fac, hipEventDisableTiming));
   return CTD_OK;
 }
 
 // Gauss-point tables of u^k and, on the 2D route, M_xy (frozen for the step).
 int precompute(ctd_solver* s) {
   update_view(s);
-  for (int d = 0; d < s->dim; ++d) HIPCHK(s, launch_quad_eval(s->I, d, s->stream));
-  if (s->dim == 2) HIPCHK(s, launch_mxy_build(s->I, s->stream));
+  for (int d = 0; d < s->dim; ++d) {
+    Work w = w_quad(s, d);
+    LAUNCH(s, CTD_K_QUAD, w.flops, w.bytes, launch_quad_eval(s->I, d, s->stream));
+  }
+  if (s->dim == 2) {
+    Work w = w_mxy(s);
+    LAUNCH(s, CTD_K_MXY, w.flops, w.bytes, launch_mxy_build(s->I, s->stream));
+  }
   return CTD_OK;
 }
 
 int read_scalars(ctd_solver* s) {
   HIPCHK(s, hipMemcpyAsync(s->sc_host, s->I.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, sync_collect(s));
   return CTD_OK;
 }
 
@@ -255,8 +388,9 @@ int cubic_after(ctd_solver* s, int d, int next) {
   if (next >= 0)
     for (int e = 0; e < 3; ++e)
       if (e != d && e != next) other = e;
-  HIPCHK(s, launch_cubic_g(s->I, d, s->stream));
-  HIPCHK(s, launch_cubic_gred(s->I, d, other, s->stream));
+  Work w = w_cubic(s, d), wr = w_gred(s);
+  LAUNCH(s, CTD_K_CUBIC_G, w.flops, w.bytes, launch_cubic_g(s->I, d, s->stream));
+  LAUNCH(s, CTD_K_CUBIC_GRED, wr.flops, wr.bytes, launch_cubic_gred(s->I, d, other, s->stream));
   return CTD_OK;
 }
 
@@ -270,18 +404,27 @@ int energy_of_uk(ctd_solver* s, double* E) {
   }
   V.sn = s->I.sk;
   const int M = s->Mk;
-  HIPCHK(s, launch_energy_grams(V, M, s->energy_partial, s->stream));
+  {
+    const double n = s->I.ax[0].n;
+    LAUNCH(s, CTD_K_ENERGY, 4.0 * s->dim * (double)M * M * n, 24.0 * s->dim * (double)M * n,
+           launch_energy_grams(V, M, s->energy_partial, s->stream));
+  }
   std::vector<double> g2((size_t)2 * M);
   HIPCHK(s, hipMemcpyAsync(g2.data(), s->energy_partial, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, s->stream));
-  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, sync_collect(s));
   double u2 = 0, gr = 0;
   for (int a = 0; a < M; ++a) { u2 += g2[2 * a]; gr += g2[2 * a + 1]; }
   int np = 0;
-  HIPCHK(s, launch_energy(V, s->energy_partial, &np, s->stream));
+  {
+    const double P = (double)M * (M + 1) / 2.0;
+    double fl = 0.0, by = 0.0;
+    for (int d = 0; d < s->dim; ++d) { fl += 2.0 * s->I.ax[d].nq * P * P; by += 8.0 * s->I.ax[d].nq * M; }
+    LAUNCH(s, CTD_K_ENERGY, fl, by, launch_energy(V, s->energy_partial, &np, s->stream));
+  }
   std::vector<double> part(np);
   if (np) {
     HIPCHK(s, hipMemcpyAsync(part.data(), s->energy_partial, sizeof(double) * np, hipMemcpyDeviceToHost, s->stream));
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, sync_collect(s));
   }
   double u4 = 0;
   for (int i = 0; i < np; ++i) u4 += part[i];
@@ -304,6 +447,31 @@ int finish_step(ctd_solver* s, int M) {
   return precompute(s);
 }
 
+// LDL^T factorisation of alpha_d M_d + beta_d K_d on the second stream, as
+// soon as the fixed factors of direction d are final (everything queued so
+// far on the main stream); the substitution waits for it.
+int factor_async(ctd_solver* s, int d) {
+  if (s->use_bcr) return CTD_OK;   // cyclic reduction factors and solves in one kernel
+  HIPCHK(s, hipEventRecord(s->ev_fixed, s->stream));
+  HIPCHK(s, hipStreamWaitEvent(s->fstream, s->ev_fixed, 0));
+  const double n = s->I.ax[d].n, B = s->I.ax[d].B;
+  LAUNCH_ON(s, s->fstream, CTD_K_FACTOR, n * (B * B + 3 * B + 8), 8.0 * n * (3 * B + 3),
+            launch_factor(s->I, d, s->fac, s->fstream));
+  HIPCHK(s, hipEventRecord(s->ev_fac, s->fstream));
+  return CTD_OK;
+}
+
+int solve_after_factor(ctd_solver* s, int d, int it, int M) {
+  Work w = w_solve(s, d);
+  if (s->use_bcr) {
+    LAUNCH(s, CTD_K_SOLVE, w.flops, w.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
+    return CTD_OK;
+  }
+  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_fac, 0));
+  LAUNCH(s, CTD_K_SOLVE, w.flops, w.bytes, launch_solve(s->I, d, it, M, s->fac, s->stream));
+  return CTD_OK;
+}
+
 int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info* info,
              std::vector<int32_t>& log) {
   auto t0 = std::chrono::steady_clock::now();
@@ -319,7 +487,14 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     HIPCHK(s, launch_reset_scalars(s->I, s->stream));
     HIPCHK(s, launch_init_mode(s->I, s->step_index, mode, warm, s->stream));
     for (int d = 0; d < D; ++d) HIPCHK(s, launch_finalize(s->I, d, 0, 1, s->stream));
-    for (int d = 0; d < D; ++d) HIPCHK(s, launch_signature(s->I, d, M, s->stream));
+    {
+      int rc = factor_async(s, 0);
+      if (rc) return rc;
+    }
+    for (int d = 0; d < D; ++d) {
+      Work w = w_sig(s, d, M);
+      LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
+    }
     if (D == 3) {
       int rc = cubic_after(s, 1, -1);
       if (rc) return rc;
@@ -332,12 +507,24 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     bool conv = false;
     for (it = 1; it <= nsw; ++it) {
       for (int d = 0; d < D; ++d) {
-        if (D == 3) HIPCHK(s, launch_cubic_h(s->I, d, s->stream));
-        else HIPCHK(s, launch_gemv(s->I, d, s->stream));
-        HIPCHK(s, launch_rhs(s->I, d, M, s->stream));
-        HIPCHK(s, launch_solve(s->I, d, it, s->stream));
+        if (D == 3) {
+          Work w = w_cubic(s, d);
+          LAUNCH(s, CTD_K_CUBIC_H, w.flops, w.bytes, launch_cubic_h(s->I, d, s->stream));
+        } else {
+          Work w = w_gemv(s, d);
+          LAUNCH(s, CTD_K_GEMV, w.flops, w.bytes, launch_gemv(s->I, d, s->stream));
+        }
+        {
+          Work w = w_rhs(s, d, M);
+          LAUNCH(s, CTD_K_RHS, w.flops, w.bytes, launch_rhs(s->I, d, M, s->stream));
+          int rc = solve_after_factor(s, d, it, M);
+          if (rc) return rc;
+        }
         if (d < D - 1) {
-          HIPCHK(s, launch_signature(s->I, d, M, s->stream));
+          int rc0 = factor_async(s, d + 1);
+          if (rc0) return rc0;
+          Work w = w_sig(s, d, M);
+          LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
           int rc = cubic_after(s, d, d + 1);
           if (rc) return rc;
         }
@@ -352,7 +539,10 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
         if (conv) last = true;
       }
       if (!last) {
-        HIPCHK(s, launch_signature(s->I, D - 1, M, s->stream));
+        int rc0 = factor_async(s, 0);
+        if (rc0) return rc0;
+        Work w = w_sig(s, D - 1, M);
+        LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
         int rc = cubic_after(s, D - 1, 0);
         if (rc) return rc;
       } else {
@@ -406,7 +596,7 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     }
     s->energy_prev = E;
   } else {
-    HIPCHK(s, hipStreamSynchronize(s->stream));
+    HIPCHK(s, sync_collect(s));
   }
   if (info) {
     auto t1 = std::chrono::steady_clock::now();
@@ -571,7 +761,7 @@ int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out, in
   if (!s || !m) return CTD_EINVAL;
   *m = s->Mk;
   if (cap < s->Mk) return (amp || out) ? s->fail(CTD_EINVAL, "cap smaller than mode count") : CTD_OK;
-  HIPCHK(s, hipStreamSynchronize(s->stream));
+  HIPCHK(s, sync_collect(s));
   if (amp) HIPCHK(s, hipMemcpy(amp, s->I.sk, sizeof(double) * s->Mk, hipMemcpyDeviceToHost));
   if (out)
     for (int d = 0; d < s->dim; ++d)
@@ -614,7 +804,12 @@ const char* ctd_last_error(const ctd_solver* s) {
 void ctd_destroy(ctd_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
+  if (s->fstream) (void)hipStreamSynchronize(s->fstream);
   s->arena.release();
+  s->prof.release();
+  if (s->ev_fixed) (void)hipEventDestroy(s->ev_fixed);
+  if (s->ev_fac) (void)hipEventDestroy(s->ev_fac);
+  if (s->fstream) (void)hipStreamDestroy(s->fstream);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
   delete s;
 }
@@ -655,7 +850,26 @@ extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const*
     HIPCHK(s, launch_gemv(s->I, d, s->stream));
   }
   HIPCHK(s, launch_rhs(s->I, d, 0, s->stream, 1));
+  HIPCHK(s, launch_rhs_sum(s->I, d, 0, 1, s->stream));
   HIPCHK(s, hipMemcpyAsync(out, s->I.ax[d].rhs, sizeof(double) * s->ax[d].n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, sync_collect(s));
+  return CTD_OK;
+}
+
+extern "C" int ctd_profile_enable(ctd_solver* s, int32_t on) {
+  if (!s) return CTD_EINVAL;
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->prof.reset();
+  s->prof.on = on != 0;
+  return CTD_OK;
+}
+
+extern "C" int ctd_profile_read(ctd_solver* s, int32_t kernel, int64_t* launches, double* ms,
+                                double* flops, double* bytes) {
+  if (!s || kernel < 0 || kernel >= CTD_K_COUNT) return CTD_EINVAL;
+  if (launches) *launches = s->prof.launches[kernel];
+  if (ms) *ms = s->prof.ms[kernel];
+  if (flops) *flops = s->prof.flops[kernel];
+  if (bytes) *bytes = s->prof.bytes[kernel];
   return CTD_OK;
 }

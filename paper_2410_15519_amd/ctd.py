@@ -22,6 +22,8 @@ PREC = {"fp64": 0, "mixed": 1}
 SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
+KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
+           "mxy_build", "energy", "quad_eval", "other", "factor"]
 
 
 class CtdError(RuntimeError):
@@ -90,6 +92,9 @@ def _load():
         "ctd_kernel_band_solve": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
                                             C.c_int32, vp]),
         "ctd_nonlinear_load": (C.c_int, [vp, C.c_int32, P(P(C.c_double)), P(C.c_double)]),
+        "ctd_profile_enable": (C.c_int, [vp, C.c_int32]),
+        "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
+                                       P(C.c_double), P(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -216,6 +221,21 @@ class Solver:
             ptrs[e] = a.ctypes.data_as(C.POINTER(C.c_double))
         out = np.empty(self.nodes[d])
         self._check(LIB.ctd_nonlinear_load(self.h, d, ptrs, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def profile(self, on=True):
+        """Enable (and reset) or disable per-kernel HIP-event timing."""
+        self._check(LIB.ctd_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        out = {}
+        for k, name in enumerate(KERNELS):
+            n, ms, fl, by = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+            self._check(LIB.ctd_profile_read(self.h, k, C.byref(n), C.byref(ms), C.byref(fl),
+                                             C.byref(by)))
+            if n.value:
+                out[name] = {"launches": n.value, "ms": ms.value, "flops": fl.value,
+                             "bytes": by.value}
         return out
 
     def decisions(self):
