@@ -12,8 +12,12 @@ Legs (rank 0, one GPU):
      per-kernel HIP-event timing inside the library gives the roofline of
      the dominant kernel.
   2. plain FP64, adaptive: same protocol (context: the mixed path must beat it).
-  3. accuracy: FP64 replay of leg 1's decisions; relative nodal l2 of the
-     mixed field against it after the same steps.
+  3. accuracy (relative nodal l2, the paper's error metric): (a) one mixed
+     step from the FP64 state u^k with the FP64 step's decisions, against the
+     FP64 step; (b) the mixed run after all its steps against an FP64 replay of
+     its decisions; (c) for scale, FP64 against FP64 started from u0 with
+     amplitudes perturbed by 1e-14 (same decisions): the capped greedy
+     decomposition amplifies any difference from step to step.
   4. CPU baseline: the oracle (numpy/scipy FP64) timed on a bounded sample of
      the same workload on the host cores.
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -166,25 +170,57 @@ def main():
              "energy_last": infos[-1]["energy"]}
     fp64 = None
     if not args.no_fp64:
-        # leg 2: FP64 adaptive
-        s64, infos64, el64, prof64, _ = run_leg(ctd, inst, "fp64", args.warmup, args.steps)
-        fp64 = {"steps_per_s": args.steps / el64,
-                "dominant": roofline_of(prof64, "fp64")[1]}
-        s64.close()
-        # leg 3: FP64 replay of the mixed run's decisions -> accuracy of the mixed field
         n = int(np.prod(inst.nodes))
         Umix = torch.empty(n, dtype=torch.float64, device="cuda")
         s_mix.reconstruct("f64", out=Umix)
         s_mix.close()
         del s_mix
+        # leg 2: FP64 adaptive (timed for context); keep u^k before its last step
+        s64 = ctd.Solver(inst, precision="fp64", energy=True)
+        for k in range(args.warmup + args.steps - 1):
+            s64.step(1)
+        amp_prev, fac_prev = s64.modes()
+        k_prev = s64.step_index
+        s64.close()
+        s64, infos64, el64, prof64, dec64 = run_leg(ctd, inst, "fp64", args.warmup, args.steps)
+        fp64 = {"steps_per_s": args.steps / el64,
+                "dominant": roofline_of(prof64, "fp64")[1]}
+        U64 = torch.empty(n, dtype=torch.float64, device="cuda")
+        s64.reconstruct("f64", out=U64)
+        s64.close()
+        # leg 3a: one mixed step from the FP64 state u^k with the FP64 step's decisions
+        from workloads import Instance
+        st = Instance(dim=inst.dim, nodes=inst.nodes, eps=inst.eps, S=inst.S, dt=inst.dt,
+                      steps=1, amp=amp_prev, factors=fac_prev, max_modes=inst.max_modes,
+                      seed=inst.seed, enrich_tol=inst.enrich_tol)
+        one = ctd.Solver(st, precision="mixed", schedule="replay")
+        one.step_index = k_prev
+        one.set_decisions(dec64[-1:])
+        one.step(1)
+        U1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        one.reconstruct("f64", out=U1)
+        one.close()
+        fp64["rel_l2_step_mixed_vs_fp64"] = float(torch.linalg.norm(U1 - U64) / torch.linalg.norm(U64))
+        del U1
+        # leg 3b: accumulated difference of the mixed run against FP64 replaying its decisions
         sref, _, _, _, _ = run_leg(ctd, inst, "fp64", 0, args.warmup + args.steps,
                                    decisions=dec_all, profile=False)
         Uref = torch.empty(n, dtype=torch.float64, device="cuda")
         sref.reconstruct("f64", out=Uref)
         sref.close()
-        rel = float(torch.linalg.norm(Umix - Uref) / torch.linalg.norm(Uref))
-        fp64["rel_l2_mixed_vs_fp64"] = rel
-        del Umix, Uref
+        fp64["rel_l2_accum_mixed_vs_fp64"] = float(torch.linalg.norm(Umix - Uref) / torch.linalg.norm(Uref))
+        del Umix
+        # leg 3c: intrinsic divergence of the truncated decomposition: FP64 replay
+        # of the same decisions from u0 with amplitudes perturbed by 1e-14
+        pert = Instance(**{**inst.__dict__, "amp": inst.amp * (1.0 + 1e-14)})
+        sp, _, _, _, _ = run_leg(ctd, pert, "fp64", 0, args.warmup + args.steps,
+                                 decisions=dec_all, profile=False)
+        Up = torch.empty(n, dtype=torch.float64, device="cuda")
+        sp.reconstruct("f64", out=Up)
+        sp.close()
+        fp64["rel_l2_accum_fp64_u0_perturbed_1e-14"] = float(torch.linalg.norm(Up - Uref) / torch.linalg.norm(Uref))
+        fp64["accuracy_steps"] = args.warmup + args.steps
+        del Up, Uref, U64
         torch.cuda.empty_cache()
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
     out = {
