@@ -198,8 +198,8 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
  * bytes of those launches (the minimal work of the operation, counted from
  * the shapes, not the executed instruction count). */
 enum {
-  CTD_K_CUBIC_G = 0,   /* cubic Gram g_e of a fresh factor (3D, MFMA)     */
-  CTD_K_CUBIC_GRED,    /* split-K reduction of g, S = w g_e g_f          */
+  CTD_K_CUBIC_G = 0,   /* cubic Gram g_e of a fresh factor and S = w g_e g_f
+                          (3D, MFMA split-K launch + its reduction)       */
   CTD_K_CUBIC_H,       /* cubic evaluation h_d at the Gauss points (MFMA)*/
   CTD_K_RHS,           /* right-hand side assembly + nonlinear projection */
   CTD_K_SOLVE,         /* banded LDL^T solve + normalisation              */

@@ -122,8 +122,9 @@ hipError_t launch_solve(const DevInst& I, int d, int sweep, int M, const double*
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
 int rhs_chunks(const DevInst& I, int M, int load_only);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
-hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
-hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st);
+// g_d (split-K partials, then their reduction) and S = w g_d g_other
+hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st);
+size_t cubic_h_lds(const DevInst& I);   // dynamic LDS bytes of k_cubic_h
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_mxy_build(const DevInst& I, hipStream_t st);
 hipError_t launch_gemv(const DevInst& I, int d, hipStream_t st);
@@ -143,5 +144,6 @@ bool bcr_fits(int n, int B);
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();
+int num_cus();
 
 }  // namespace ctd

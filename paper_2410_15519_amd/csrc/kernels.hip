@@ -1209,56 +1209,84 @@ hipError_t launch_reset_scalars(const DevInst& I, hipStream_t st) {
 // is an MFMA product with K = q (g) or K = 256 mode pairs (h).
 constexpr int kGChunk = 64;
 
+// g over one tile triple and one Gauss-point range (split-K).  Y rows of the
+// A, B, C tiles (the C tile pre-multiplied by v) are staged in 64-point
+// chunks, the next chunk fetched into registers while the MFMAs of the
+// current one run.  Each workgroup writes its split partial.
 template <class T>
 __global__ __launch_bounds__(256) void k_cubic_g(DevInst I, int d) {
   typedef typename Vec4<T>::type V;
+  constexpr int TS = kTileSq * kTile;
+  constexpr int WPS = (int)sizeof(T);              // 16-byte words per 16-wide row segment
+  constexpr int NW = 3 * WPS * kGChunk / 256;      // words per thread per chunk
+  constexpr int EPW = 16 / (int)sizeof(T);         // elements per word
   const DevAxis& A = I.ax[d];
   const T* Y = (const T*)(sizeof(T) == 4 ? (const void*)A.Xhf : (const void*)A.Xh);
   const T* vq = (const T*)(sizeof(T) == 4 ? (const void*)A.vf : (const void*)A.v);
   const int ldh = I.Mkp;
   const int t = blockIdx.x, split = blockIdx.y;
   const int4 tr = I.tri[t];
-  const int A0 = tr.x * kTile, B0 = tr.y * kTile, C0 = tr.z * kTile;
+  const int col0[3] = {tr.x * kTile, tr.y * kTile, tr.z * kTile};
   const int nq = A.nq;
   const int per = ((nq + I.nsplit_g - 1) / I.nsplit_g + kGChunk - 1) / kGChunk * kGChunk;
   const int qbeg = split * per;
   const int qend = qbeg + per < nq ? qbeg + per : nq;
-  __shared__ T ya[kGChunk][kTile];
-  __shared__ T yb[kGChunk][kTile];
-  __shared__ T yc[kGChunk][kTile];
+  const int nchunk = qend > qbeg ? (qend - qbeg + kGChunk - 1) / kGChunk : 0;
+  __shared__ T ys[2][3][kGChunk][kTile];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  // word f of a chunk: row f / (3 WPS), array (f % (3 WPS)) / WPS, part f % WPS
+  auto load_chunk = [&](int q0, uint4* r) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int f = tid + 256 * k;
+      const int row = f / (3 * WPS), rem = f % (3 * WPS), arr = rem / WPS, part = rem % WPS;
+      const int q = q0 + row;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (q < qend) {
+        val = *(const uint4*)(Y + (size_t)q * ldh + col0[arr] + part * EPW);
+        if (arr == 2) {
+          T* e = (T*)&val;
+          const T vv = vq[q];
+#pragma unroll
+          for (int x = 0; x < EPW; ++x) e[x] *= vv;
+        }
+      }
+      r[k] = val;
+    }
+  };
+  auto store_chunk = [&](int buf, const uint4* r) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int f = tid + 256 * k;
+      const int row = f / (3 * WPS), rem = f % (3 * WPS), arr = rem / WPS, part = rem % WPS;
+      *(uint4*)&ys[buf][arr][row][part * EPW] = r[k];
+    }
+  };
   V acc[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] = V{0, 0, 0, 0};
-  for (int q0 = qbeg; q0 < qend; q0 += kGChunk) {
-    for (int idx = tid; idx < kGChunk * kTile; idx += 256) {
-      const int qq = idx / kTile, cc = idx % kTile, q = q0 + qq;
-      T va = 0, vb = 0, vc = 0;
-      if (q < qend) {
-        const T* row = Y + (size_t)q * ldh;
-        va = row[A0 + cc];
-        vb = row[B0 + cc];
-        vc = row[C0 + cc] * vq[q];
-      }
-      ya[qq][cc] = va;
-      yb[qq][cc] = vb;
-      yc[qq][cc] = vc;
-    }
-    __syncthreads();
+  uint4 pre[NW];
+  load_chunk(qbeg, pre);
+  store_chunk(0, pre);
+  __syncthreads();
+  for (int ci = 0; ci < nchunk; ++ci) {
+    load_chunk(qbeg + (ci + 1) * kGChunk, pre);   // beyond qend: zeros, unused
+    const int b = ci & 1;
 #pragma unroll 4
     for (int ks = 0; ks < kGChunk / 4; ++ks) {
       const int qq = ks * 4 + (l >> 4);
-      const T bval = yc[qq][l & 15];
-      const T ybv = yb[qq][l & 15];
+      const T bval = ys[b][2][qq][l & 15];
+      const T ybv = ys[b][1][qq][l & 15];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T aval = ya[qq][w * 4 + r] * ybv;
+        const T aval = ys[b][0][qq][w * 4 + r] * ybv;
         acc[r] = mfma16(aval, bval, acc[r]);
       }
     }
+    store_chunk(b ^ 1, pre);
     __syncthreads();
   }
-  T* out = (T*)I.gpart + ((size_t)split * I.ntri + t) * (kTileSq * kTile);
+  T* out = (T*)I.gpart + ((size_t)split * I.ntri + t) * TS;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int al = w * 4 + r;
@@ -1270,8 +1298,12 @@ __global__ __launch_bounds__(256) void k_cubic_g(DevInst I, int d) {
   }
 }
 
+// Split-K reduction of g in fixed split order, and S = w g_d g_other.  A
+// separate launch: a cross-workgroup reduction inside k_cubic_g needs device-
+// scope fences, whose L2 write-back/invalidate on this chip costs more than
+// the extra launch.
 template <class T>
-__global__ void k_cubic_gred(DevInst I, int d, int e_other) {
+__global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_other) {
   const size_t per = (size_t)kTileSq * kTile;
   const size_t total = (size_t)I.ntri * per;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1279,8 +1311,7 @@ __global__ void k_cubic_gred(DevInst I, int d, int e_other) {
   const T* gp = (const T*)I.gpart;
   double s = 0.0;
   for (int sp = 0; sp < I.nsplit_g; ++sp) s += (double)gp[(size_t)sp * total + idx];
-  T* g = (T*)I.ax[d].g;
-  g[idx] = (T)s;
+  ((T*)I.ax[d].g)[idx] = (T)s;
   if (e_other >= 0) {
     const int t = (int)(idx / per);
     const T* go = (const T*)I.ax[e_other].g;
@@ -1288,16 +1319,30 @@ __global__ void k_cubic_gred(DevInst I, int d, int e_other) {
   }
 }
 
+
+// h over a 64-row Gauss-point tile and a contiguous range of tile triples.
+// The S tile of the next triple is fetched into registers while the MFMAs of
+// the current one run, then stored to the other LDS buffer (one barrier per
+// triple).
+// Row stride of the LDS copy of the Gauss-point factor rows in k_cubic_h:
+// one 16-byte word of padding makes the stride an odd number of words, so the
+// 16 rows that the lane groups of a wave read at once fall in distinct banks.
+template <class T>
+__host__ __device__ constexpr int h_lds_stride(int ldh) { return ldh + 16 / (int)sizeof(T); }
+
 template <class T>
 __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   typedef typename Vec4<T>::type V;
+  constexpr int TS = kTileSq * kTile;                 // elements per S tile
+  constexpr int NV = TS * (int)sizeof(T) / 16 / 256;  // 16-byte words per thread
   extern __shared__ unsigned char smraw[];
   const DevAxis& A = I.ax[d];
   const T* X = (const T*)(sizeof(T) == 4 ? (const void*)A.Xhf : (const void*)A.Xh);
   const int ldh = I.Mkp;
+  const int ldx = h_lds_stride<T>(ldh);    // padded: the 16 rows a lane group reads hit distinct banks
   const int nq = A.nq;
-  T* xs = (T*)smraw;                       // 64 x ldh
-  T* ss = xs + 64 * ldh;                   // 256 x 16
+  T* xs = (T*)smraw;                       // 64 x ldx
+  T* sb = xs + 64 * ldx;                   // 2 x (256 x 16)
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int q0 = blockIdx.x * 64;
   const int split = blockIdx.y;
@@ -1306,20 +1351,40 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
   for (int idx = tid; idx < 64 * ldh; idx += 256) {
     const int qq = idx / ldh, c = idx % ldh, q = q0 + qq;
-    xs[idx] = q < nq ? X[(size_t)q * ldh + c] : (T)0;
+    xs[qq * ldx + c] = q < nq ? X[(size_t)q * ldh + c] : (T)0;
   }
+  // Prefetch registers; loads are unconditional from a clamped tile index
+  // (the surplus store lands in the idle buffer) so they stay in VGPRs.
+  const int tlast = t1 > t0 ? t1 - 1 : 0;
+  uint4 pre[NV];
+  {
+    const int tt = t0 < tlast ? t0 : tlast;
+    const uint4* src = (const uint4*)((const T*)I.S + (size_t)tt * TS);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) pre[v] = src[tid * NV + v];
+    uint4* dst = (uint4*)sb;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dst[tid * NV + v] = pre[v];
+  }
+  __syncthreads();
   const int rowA = w * 16 + (l & 15);     // A-operand row (q) of this lane
   double hq[4] = {0, 0, 0, 0};
   V acc = V{0, 0, 0, 0};
   int curC = -1;
   for (int t = t0; t < t1; ++t) {
     const int4 tr = I.tri[t];
+    {
+      const int tn = t + 1 < tlast ? t + 1 : tlast;
+      const uint4* src = (const uint4*)((const T*)I.S + (size_t)tn * TS);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pre[v] = src[tid * NV + v];
+    }
     if (tr.z != curC) {
       if (curC >= 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = w * 16 + mfma_row<T>(l, r);
-          double v = (double)acc[r] * (double)xs[row * ldh + curC * kTile + (l & 15)];
+          double v = (double)acc[r] * (double)xs[row * ldx + curC * kTile + (l & 15)];
           v += __shfl_xor(v, 8, 64);
           v += __shfl_xor(v, 4, 64);
           v += __shfl_xor(v, 2, 64);
@@ -1330,28 +1395,31 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
       acc = V{0, 0, 0, 0};
       curC = tr.z;
     }
-    __syncthreads();
-    const T* St = (const T*)I.S + (size_t)t * (kTileSq * kTile);
-    for (int idx = tid; idx < kTileSq * kTile; idx += 256) ss[idx] = St[idx];
-    __syncthreads();
+    const T* ss = sb + ((t - t0) & 1) * TS;
     const int A0 = tr.x * kTile, B0 = tr.y * kTile;
     T xa[kTile], xb[4];
 #pragma unroll
-    for (int a = 0; a < kTile; ++a) xa[a] = xs[rowA * ldh + A0 + a];
+    for (int a = 0; a < kTile; ++a) xa[a] = xs[rowA * ldx + A0 + a];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) xb[m] = xs[rowA * ldh + B0 + 4 * m + (l >> 4)];
+    for (int m = 0; m < 4; ++m) xb[m] = xs[rowA * ldx + B0 + 4 * m + (l >> 4)];
 #pragma unroll
     for (int ks = 0; ks < kTileSq / 4; ++ks) {
       const T aval = xa[ks >> 2] * xb[ks & 3];
       const T bval = ss[(4 * ks + (l >> 4)) * kTile + (l & 15)];
       acc = mfma16(aval, bval, acc);
     }
+    {
+      uint4* dst = (uint4*)(sb + ((t + 1 - t0) & 1) * TS);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dst[tid * NV + v] = pre[v];
+    }
+    __syncthreads();
   }
   if (curC >= 0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = w * 16 + mfma_row<T>(l, r);
-      double v = (double)acc[r] * (double)xs[row * ldh + curC * kTile + (l & 15)];
+      double v = (double)acc[r] * (double)xs[row * ldx + curC * kTile + (l & 15)];
       v += __shfl_xor(v, 8, 64);
       v += __shfl_xor(v, 4, 64);
       v += __shfl_xor(v, 2, 64);
@@ -1368,30 +1436,31 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   }
 }
 
-hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st) {
+hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st) {
   dim3 grid(I.ntri, I.nsplit_g);
   if (I.mixed) k_cubic_g<float><<<grid, 256, 0, st>>>(I, d);
   else k_cubic_g<double><<<grid, 256, 0, st>>>(I, d);
-  return hipGetLastError();
-}
-
-hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st) {
-  size_t total = (size_t)I.ntri * kTileSq * kTile;
-  int blocks = (int)((total + 255) / 256);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t total = (size_t)I.ntri * kTileSq * kTile;
+  const int blocks = (int)((total + 255) / 256);
   if (I.mixed) k_cubic_gred<float><<<blocks, 256, 0, st>>>(I, d, e_other);
   else k_cubic_gred<double><<<blocks, 256, 0, st>>>(I, d, e_other);
   return hipGetLastError();
+}
+
+size_t cubic_h_lds(const DevInst& I) {
+  if (I.mixed) return sizeof(float) * (64 * (size_t)h_lds_stride<float>(I.Mkp) + 2 * kTileSq * kTile);
+  return sizeof(double) * (64 * (size_t)h_lds_stride<double>(I.Mkp) + 2 * kTileSq * kTile);
 }
 
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
   const int nq = I.ax[d].nq;
   dim3 grid((nq + 63) / 64, I.nsplit_h);
   if (I.mixed) {
-    size_t shm = sizeof(float) * (64 * I.Mkp + kTileSq * kTile);
-    k_cubic_h<float><<<grid, 256, shm, st>>>(I, d);
+    k_cubic_h<float><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   } else {
-    size_t shm = sizeof(double) * (64 * I.Mkp + kTileSq * kTile);
-    k_cubic_h<double><<<grid, 256, shm, st>>>(I, d);
+    k_cubic_h<double><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   }
   return hipGetLastError();
 }
@@ -1671,6 +1740,7 @@ hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
 
 namespace ctd {
 static int g_max_lds = 65536;
+static int g_num_cus = 256;
 // Kernels whose dynamic LDS can exceed 64 KiB (the banded solve stages the
 // whole band; the FP64 cubic h kernel stages a 64 x Mkp tile plus an S tile).
 hipError_t configure_kernels() {
@@ -1682,6 +1752,9 @@ hipError_t configure_kernels() {
     e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
   g_max_lds = lds;
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+    g_num_cus = ncu;
   // Raising the limit is best effort: launches check their own LDS needs.
   const void* ks[] = {(const void*)k_solve, (const void*)k_band_solve_batch, (const void*)k_factor,
                       (const void*)k_solve_bcr<3>, (const void*)k_solve_bcr<5>,
@@ -1696,4 +1769,5 @@ hipError_t configure_kernels() {
 }
 
 int max_lds_bytes() { return g_max_lds; }
+int num_cus() { return g_num_cus; }
 }  // namespace ctd

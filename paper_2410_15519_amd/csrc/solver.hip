@@ -172,9 +172,6 @@ Work w_cubic(const ctd_solver* s, int d) {   // g or h: one FMA per (q, a<=b<=c)
   const double nq = s->I.ax[d].nq, M = s->I.Mk;
   return {2.0 * nq * symT(s->I.Mk), tsz(s) * (nq * M + symT(s->I.Mk)) + 8.0 * nq};
 }
-Work w_gred(const ctd_solver* s) {
-  return {0.0, tsz(s) * (double)(s->I.nsplit_g + 3) * s->I.ntri * kTileSq * kTile};
-}
 Work w_rhs(const ctd_solver* s, int d, int M) {
   const double n = s->I.ax[d].n, c = s->I.Mk + 2.0 * M;
   return {2.0 * n * c, 8.0 * n * (c + 2)};
@@ -252,11 +249,16 @@ void update_view(ctd_solver* s) {
   if (s->dim == 3) {
     int nqmin = 1 << 30;
     for (int d = 0; d < 3; ++d) nqmin = std::min(nqmin, I.ax[d].nq);
+    // g: about 1024 workgroups of 64-point chunks
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
     ng = std::min(ng, s->nsplit_g_cap / I.ntri);
     I.nsplit_g = std::max(1, ng);
-    int nqt = (nqmin + 63) / 64;
-    I.nsplit_h = std::max(1, std::min(I.ntri, (1024 + nqt - 1) / nqt));
+    // h: one round of resident workgroups (LDS-limited), triples split evenly
+    const int nqt = (nqmin + 63) / 64;
+    const size_t shm_h = cubic_h_lds(I);
+    const int per_cu = std::max(1, std::min(8, (int)((size_t)max_lds_bytes() / shm_h)));
+    const int slots = num_cus() * per_cu;
+    I.nsplit_h = std::max(1, std::min(I.ntri, slots / nqt));
   }
 }
 
@@ -388,9 +390,8 @@ int cubic_after(ctd_solver* s, int d, int next) {
   if (next >= 0)
     for (int e = 0; e < 3; ++e)
       if (e != d && e != next) other = e;
-  Work w = w_cubic(s, d), wr = w_gred(s);
-  LAUNCH(s, CTD_K_CUBIC_G, w.flops, w.bytes, launch_cubic_g(s->I, d, s->stream));
-  LAUNCH(s, CTD_K_CUBIC_GRED, wr.flops, wr.bytes, launch_cubic_gred(s->I, d, other, s->stream));
+  Work w = w_cubic(s, d);
+  LAUNCH(s, CTD_K_CUBIC_G, w.flops, w.bytes, launch_cubic_g(s->I, d, other, s->stream));
   return CTD_OK;
 }
 
@@ -641,6 +642,15 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
         g_init_error = "nodes per axis exceed the LDS-resident banded solve";
         return CTD_EUNSUPPORTED;
       }
+    if (p->dim == 3) {
+      DevInst probe{};
+      probe.mixed = p->precision == CTD_PREC_MIXED;
+      probe.Mkp = std::max(kTile, round_up(std::max(p->max_modes, m0), kTile));
+      if (cubic_h_lds(probe) > (size_t)max_lds_bytes()) {
+        g_init_error = "max_modes exceeds the LDS-resident cubic evaluation of this precision";
+        return CTD_EUNSUPPORTED;
+      }
+    }
   }
   for (int d = 0; d < p->dim; ++d)
     if (!init[d]) { g_init_error = "init factor pointer is NULL"; return CTD_EINVAL; }

@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "mixed": 1}
 SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
-KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
+KERNELS = ["cubic_g", "cubic_h", "rhs", "solve", "signature", "gemv",
            "mxy_build", "energy", "quad_eval", "other", "factor"]
 
 
