@@ -124,7 +124,9 @@ int rhs_chunks(const DevInst& I, int M, int load_only);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
 // g_d (split-K partials, then their reduction) and S = w g_d g_other
 hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st);
-size_t cubic_h_lds(const DevInst& I);   // dynamic LDS bytes of k_cubic_h
+size_t cubic_h_lds(const DevInst& I);   // dynamic LDS bytes of the h kernel
+int cubic_h_rows(const DevInst& I);     // Gauss points per workgroup of the h kernel
+int cubic_h_blocks_per_cu(const DevInst& I);   // resident h workgroups per CU
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_mxy_build(const DevInst& I, hipStream_t st);
 hipError_t launch_gemv(const DevInst& I, int d, hipStream_t st);

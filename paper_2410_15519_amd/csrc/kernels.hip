@@ -7,6 +7,7 @@
 // and its Gauss-point tables Xh_d = Phi_d X^k_d diag(sk^(1/D)).
 #include "ctd_internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace ctd {
@@ -1315,7 +1316,15 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
   if (e_other >= 0) {
     const int t = (int)(idx / per);
     const T* go = (const T*)I.ax[e_other].g;
-    ((T*)I.S)[idx] = (T)((double)I.tri[t].w * s * (double)go[idx]);
+    const T val = (T)((double)I.tri[t].w * s * (double)go[idx]);
+    size_t dst = idx;
+    if (sizeof(T) == 4) {
+      // element e = 64 ks + l of the tile (k-step ks, lane l) goes where lane l
+      // finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
+      const int e = (int)(idx - (size_t)t * per), ks = e >> 6, l = e & 63;
+      dst = (size_t)t * per + ((((ks >> 2) << 6) + l) << 2) + (ks & 3);
+    }
+    ((T*)I.S)[dst] = val;
   }
 }
 
@@ -1324,6 +1333,111 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
 // The S tile of the next triple is fetched into registers while the MFMAs of
 // the current one run, then stored to the other LDS buffer (one barrier per
 // triple).
+// h for the FP32 path.  A workgroup of 4 waves owns 64 Gauss points (a
+// 16-point MFMA block per wave) and walks its share of the tile triples.
+// Only the S tiles are staged in LDS (32 KB, double-buffered; in the order
+// k_cubic_gred<float> writes them: lane l finds k-steps 4j..4j+3 in one
+// 16-byte word), so several workgroups share a CU.  The factor values of a
+// lane's Gauss point come from L2 straight into VGPRs, and the S tile and
+// factor values of the next triple are fetched while the MFMAs of the
+// current one run.
+constexpr int kHQ = 64;   // Gauss points per workgroup
+
+__global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
+  extern __shared__ unsigned char smraw[];
+  constexpr int TW = kTileSq * kTile / 4;   // 16-byte words per S tile
+  const DevAxis& A = I.ax[d];
+  const float* X = (const float*)A.Xhf;
+  const int ldh = I.Mkp;
+  const int nq = A.nq;
+  float4* sb = (float4*)smraw;           // 2 x TW words
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int q0 = blockIdx.x * kHQ;
+  const int split = blockIdx.y;
+  const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
+  const int t0 = split * per;
+  const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
+  // A-operand row of this lane; rows past the end read the last point (their
+  // MFMA output rows are never stored)
+  int qa = q0 + w * 16 + (l & 15);
+  qa = qa < nq ? qa : nq - 1;
+  const float* xrow = X + (size_t)qa * ldh;
+  // prefetch registers; loads use a clamped triple index so they are
+  // unconditional (the surplus S words land in the idle buffer)
+  const int tlast = t1 > t0 ? t1 - 1 : 0;
+  const float4* Sp = (const float4*)I.S;
+  float4 pre[TW / 256];
+  float4 xa4[4], xan[4];
+  float xb[4], xbn[4];
+#define H32_FETCH(tt, XA, XB)                                                    \
+  do {                                                                          \
+    const int4 tr_ = I.tri[tt];                                                 \
+    const size_t base_ = (size_t)(tt) * TW + tid;                               \
+    _Pragma("unroll") for (int v = 0; v < TW / 256; ++v) pre[v] = Sp[base_ + v * 256]; \
+    const float4* ar_ = (const float4*)(xrow + tr_.x * kTile);                   \
+    _Pragma("unroll") for (int v = 0; v < 4; ++v) XA[v] = ar_[v];                \
+    _Pragma("unroll") for (int m = 0; m < 4; ++m) XB[m] = xrow[tr_.y * kTile + 4 * m + (l >> 4)]; \
+  } while (0)
+  H32_FETCH(t0 < tlast ? t0 : tlast, xa4, xb);
+#pragma unroll
+  for (int v = 0; v < TW / 256; ++v) sb[v * 256 + tid] = pre[v];
+  __syncthreads();
+  double hq[4] = {0, 0, 0, 0};
+  f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+  int curC = -1;
+  auto close_c = [&]() {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int q = q0 + w * 16 + mfma_row<float>(l, r);
+      q = q < nq ? q : nq - 1;
+      double v = ((double)acc[0][r] + (double)acc[1][r]) *
+                 (double)X[(size_t)q * ldh + curC * kTile + (l & 15)];
+      v += __shfl_xor(v, 8, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 1, 64);
+      hq[r] += v;
+    }
+    acc[0] = f4{0, 0, 0, 0};
+    acc[1] = f4{0, 0, 0, 0};
+  };
+  for (int t = t0; t < t1; ++t) {
+    const int cz = I.tri[t].z;
+    H32_FETCH(t + 1 < tlast ? t + 1 : tlast, xan, xbn);
+    if (cz != curC) {
+      if (curC >= 0) close_c();
+      curC = cz;
+    }
+    const float4* sq = sb + ((t - t0) & 1) * TW;
+#pragma unroll
+    for (int j = 0; j < kTileSq / 16; ++j) {
+      const float4 b4 = sq[j * 64 + l];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int ks = 4 * j + u;
+        acc[u & 1] = mfma16(xa4[ks >> 4][(ks >> 2) & 3] * xb[ks & 3], b4[u], acc[u & 1]);
+      }
+    }
+    {
+      float4* dst = sb + ((t + 1 - t0) & 1) * TW;
+#pragma unroll
+      for (int v = 0; v < TW / 256; ++v) dst[v * 256 + tid] = pre[v];
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) { xa4[v] = xan[v]; xb[v] = xbn[v]; }
+    __syncthreads();
+  }
+  if (curC >= 0) close_c();
+  if ((l & 15) == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int q = q0 + w * 16 + mfma_row<float>(l, r);
+      if (q < nq) I.hpart[(size_t)split * nq + q] = hq[r];
+    }
+  }
+#undef H32_FETCH
+}
+
 // Row stride of the LDS copy of the Gauss-point factor rows in k_cubic_h:
 // one 16-byte word of padding makes the stride an odd number of words, so the
 // 16 rows that the lane groups of a wave read at once fall in distinct banks.
@@ -1450,15 +1564,38 @@ hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st) 
 }
 
 size_t cubic_h_lds(const DevInst& I) {
-  if (I.mixed) return sizeof(float) * (64 * (size_t)h_lds_stride<float>(I.Mkp) + 2 * kTileSq * kTile);
+  if (I.mixed) return sizeof(float) * 2 * kTileSq * kTile;
   return sizeof(double) * (64 * (size_t)h_lds_stride<double>(I.Mkp) + 2 * kTileSq * kTile);
+}
+
+int cubic_h_rows(const DevInst& I) { return I.mixed ? kHQ : 64; }
+
+int cubic_h_blocks_per_cu(const DevInst& I) {
+  // resident workgroups per CU as the runtime computes them (registers and
+  // LDS), cached per LDS size
+  static thread_local size_t last_shm[2] = {0, 0};
+  static thread_local int last_nb[2] = {0, 0};
+  const int k = I.mixed ? 1 : 0;
+  const size_t shm = cubic_h_lds(I);
+  if (last_shm[k] != shm) {
+    int nb = 0;
+    const void* f = I.mixed ? (const void*)k_cubic_h32 : (const void*)k_cubic_h<double>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, shm) != hipSuccess || nb < 1) {
+      (void)hipGetLastError();
+      nb = std::max(1, (int)((size_t)max_lds_bytes() / shm));
+    }
+    last_shm[k] = shm;
+    last_nb[k] = nb;
+  }
+  return last_nb[k];
 }
 
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
   const int nq = I.ax[d].nq;
-  dim3 grid((nq + 63) / 64, I.nsplit_h);
+  const int rows = cubic_h_rows(I);
+  dim3 grid((nq + rows - 1) / rows, I.nsplit_h);
   if (I.mixed) {
-    k_cubic_h<float><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
+    k_cubic_h32<<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   } else {
     k_cubic_h<double><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   }
@@ -1760,7 +1897,8 @@ hipError_t configure_kernels() {
                       (const void*)k_solve_bcr<3>, (const void*)k_solve_bcr<5>,
                       (const void*)k_solve_bcr<7>, (const void*)k_band_solve_bcr<3>,
                       (const void*)k_band_solve_bcr<5>, (const void*)k_band_solve_bcr<7>,
-                      (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>};
+                      (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>,
+                      (const void*)k_cubic_h32};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipGetLastError();

@@ -253,10 +253,9 @@ void update_view(ctd_solver* s) {
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
     ng = std::min(ng, s->nsplit_g_cap / I.ntri);
     I.nsplit_g = std::max(1, ng);
-    // h: one round of resident workgroups (LDS-limited), triples split evenly
-    const int nqt = (nqmin + 63) / 64;
-    const size_t shm_h = cubic_h_lds(I);
-    const int per_cu = std::max(1, std::min(8, (int)((size_t)max_lds_bytes() / shm_h)));
+    // h: one round of resident workgroups, triples split evenly
+    const int nqt = (nqmin + cubic_h_rows(I) - 1) / cubic_h_rows(I);
+    const int per_cu = std::max(1, std::min(8, cubic_h_blocks_per_cu(I)));
     const int slots = num_cus() * per_cu;
     I.nsplit_h = std::max(1, std::min(I.ntri, slots / nqt));
   }
