@@ -186,7 +186,9 @@ void ctd_batch_destroy(ctd_batch* b);
 /* Symmetric positive definite banded solve, FP64: count independent systems
  * A_k x_k = b_k, A_k = alpha[k] Mb + beta[k] Kb with Mb, Kb in lower band
  * storage ((bw+1) x n, row t holds A[i+t, i] at [t*n + i]).  b, x: device,
- * count x n.  alpha/beta: device, count values. */
+ * count x n.  alpha/beta: device, count values.  Block cyclic reduction, one
+ * workgroup per system; systems whose block data exceed the LDS use a
+ * stream-ordered device workspace allocated and released by the call. */
 int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
                           const double* Kb, const double* alpha,
                           const double* beta, const double* b, double* x,
@@ -202,14 +204,13 @@ enum {
                           (3D, MFMA split-K launch + its reduction)       */
   CTD_K_CUBIC_H,       /* cubic evaluation h_d at the Gauss points (MFMA)*/
   CTD_K_RHS,           /* right-hand side assembly + nonlinear projection */
-  CTD_K_SOLVE,         /* banded LDL^T solve + normalisation              */
+  CTD_K_SOLVE,         /* banded solve (block cyclic reduction) + normalisation */
   CTD_K_SIGNATURE,     /* Grams of a fresh factor, Gauss-point values     */
   CTD_K_GEMV,          /* M_xy products (2D)                              */
   CTD_K_MXY,           /* M_xy build (2D, once per step)                  */
   CTD_K_ENERGY,        /* separated energy                                */
   CTD_K_QUAD,          /* Gauss-point tables of u^k (once per step)       */
   CTD_K_OTHER,         /* init/append/reset                               */
-  CTD_K_FACTOR,        /* banded LDL^T factorisation (second stream)      */
   CTD_K_COUNT
 };
 int ctd_profile_enable(ctd_solver* s, int32_t on);

@@ -99,6 +99,7 @@ struct DevInst {
   void* gpart;       // nsplit_g x ntri x 4096 (T)
   void* S;           // ntri x 4096 (T), weighted g_e * g_f
   double* hpart;     // nsplit_h x nqmax
+  double* bcr_ws;    // cyclic-reduction block data in HBM for axes too large for LDS (else null)
   int nsplit_g, nsplit_h;
   // 2D route
   double* T1;        // n0 x nq1
@@ -117,8 +118,6 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
                            hipStream_t st);
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
-hipError_t launch_factor(const DevInst& I, int d, double* fac, hipStream_t st);
-hipError_t launch_solve(const DevInst& I, int d, int sweep, int M, const double* fac, hipStream_t st);
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
 int rhs_chunks(const DevInst& I, int M, int load_only);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
@@ -141,8 +140,8 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* Kb, const double* alpha,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
-int solve_lds_max_n(int B);
-bool bcr_fits(int n, int B);
+bool bcr_fits(int n, int B);                       // block data fit in LDS
+__host__ __device__ size_t bcr_lds_bytes(int n, int B);   // block data bytes of one system
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();

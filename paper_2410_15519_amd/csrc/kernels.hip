@@ -438,231 +438,33 @@ hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStre
 }
 
 // ------------------------------------------------------------ band solve
-// SPD banded systems (alpha M + beta K) x = b, half-bandwidth B, by LDL^T.
-// Factorisation and substitution are separate kernels: the factorisation
-// depends only on (alpha, beta), so the host launches it on a second stream
-// where it overlaps the nonlinear contraction; the substitution and the
-// normalisation stay on the critical path.  Both recurrences are sequential
-// in the row index and run in one thread with the active window in
-// registers and the band staged in LDS; the recurrences are ordered so that
-// each step depends on the previous one through a single FMA.
-// Factor layout ((B+1) x n, global or LDS): [j] = 1/D_j, [t*n + j] = L_{j+t,j}.
-
-__device__ __forceinline__ double recip(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
-
-template <int B>
-__device__ void ldlt_factor(int n, double* band) {
-  double w[B + 1][B + 1];
-#pragma unroll
-  for (int r = 0; r <= B; ++r)
-#pragma unroll
-    for (int c = 0; c <= r; ++c) w[r][c] = band[(r - c) * n + c];
-  double nr[B + 1];
-#pragma unroll
-  for (int c = 0; c <= B; ++c)
-    nr[c] = (B + 1 < n) ? band[(B - c) * n + (1 + c)] : (c == B ? 1.0 : 0.0);
-  for (int j = 0; j < n; ++j) {
-    const double dj = w[0][0];
-    const double sq = w[1][0] * w[1][0];
-    const double rd = recip(dj);
-    double l[B + 1];
-#pragma unroll
-    for (int t = 1; t <= B; ++t) l[t] = w[t][0] * rd;
-    double wn[B + 1][B + 1];
-    wn[0][0] = fma(-sq, rd, w[1][1]);
-#pragma unroll
-    for (int r = 0; r < B; ++r)
-#pragma unroll
-      for (int c = 0; c <= r; ++c)
-        if (r > 0 || c > 0) wn[r][c] = fma(-w[r + 1][0], l[c + 1], w[r + 1][c + 1]);
-#pragma unroll
-    for (int c = 0; c <= B; ++c) wn[B][c] = nr[c];
-    // prefetch the row entering at the next step
-    const int inew = j + 2 + B;
-#pragma unroll
-    for (int c = 0; c <= B; ++c)
-      nr[c] = (inew < n) ? band[(B - c) * n + (j + 2 + c)] : (c == B ? 1.0 : 0.0);
-    band[j] = rd;
-#pragma unroll
-    for (int t = 1; t <= B; ++t) band[t * n + j] = l[t];
-#pragma unroll
-    for (int r = 0; r <= B; ++r)
-#pragma unroll
-      for (int c = 0; c <= r; ++c) w[r][c] = wn[r][c];
-  }
-}
-
-template <int B>
-__device__ void ldlt_subst(int n, const double* fac, double* x) {
-  double yw[B];
-#pragma unroll
-  for (int t = 0; t < B; ++t) yw[t] = 0.0;
-  double pb = x[0], pr = fac[0];
-  double pl[B + 1];
-#pragma unroll
-  for (int t = 1; t <= B; ++t) pl[t] = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double bj = pb, rj = pr;
-    double lj[B + 1];
-#pragma unroll
-    for (int t = 1; t <= B; ++t) lj[t] = pl[t];
-    if (j + 1 < n) {
-      pb = x[j + 1];
-      pr = fac[j + 1];
-#pragma unroll
-      for (int t = 1; t <= B; ++t) pl[t] = (j + 1 - t >= 0) ? fac[t * n + j + 1 - t] : 0.0;
-    }
-    double part = bj;
-#pragma unroll
-    for (int t = B; t >= 2; --t) part = fma(-lj[t], yw[t - 1], part);
-    const double yj = fma(-lj[1], yw[0], part);
-    x[j] = yj * rj;
-#pragma unroll
-    for (int t = B - 1; t > 0; --t) yw[t] = yw[t - 1];
-    yw[0] = yj;
-  }
-  double xw[B];
-#pragma unroll
-  for (int t = 0; t < B; ++t) xw[t] = 0.0;
-  double pz = x[n - 1];
-#pragma unroll
-  for (int t = 1; t <= B; ++t) pl[t] = fac[t * n + n - 1];
-  for (int j = n - 1; j >= 0; --j) {
-    const double zj = pz;
-    double lj[B + 1];
-#pragma unroll
-    for (int t = 1; t <= B; ++t) lj[t] = pl[t];
-    if (j > 0) {
-      pz = x[j - 1];
-#pragma unroll
-      for (int t = 1; t <= B; ++t) pl[t] = fac[t * n + j - 1];
-    }
-    double part = zj;
-#pragma unroll
-    for (int t = B; t >= 2; --t) part = fma(-lj[t], xw[t - 1], part);
-    const double xj = fma(-lj[1], xw[0], part);
-    x[j] = xj;
-#pragma unroll
-    for (int t = B - 1; t > 0; --t) xw[t] = xw[t - 1];
-    xw[0] = xj;
-  }
-}
-
-__device__ void run_factor(int B, int n, double* band) {
-  switch (B) {
-    case 3: ldlt_factor<3>(n, band); break;
-    case 5: ldlt_factor<5>(n, band); break;
-    case 7: ldlt_factor<7>(n, band); break;
-    default: break;
-  }
-}
-
-__device__ void run_subst(int B, int n, const double* fac, double* x) {
-  switch (B) {
-    case 3: ldlt_subst<3>(n, fac, x); break;
-    case 5: ldlt_subst<5>(n, fac, x); break;
-    case 7: ldlt_subst<7>(n, fac, x); break;
-    default: break;
-  }
-}
+// SPD banded systems (alpha M + beta K) x = b, half-bandwidth B.
 
 int max_lds_bytes();
-int solve_lds_max_n(int B) {
-  const size_t budget = (size_t)max_lds_bytes() - 1024;
-  return (int)(budget / (sizeof(double) * (B + 2)));
-}
 
-// alpha_d, beta_d of K_d = alpha_d M_d + beta_d K_d (eq. KxQx, 3D analogue)
-// from the fixed factors' m_e = u_e.M.u_e, k_e = u_e.K.u_e; then the factor.
-__global__ __launch_bounds__(64) void k_factor(DevInst I, int d, double* fac) {
-  extern __shared__ double sm[];
-  DevAxis& A = I.ax[d];
-  const int n = A.n, B = A.B;
-  __shared__ double ab[2];
-  if (threadIdx.x == 0) {
-    double pm = 1.0, grad = 0.0;
-    for (int e = 0; e < I.dim; ++e)
-      if (e != d) pm *= I.sc->m[e];
-    for (int e = 0; e < I.dim; ++e) {
-      if (e == d) continue;
-      double t = I.sc->k[e];
-      for (int f = 0; f < I.dim; ++f)
-        if (f != d && f != e) t *= I.sc->m[f];
-      grad += t;
-    }
-    ab[0] = I.c * pm + I.lam * grad;
-    ab[1] = I.lam * pm;
-    I.sc->alpha[d] = ab[0];
-    I.sc->beta[d] = ab[1];
-  }
-  __syncthreads();
-  const double al = ab[0], be = ab[1];
-  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x)
-    sm[idx] = al * A.Mb[idx] + be * A.Kb[idx];
-  __syncthreads();
-  if (threadIdx.x == 0) run_factor(B, n, sm);
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x) fac[idx] = sm[idx];
-}
-
-hipError_t launch_factor(const DevInst& I, int d, double* fac, hipStream_t st) {
-  const DevAxis& A = I.ax[d];
-  size_t shm = sizeof(double) * ((size_t)(A.B + 1) * A.n);
-  k_factor<<<1, 64, shm, st>>>(I, d, fac);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_solve(DevInst I, int d, int sweep, const double* fac, int nchunk) {
-  extern __shared__ double sm[];
-  __shared__ double red[16];
-  DevAxis& A = I.ax[d];
-  const int n = A.n, B = A.B;
-  double* f = sm;
-  double* x = sm + (size_t)(B + 1) * n;
-  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x) f[idx] = fac[idx];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = rhs_at(A, i, nchunk);
-  __syncthreads();
-  if (threadIdx.x == 0) run_subst(B, n, f, x);
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) A.u[i] = x[i];
-  __syncthreads();
-  finalize_body(I, d, sweep, 0, red);
-}
-
-hipError_t launch_solve(const DevInst& I, int d, int sweep, int M, const double* fac, hipStream_t st) {
-  const DevAxis& A = I.ax[d];
-  size_t shm = sizeof(double) * ((size_t)(A.B + 2) * A.n);
-  k_solve<<<1, 256, shm, st>>>(I, d, sweep, fac, rhs_chunks(I, M, 0));
-  return hipGetLastError();
-}
-
-// ---- block cyclic reduction (all sizes whose block data fit in LDS) ----
+// ---- block cyclic reduction (block data in LDS, or in a global workspace) ----
 // The band matrix is block tridiagonal with B x B blocks: D_I (diagonal),
 // L_I = A[block I, block I-1] (upper triangular at the start).  At level
 // l (stride s = 2^l) the active blocks are I = s-1 + k s; those with even k
 // are eliminated, the odd ones receive the Schur complements
-//   D_I -= L_I D_J1^-1 L_I^T + L_J2^T D_J2^-1 L_J2,   L_I <- -L_I D_J1^-1 L_J1,
-//   b_I -= L_I D_J1^-1 b_J1 + L_J2^T D_J2^-1 b_J2     (J1 = I-s, J2 = I+s),
-// formed through the Cholesky factors G of the eliminated D_J.  The
-// back substitution walks the levels down: x_J = D_J^-1 (b_J - L_J x_{J-s}
-// - L_{J+s}^T x_{J+s}).  One thread per block, barriers between phases.
-// LDS is block-major with an odd stride in doubles so that the threads of
-// a level read different banks; per block: packed G/D
-// (B(B+1)/2, G keeps 1/g on its diagonal), L (B^2), copy of L_{J+s} (B^2),
-// b/x (B).
+//   D_I -= V1^T V1 + V2^T V2,   L_I <- -V1^T W1,   b_I -= V1^T y1 + V2^T y2,
+// V1 = G1^-1 L_I^T, W1 = G1^-1 L_J1, y1 = G1^-1 b_J1, V2 = G2^-1 L_J2,
+// y2 = G2^-1 b_J2, with G1 G1^T = D_J1, G2 G2^T = D_J2 (J1 = I-s, J2 = I+s).
+// The back substitution walks the levels down:
+//   x_J = G_J^-T G_J^-1 (b_J - L_J x_{J-s} - L_{J+s}^T x_{J+s}).
+// One group of B lanes per kept block, lane c owning column c; both
+// neighbour Cholesky factors are formed redundantly in every lane of the
+// group, and the columns are exchanged with in-wave shuffles, so a level
+// costs one workgroup barrier.  Per block (block-major, odd stride in
+// doubles): D (packed, B(B+1)/2), L (B^2), copy of the L_{J+s} the
+// back substitution needs (B^2), b/x (B), Cholesky factor G of the block
+// when it is eliminated (packed; 1/g on its diagonal).
 template <int B>
 struct Bcr {
   static constexpr int NP = B * (B + 1) / 2;
-  static constexpr int OL = NP, OLN = NP + B * B, OB = NP + 2 * B * B;
-  // odd stride in doubles: consecutive blocks fall in different LDS banks
-  static constexpr int STRIDE = (NP + 2 * B * B + B) | 1;
-  __device__ static constexpr int pk(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
+  static constexpr int OL = NP, OLN = NP + B * B, OB = NP + 2 * B * B, OG = NP + 2 * B * B + B;
+  static constexpr int STRIDE = (2 * NP + 2 * B * B + B) | 1;
+  __host__ __device__ static constexpr int pk(int r, int c) { return r * (r + 1) / 2 + c; }   // c <= r
   // Cholesky of a packed SPD block; diagonal stored as 1/g
   __device__ static void chol(double* D) {
 #pragma unroll
@@ -704,347 +506,232 @@ struct Bcr {
   }
 };
 
-template <int B>
-__device__ void bcr_solve(int n, const double* Mb, const double* Kb, double al, double be,
-                          const double* rpart, int nchunk, double* out, double* sm) {
-  typedef Bcr<B> T;
+// Threads of the solve workgroup: one wave per 64/B kept blocks of the first
+// level (one round up to n ~ 1.1k at B = 5), 4 waves at least, and at most
+// as many as keep the per-lane registers of a level (which grow as B^2) free
+// of spills.
+__host__ __device__ constexpr int bcr_max_waves(int B) { return B >= 7 ? 8 : 10; }
+__host__ __device__ inline int bcr_threads(int n, int B) {
   const int N = (n + B - 1) / B;
-  const int tid = threadIdx.x, nt = blockDim.x;
-#define BCR(e, I) sm[(size_t)(I) * T::STRIDE + (e)]
-  for (int idx = tid; idx < N * T::STRIDE; idx += nt) sm[idx] = 0.0;
-  __syncthreads();
-  // band entries (t, j) = A[j+t][j] scattered into D_I (same block) or L_I
-  // (next block); coalesced over j
-  for (int idx = tid; idx < (B + 1) * n; idx += nt) {
-    const int t = idx / n, j = idx - t * n, i = j + t;
-    if (i >= n) continue;
-    const double v = al * Mb[idx] + be * Kb[idx];
-    const int I = i / B, r = i - I * B, J = j / B, c = j - J * B;
-    if (I == J) BCR(T::pk(r, c), I) = v;
-    else BCR(T::OL + r * B + c, I) = v;
-  }
-  // identity padding rows and the right-hand side (sum of chunk partials)
-  for (int i = tid; i < N * B; i += nt) {
-    const int I = i / B, r = i - I * B;
-    if (i >= n) BCR(T::pk(r, r), I) = 1.0;
-    double v = 0.0;
-    if (i < n)
-      for (int y = 0; y <= nchunk; ++y) v += rpart[(size_t)y * n + i];
-    BCR(T::OB + r, I) = v;
-  }
-  __syncthreads();
-  int top = 1;
-  for (int s = 1;; s <<= 1) {
-    const int first = s - 1;
-    if (first >= N) break;
-    const int count = (N - first + s - 1) / s;
-    top = s;
-    // phase A: eliminated blocks factor their diagonal block, keep L_{J+s}
-    for (int k = 2 * tid; k < count; k += 2 * nt) {
-      const int J = first + k * s;
-      double D[T::NP];
-#pragma unroll
-      for (int e = 0; e < T::NP; ++e) D[e] = BCR(e, J);
-      T::chol(D);
-#pragma unroll
-      for (int e = 0; e < T::NP; ++e) BCR(e, J) = D[e];
-      const bool has = J + s < N;
-#pragma unroll
-      for (int e = 0; e < B * B; ++e) BCR(T::OLN + e, J) = has ? BCR(T::OL + e, J + s) : 0.0;
-    }
-    __syncthreads();
-    // phase B: kept blocks take the Schur complements.  The columns of
-    // V = G^-1 (coupling) are staged in the block's idle L_{J+s} slot.
-    for (int k = 2 * tid + 1; k < count; k += 2 * nt) {
-      const int I = first + k * s;
-      const int J1 = I - s, J2 = I + s;
-#pragma unroll 1
-      for (int side = 0; side < 2; ++side) {
-        const int J = side == 0 ? J1 : J2;
-        if (J >= N) break;
-        double G[T::NP];
-#pragma unroll
-        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
-        // V[:, c]: side 0 uses L_I^T (coupling I -> J1), side 1 uses L_J2
-#pragma unroll 1
-        for (int c = 0; c < B; ++c) {
-          double col[B];
-#pragma unroll
-          for (int r = 0; r < B; ++r)
-            col[r] = side == 0 ? BCR(T::OL + c * B + r, I) : BCR(T::OL + r * B + c, J);
-          T::fwd(G, col);
-#pragma unroll
-          for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = col[r];
-        }
-        double u[B];
-#pragma unroll
-        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J);
-        T::fwd(G, u);
-#pragma unroll 1
-        for (int r = 0; r < B; ++r) {
-          double vr[B];
-#pragma unroll
-          for (int q = 0; q < B; ++q) vr[q] = BCR(T::OLN + r * B + q, I);
-          double t = 0.0;
-#pragma unroll
-          for (int q = 0; q < B; ++q) t += vr[q] * u[q];
-          BCR(T::OB + r, I) -= t;
-#pragma unroll 1
-          for (int c = 0; c <= r; ++c) {
-            double z = 0.0;
-#pragma unroll
-            for (int q = 0; q < B; ++q) z += vr[q] * BCR(T::OLN + c * B + q, I);
-            BCR(T::pk(r, c), I) -= z;
-          }
-        }
-        if (side == 0) {
-          // new coupling to I - 2s: -L_I D_J1^-1 L_J1 = -V^T (G^-1 L_J1)
-#pragma unroll 1
-          for (int c = 0; c < B; ++c) {
-            double wc[B];
-#pragma unroll
-            for (int r = 0; r < B; ++r) wc[r] = BCR(T::OL + r * B + c, J);
-            T::fwd(G, wc);
-#pragma unroll
-            for (int r = 0; r < B; ++r) {
-              double z = 0.0;
-#pragma unroll
-              for (int q = 0; q < B; ++q) z += BCR(T::OLN + r * B + q, I) * wc[q];
-              BCR(T::OL + r * B + c, I) = -z;
-            }
-          }
-        }
-      }
-    }
-    __syncthreads();
-    if (count == 1) break;
-  }
-  // back substitution, top level down; x overwrites b of each block
-  for (int s = top; s >= 1; s >>= 1) {
-    const int first = s - 1;
-    const int count = first < N ? (N - first + s - 1) / s : 0;
-    for (int k = 2 * tid; k < count; k += 2 * nt) {
-      const int J = first + k * s;
-      double v[B], G[T::NP];
-#pragma unroll
-      for (int r = 0; r < B; ++r) v[r] = BCR(T::OB + r, J);
-#pragma unroll
-      for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
-      if (J - s >= 0) {
-        double xm[B];
-#pragma unroll
-        for (int c = 0; c < B; ++c) xm[c] = BCR(T::OB + c, J - s);
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-#pragma unroll
-          for (int c = 0; c < B; ++c) v[r] -= BCR(T::OL + r * B + c, J) * xm[c];
-      }
-      if (J + s < N) {
-        double xp[B];
-#pragma unroll
-        for (int c = 0; c < B; ++c) xp[c] = BCR(T::OB + c, J + s);
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-#pragma unroll
-          for (int c = 0; c < B; ++c) v[r] -= BCR(T::OLN + c * B + r, J) * xp[c];
-      }
-      T::fwd(G, v);
-      T::bwd(G, v);
-#pragma unroll
-      for (int r = 0; r < B; ++r) BCR(T::OB + r, J) = v[r];
-    }
-    __syncthreads();
-  }
-  for (int i = tid; i < n; i += nt) {
-    const int I = i / B, r = i - I * B;
-    out[i] = BCR(T::OB + r, I);
-  }
-  __syncthreads();
-#undef BCR
+  const int gpw = 64 / B, wmax = bcr_max_waves(B);
+  int w = ((N / 2) + gpw - 1) / gpw;
+  w = w < 4 ? 4 : (w > wmax ? wmax : w);
+  return 64 * w;
 }
 
-// Column-parallel variant: a group of 8 lanes per block, lane c owning
-// column c of every B x B operation (B <= 8), so each level's dependency
-// chain is that of one column instead of a whole block.
 template <int B>
-__device__ void bcr_solve_par(int n, const double* Mb, const double* Kb, double al, double be,
+__device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const double* Kb, double al, double be,
                               const double* rpart, int nchunk, double* out, double* sm) {
   typedef Bcr<B> T;
-  static_assert(B <= 8, "group of 8 lanes per block");
+  static_assert(B <= 8, "a group of B lanes per block");
+  constexpr int NP = T::NP;
+  constexpr int GPW = 64 / B;                  // groups per wave
   const int N = (n + B - 1) / B;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int grp = tid >> 3, c = tid & 7, ngrp = nt >> 3;
-  const bool lane_ok = c < B;
+  const int ln = tid & 63, gi = ln / B;
+  const bool lane_ok = gi < GPW;
+  const int c = lane_ok ? ln - gi * B : 0;     // column owned by this lane
+  const int gbase = lane_ok ? gi * B : 0;      // first lane of the group in its wave
+  const int grp = (tid >> 6) * GPW + (lane_ok ? gi : 0), ngrp = (nt >> 6) * GPW;
 #define BCR(e, I) sm[(size_t)(I) * T::STRIDE + (e)]
-  for (int idx = tid; idx < N * T::STRIDE; idx += nt) sm[idx] = 0.0;
-  __syncthreads();
-  for (int idx = tid; idx < (B + 1) * n; idx += nt) {
-    const int t = idx / n, j = idx - t * n, i = j + t;
-    if (i >= n) continue;
-    const double v = al * Mb[idx] + be * Kb[idx];
-    const int I = i / B, r = i - I * B, J = j / B, cc = j - J * B;
-    if (I == J) BCR(T::pk(r, cc), I) = v;
-    else BCR(T::OL + r * B + cc, I) = v;
+  // D, L and b of every block: clear D and L (padding rows of the last block
+  // get a unit diagonal), scatter the band entries with coalesced loads
+  // issued four at a time, and sum the RHS partials
+  for (int idx = tid; idx < N * (NP + B * B); idx += nt) {
+    const int I = idx / (NP + B * B), e = idx - I * (NP + B * B);
+    double v = 0.0;
+    if (e < NP) {
+      int r = 0;
+      while (T::pk(r + 1, 0) <= e) ++r;
+      if (I * B + r >= n && e == T::pk(r, r)) v = 1.0;
+    }
+    BCR(e, I) = v;
   }
   for (int i = tid; i < N * B; i += nt) {
     const int I = i / B, r = i - I * B;
-    if (i >= n) BCR(T::pk(r, r), I) = 1.0;
     double v = 0.0;
     if (i < n)
       for (int y = 0; y <= nchunk; ++y) v += rpart[(size_t)y * n + i];
     BCR(T::OB + r, I) = v;
   }
   __syncthreads();
+  {
+    const int total = (B + 1) * n;
+    for (int base = tid; base < total; base += 4 * nt) {
+      double mv[4], kv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = base + u * nt;
+        mv[u] = idx < total ? Mb[idx] : 0.0;
+        kv[u] = idx < total ? Kb[idx] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int idx = base + u * nt;
+        const int t = idx / n, j = idx - t * n, i = j + t;   // entry A[i, j], i = j + t
+        if (idx < total && i < n) {
+          const double v = al * mv[u] + be * kv[u];
+          const int I = i / B, r = i - I * B, J = j / B, cc = j - J * B;
+          if (I == J) BCR(T::pk(r, cc), I) = v;
+          else BCR(T::OL + r * B + cc, I) = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
   int top = 1;
   for (int s = 1;; s <<= 1) {
     const int first = s - 1;
-    if (first >= N) break;
     const int count = (N - first + s - 1) / s;
-    top = s;
-    const int nelim = (count + 1) / 2, nkept = count / 2;
-    // phase A: eliminated blocks: Cholesky (lane 0), copy of L_{J+s} (column per lane)
-    for (int g = grp; g < nelim; g += ngrp) {
-      const int J = first + 2 * g * s;
-      if (c == 0) {
-        double D[T::NP];
+    if (count <= 1) { top = s; break; }
+    const int nkept = count / 2;
+    for (int g0 = 0; g0 < nkept; g0 += ngrp) {
+      const int g = g0 + grp;
+      const bool act = lane_ok && g < nkept;
+      // inactive lanes work on kept block 0 of the level (loads stay in
+      // range; nothing is stored) so that every lane takes part in the shuffles
+      const int k = act ? 2 * g + 1 : 1;
+      const int I = first + k * s, J1 = I - s;
+      const bool has2 = k + 1 < count;
+      const int J2 = has2 ? I + s : J1;
+      // V1 = G1^-1 L_I^T and V2 = G2^-1 L_J2 are exchanged between the lanes
+      // of the group through the idle slots of the kept block I (its L copy
+      // and factor slots are first written when I is eliminated); a group
+      // lives in one wave, whose LDS accesses complete in order.
+      double* vx = &BCR(T::OLN, I);               // V1 (B x B, column-major by lane)
+      double w1[B], y1[B], v2[B], y2[B];
+      double bc = 0.0;
+      {
+        // side J1: its factor is kept for the back substitution together
+        // with the L_I it will need
+        double G[NP], v1[B];
 #pragma unroll
-        for (int e = 0; e < T::NP; ++e) D[e] = BCR(e, J);
-        T::chol(D);
+        for (int q = 0; q < B; ++q) {
+          v1[q] = BCR(T::OL + c * B + q, I);      // row c of L_I
+          w1[q] = BCR(T::OL + q * B + c, J1);     // column c of L_J1
+          y1[q] = BCR(T::OB + q, J1);
+        }
+        if (act)
 #pragma unroll
-        for (int e = 0; e < T::NP; ++e) BCR(e, J) = D[e];
+          for (int q = 0; q < B; ++q) BCR(T::OLN + c * B + q, J1) = v1[q];
+#pragma unroll
+        for (int e = 0; e < NP; ++e) G[e] = BCR(e, J1);
+        T::chol(G);
+        T::fwd(G, v1);
+        T::fwd(G, w1);
+        T::fwd(G, y1);
+        if (act) {
+#pragma unroll
+          for (int e = 0; e < NP; ++e)
+            if (e % B == c) BCR(T::OG + e, J1) = G[e];
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) bc += v1[q] * y1[q];
+        __builtin_amdgcn_wave_barrier();
+        if (act)
+#pragma unroll
+          for (int q = 0; q < B; ++q) vx[c * B + q] = v1[q];
       }
-      if (lane_ok) {
-        const bool has = J + s < N;
+      {
+        // side J2 (absent: contributes zero); its factor is kept when it is
+        // the last active block, which no other kept block has as J1
+        double G[NP];
+#pragma unroll
+        for (int e = 0; e < NP; ++e) G[e] = BCR(e, J2);
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+          v2[q] = BCR(T::OL + q * B + c, J2);     // column c of L_J2
+          y2[q] = BCR(T::OB + q, J2);
+        }
+        T::chol(G);
+        T::fwd(G, v2);
+        T::fwd(G, y2);
+        if (act && has2 && k + 1 == count - 1) {
+#pragma unroll
+          for (int e = 0; e < NP; ++e)
+            if (e % B == c) BCR(T::OG + e, J2) = G[e];
+        }
+        if (!has2) {
+#pragma unroll
+          for (int q = 0; q < B; ++q) { v2[q] = 0.0; y2[q] = 0.0; }
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) bc += v2[q] * y2[q];
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (act) {
+        double v1c[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) v1c[q] = vx[c * B + q];
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+          double d = 0.0, lsum = 0.0;
+#pragma unroll
+          for (int q = 0; q < B; ++q) {
+            const double a1 = vx[r * B + q];                    // V1[q][r]
+            const double a2 = __shfl(v2[q], gbase + r, 64);     // V2[q][r]
+            d += a1 * v1c[q] + a2 * v2[q];
+            lsum += a1 * w1[q];
+          }
+          if (r >= c) BCR(T::pk(r, c), I) -= d;
+          BCR(T::OL + r * B + c, I) = -lsum;
+        }
+        BCR(T::OB + c, I) -= bc;
+      } else {
 #pragma unroll
         for (int r = 0; r < B; ++r)
-          BCR(T::OLN + r * B + c, J) = has ? BCR(T::OL + r * B + c, J + s) : 0.0;
+#pragma unroll
+          for (int q = 0; q < B; ++q) (void)__shfl(v2[q], gbase + r, 64);
       }
     }
     __syncthreads();
-    // phase B, side J1 = I - s: V = G^-1 L_I^T staged in the kept block's
-    // idle L_{J+s} slot (column per lane), then Schur updates per column
-    const int rounds = (nkept + ngrp - 1) / ngrp;
-    for (int rd = 0; rd < rounds; ++rd) {
-      const int g = grp + rd * ngrp;
-      const bool act = lane_ok && g < nkept;
-      const int I = first + (2 * g + 1) * s;
-      const int J1 = I - s, J2 = I + s;
-      double G[T::NP], w[B], u[B];
-      if (act) {
-#pragma unroll
-        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J1);
-        double v[B];
-#pragma unroll
-        for (int r = 0; r < B; ++r) v[r] = BCR(T::OL + c * B + r, I);   // L_I^T column c
-        T::fwd(G, v);
-#pragma unroll
-        for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = v[r];
-#pragma unroll
-        for (int r = 0; r < B; ++r) w[r] = BCR(T::OL + r * B + c, J1);  // L_J1 column c
-        T::fwd(G, w);
-#pragma unroll
-        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J1);
-        T::fwd(G, u);
-      }
-      __syncthreads();
-      if (act) {
-        double vc[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) vc[q] = BCR(T::OLN + c * B + q, I);
-#pragma unroll
-        for (int r = 0; r < B; ++r) {
-          double vr[B];
-#pragma unroll
-          for (int q = 0; q < B; ++q) vr[q] = BCR(T::OLN + r * B + q, I);
-          if (r >= c) {
-            double z = 0.0;
-#pragma unroll
-            for (int q = 0; q < B; ++q) z += vr[q] * vc[q];
-            BCR(T::pk(r, c), I) -= z;
-          }
-          double z = 0.0;
-#pragma unroll
-          for (int q = 0; q < B; ++q) z += vr[q] * w[q];
-          BCR(T::OL + r * B + c, I) = -z;   // coupling to I - 2s
-        }
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < B; ++q) t += vc[q] * u[q];
-        BCR(T::OB + c, I) -= t;
-      }
-      __syncthreads();
-      // side J2 = I + s
-      const bool act2 = act && J2 < N;
-      if (act2) {
-#pragma unroll
-        for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J2);
-        double v[B];
-#pragma unroll
-        for (int r = 0; r < B; ++r) v[r] = BCR(T::OL + r * B + c, J2);  // L_J2 column c
-        T::fwd(G, v);
-#pragma unroll
-        for (int r = 0; r < B; ++r) BCR(T::OLN + c * B + r, I) = v[r];
-#pragma unroll
-        for (int r = 0; r < B; ++r) u[r] = BCR(T::OB + r, J2);
-        T::fwd(G, u);
-      }
-      __syncthreads();
-      if (act2) {
-        double vc[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) vc[q] = BCR(T::OLN + c * B + q, I);
-#pragma unroll
-        for (int r = 0; r < B; ++r) {
-          if (r < c) continue;
-          double z = 0.0;
-#pragma unroll
-          for (int q = 0; q < B; ++q) z += BCR(T::OLN + r * B + q, I) * vc[q];
-          BCR(T::pk(r, c), I) -= z;
-        }
-        double t = 0.0;
-#pragma unroll
-        for (int q = 0; q < B; ++q) t += vc[q] * u[q];
-        BCR(T::OB + c, I) -= t;
-      }
-      __syncthreads();
-    }
-    if (count == 1) break;
   }
-  // back substitution, top level down (lane 0 of each group)
-  for (int s = top; s >= 1; s >>= 1) {
+  // last active block: x = D^-1 b
+  if (tid < B) {
+    const int J = top - 1;
+    double G[NP], v[B];
+#pragma unroll
+    for (int e = 0; e < NP; ++e) G[e] = BCR(e, J);
+#pragma unroll
+    for (int q = 0; q < B; ++q) v[q] = BCR(T::OB + q, J);
+    T::chol(G);
+    T::fwd(G, v);
+    T::bwd(G, v);
+    if (tid == 0)
+#pragma unroll
+      for (int q = 0; q < B; ++q) BCR(T::OB + q, J) = v[q];
+  }
+  __syncthreads();
+  // back substitution, top level down
+  for (int s = top >> 1; s >= 1; s >>= 1) {
     const int first = s - 1;
-    const int count = first < N ? (N - first + s - 1) / s : 0;
+    const int count = (N - first + s - 1) / s;
     const int nelim = (count + 1) / 2;
-    for (int g = grp; g < nelim; g += ngrp) {
-      if (c != 0) continue;
-      const int J = first + 2 * g * s;
-      double v[B], G[T::NP];
+    for (int g0 = 0; g0 < nelim; g0 += ngrp) {
+      const int g = g0 + grp;
+      const bool act = lane_ok && g < nelim;
+      const int J = first + 2 * (act ? g : 0) * s;
+      const bool lo = J - s >= 0, hi = J + s < N;
+      double t = BCR(T::OB + c, J);
+      if (lo) {
 #pragma unroll
-      for (int r = 0; r < B; ++r) v[r] = BCR(T::OB + r, J);
-#pragma unroll
-      for (int e = 0; e < T::NP; ++e) G[e] = BCR(e, J);
-      if (J - s >= 0) {
-        double xm[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) xm[q] = BCR(T::OB + q, J - s);
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-#pragma unroll
-          for (int q = 0; q < B; ++q) v[r] -= BCR(T::OL + r * B + q, J) * xm[q];
+        for (int q = 0; q < B; ++q) t -= BCR(T::OL + c * B + q, J) * BCR(T::OB + q, J - s);
       }
-      if (J + s < N) {
-        double xp[B];
+      if (hi) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) xp[q] = BCR(T::OB + q, J + s);
-#pragma unroll
-        for (int r = 0; r < B; ++r)
-#pragma unroll
-          for (int q = 0; q < B; ++q) v[r] -= BCR(T::OLN + q * B + r, J) * xp[q];
+        for (int q = 0; q < B; ++q) t -= BCR(T::OLN + q * B + c, J) * BCR(T::OB + q, J + s);
       }
+      double v[B], G[NP];
+#pragma unroll
+      for (int q = 0; q < B; ++q) v[q] = __shfl(t, gbase + q, 64);
+#pragma unroll
+      for (int e = 0; e < NP; ++e) G[e] = BCR(T::OG + e, J);
       T::fwd(G, v);
       T::bwd(G, v);
+      double xc = v[0];
 #pragma unroll
-      for (int r = 0; r < B; ++r) BCR(T::OB + r, J) = v[r];
+      for (int q = 1; q < B; ++q) xc = q == c ? v[q] : xc;
+      if (act) BCR(T::OB + c, J) = xc;
     }
     __syncthreads();
   }
@@ -1056,9 +743,9 @@ __device__ void bcr_solve_par(int n, const double* Mb, const double* Kb, double 
 #undef BCR
 }
 
-size_t bcr_lds_bytes(int n, int B) {
+__host__ __device__ size_t bcr_lds_bytes(int n, int B) {
   const int N = (n + B - 1) / B;
-  const int stride = (B * (B + 1) / 2 + 2 * B * B + B) | 1;
+  const int stride = (B * (B + 1) + 2 * B * B + B) | 1;   // Bcr<B>::STRIDE
   return sizeof(double) * (size_t)N * stride;
 }
 
@@ -1066,9 +753,12 @@ bool bcr_fits(int n, int B) { return bcr_lds_bytes(n, B) + 1024 <= (size_t)max_l
 
 // Directional solve by block cyclic reduction: alpha_d, beta_d from the
 // fixed factors, solve, then normalisation and the fixed-point test.
-template <int B>
-__global__ __launch_bounds__(512) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk) {
-  extern __shared__ double sm[];
+// GWS: block data in the global workspace (a separate instantiation, so that
+// the LDS one keeps LDS addressing)
+template <int B, bool GWS>
+__global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk, double* gws) {
+  extern __shared__ double lds[];
+  double* sm = GWS ? gws : lds;
   __shared__ double red[16];
   __shared__ double ab[2];
   DevAxis& A = I.ax[d];
@@ -1095,63 +785,64 @@ __global__ __launch_bounds__(512) void k_solve_bcr(DevInst I, int d, int sweep, 
 
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st) {
   const DevAxis& A = I.ax[d];
-  const size_t shm = bcr_lds_bytes(A.n, A.B);
+  const bool fits = bcr_fits(A.n, A.B);
+  if (!fits && !I.bcr_ws) return hipErrorInvalidValue;
+  const size_t shm = fits ? bcr_lds_bytes(A.n, A.B) : 0;
+  double* gws = fits ? nullptr : I.bcr_ws;
   const int nchunk = rhs_chunks(I, M, 0);
+  const int nt = bcr_threads(A.n, A.B);
+#define SOLVE_BCR(BW)                                                              \
+  (fits ? k_solve_bcr<BW, false><<<1, nt, shm, st>>>(I, d, sweep, nchunk, nullptr)      \
+        : k_solve_bcr<BW, true><<<1, nt, 0, st>>>(I, d, sweep, nchunk, gws))
   switch (A.B) {
-    case 3: k_solve_bcr<3><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
-    case 5: k_solve_bcr<5><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
-    case 7: k_solve_bcr<7><<<1, 512, shm, st>>>(I, d, sweep, nchunk); break;
+    case 3: SOLVE_BCR(3); break;
+    case 5: SOLVE_BCR(5); break;
+    case 7: SOLVE_BCR(7); break;
     default: return hipErrorInvalidValue;
   }
+#undef SOLVE_BCR
   return hipGetLastError();
 }
 
-template <int B>
-__global__ __launch_bounds__(512) void k_band_solve_bcr(int n, const double* Mb, const double* Kb,
+template <int B, bool GWS>
+__global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_band_solve_bcr(int n, const double* Mb, const double* Kb,
                                                         const double* alpha, const double* beta,
-                                                        const double* b, double* x) {
-  extern __shared__ double sm[];
+                                                        const double* b, double* x, double* gws) {
+  extern __shared__ double lds[];
   const int k = blockIdx.x;
+  double* sm = GWS ? gws + (size_t)k * (bcr_lds_bytes(n, B) / sizeof(double)) : lds;
   bcr_solve_par<B>(n, Mb, Kb, alpha[k], beta[k], b + (size_t)k * n, 0, x + (size_t)k * n, sm);
-}
-
-__global__ __launch_bounds__(64) void k_band_solve_batch(int n, int B, const double* Mb, const double* Kb,
-                                   const double* alpha, const double* beta,
-                                   const double* b, double* x) {
-  extern __shared__ double sm[];
-  const int k = blockIdx.x;
-  double* band = sm;
-  double* xs = sm + (size_t)(B + 1) * n;
-  const double al = alpha[k], be = beta[k];
-  for (int idx = threadIdx.x; idx < (B + 1) * n; idx += blockDim.x)
-    band[idx] = al * Mb[idx] + be * Kb[idx];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) xs[i] = b[(size_t)k * n + i];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    run_factor(B, n, band);
-    run_subst(B, n, band, xs);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) x[(size_t)k * n + i] = xs[i];
 }
 
 hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* Kb, const double* alpha,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st) {
-  if (bcr_fits(n, bw)) {
-    const size_t shm = bcr_lds_bytes(n, bw);
-    switch (bw) {
-      case 3: k_band_solve_bcr<3><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
-      case 5: k_band_solve_bcr<5><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
-      case 7: k_band_solve_bcr<7><<<count, 512, shm, st>>>(n, Mb, Kb, alpha, beta, b, x); break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+  const bool fits = bcr_fits(n, bw);
+  const size_t bytes = bcr_lds_bytes(n, bw);
+  double* gws = nullptr;
+  if (!fits) {
+    hipError_t e = hipMallocAsync((void**)&gws, bytes * (size_t)count, st);
+    if (e != hipSuccess) return e;
   }
-  size_t shm = sizeof(double) * ((size_t)(bw + 2) * n);
-  k_band_solve_batch<<<count, 64, shm, st>>>(n, bw, Mb, Kb, alpha, beta, b, x);
-  return hipGetLastError();
+  const size_t shm = fits ? bytes : 0;
+  const int nt = bcr_threads(n, bw);
+#define BAND_BCR(BW)                                                                     \
+  (fits ? k_band_solve_bcr<BW, false><<<count, nt, shm, st>>>(n, Mb, Kb, alpha, beta, b, x, nullptr) \
+        : k_band_solve_bcr<BW, true><<<count, nt, 0, st>>>(n, Mb, Kb, alpha, beta, b, x, gws))
+  switch (bw) {
+    case 3: BAND_BCR(3); break;
+    case 5: BAND_BCR(5); break;
+    case 7: BAND_BCR(7); break;
+    default: break;
+  }
+#undef BAND_BCR
+  hipError_t e = hipGetLastError();
+  if (gws) {
+    hipError_t f = hipFreeAsync(gws, st);
+    if (e == hipSuccess) e = f;
+  }
+  return e;
 }
 
 // ------------------------------------------------------------ append
@@ -1893,10 +1584,9 @@ hipError_t configure_kernels() {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     g_num_cus = ncu;
   // Raising the limit is best effort: launches check their own LDS needs.
-  const void* ks[] = {(const void*)k_solve, (const void*)k_band_solve_batch, (const void*)k_factor,
-                      (const void*)k_solve_bcr<3>, (const void*)k_solve_bcr<5>,
-                      (const void*)k_solve_bcr<7>, (const void*)k_band_solve_bcr<3>,
-                      (const void*)k_band_solve_bcr<5>, (const void*)k_band_solve_bcr<7>,
+  const void* ks[] = {(const void*)k_solve_bcr<3, false>, (const void*)k_solve_bcr<5, false>,
+                      (const void*)k_solve_bcr<7, false>, (const void*)k_band_solve_bcr<3, false>,
+                      (const void*)k_band_solve_bcr<5, false>, (const void*)k_band_solve_bcr<7, false>,
                       (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>,
                       (const void*)k_cubic_h32};
   for (const void* k : ks)

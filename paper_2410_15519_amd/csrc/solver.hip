@@ -116,11 +116,6 @@ struct ctd_solver {
   size_t energy_partial_cap = 0;
   std::vector<double> host_tmp;
   Profiler prof;
-  // second stream for the banded factorisations (default priority)
-  hipStream_t fstream = nullptr;
-  hipEvent_t ev_fixed = nullptr, ev_fac = nullptr;
-  double* fac = nullptr;   // (B+1) x nmax LDL^T factor of the current direction
-  bool use_bcr = false;    // every axis fits the LDS-resident cyclic reduction
 
   int fail(int code, const std::string& msg) {
     err = msg;
@@ -159,7 +154,6 @@ namespace {
 
 hipError_t sync_collect(ctd_solver* s) {
   hipError_t e = hipStreamSynchronize(s->stream);
-  if (e == hipSuccess && s->fstream) e = hipStreamSynchronize(s->fstream);
   if (e == hipSuccess && s->prof.on) e = s->prof.collect();
   return e;
 }
@@ -346,19 +340,13 @@ int alloc_instance(ctd_solver* s, int m0) {
   AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
 #undef AL
   {
-    int nmax = 0, bmax = 0;
-    for (int d = 0; d < s->dim; ++d) {
-      nmax = std::max(nmax, s->ax[d].n);
-      bmax = std::max(bmax, s->ax[d].B);
-    }
-    HIPCHK(s, A.alloc((void**)&s->fac, sizeof(double) * (size_t)(bmax + 1) * nmax));
-    s->use_bcr = true;
-    for (int d = 0; d < s->dim; ++d) s->use_bcr = s->use_bcr && bcr_fits(s->ax[d].n, s->ax[d].B);
+    // cyclic-reduction block data of axes too large for LDS live in HBM
+    size_t ws = 0;
+    for (int d = 0; d < s->dim; ++d)
+      if (!bcr_fits(s->ax[d].n, s->ax[d].B)) ws = std::max(ws, bcr_lds_bytes(s->ax[d].n, s->ax[d].B));
+    if (ws) HIPCHK(s, A.alloc((void**)&I.bcr_ws, ws));
   }
   HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
-  HIPCHK(s, hipStreamCreateWithFlags(&s->fstream, hipStreamNonBlocking));
-  HIPCHK(s, hipEventCreateWithFlags(&s->ev_fixed, hipEventDisableTiming));
-  HIPCHK(s, hipEventCreateWithFlags(&s->ev_fac, hipEventDisableTiming));
   return CTD_OK;
 }
 
@@ -447,31 +435,6 @@ int finish_step(ctd_solver* s, int M) {
   return precompute(s);
 }
 
-// LDL^T factorisation of alpha_d M_d + beta_d K_d on the second stream, as
-// soon as the fixed factors of direction d are final (everything queued so
-// far on the main stream); the substitution waits for it.
-int factor_async(ctd_solver* s, int d) {
-  if (s->use_bcr) return CTD_OK;   // cyclic reduction factors and solves in one kernel
-  HIPCHK(s, hipEventRecord(s->ev_fixed, s->stream));
-  HIPCHK(s, hipStreamWaitEvent(s->fstream, s->ev_fixed, 0));
-  const double n = s->I.ax[d].n, B = s->I.ax[d].B;
-  LAUNCH_ON(s, s->fstream, CTD_K_FACTOR, n * (B * B + 3 * B + 8), 8.0 * n * (3 * B + 3),
-            launch_factor(s->I, d, s->fac, s->fstream));
-  HIPCHK(s, hipEventRecord(s->ev_fac, s->fstream));
-  return CTD_OK;
-}
-
-int solve_after_factor(ctd_solver* s, int d, int it, int M) {
-  Work w = w_solve(s, d);
-  if (s->use_bcr) {
-    LAUNCH(s, CTD_K_SOLVE, w.flops, w.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
-    return CTD_OK;
-  }
-  HIPCHK(s, hipStreamWaitEvent(s->stream, s->ev_fac, 0));
-  LAUNCH(s, CTD_K_SOLVE, w.flops, w.bytes, launch_solve(s->I, d, it, M, s->fac, s->stream));
-  return CTD_OK;
-}
-
 int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info* info,
              std::vector<int32_t>& log) {
   auto t0 = std::chrono::steady_clock::now();
@@ -487,10 +450,6 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     HIPCHK(s, launch_reset_scalars(s->I, s->stream));
     HIPCHK(s, launch_init_mode(s->I, s->step_index, mode, warm, s->stream));
     for (int d = 0; d < D; ++d) HIPCHK(s, launch_finalize(s->I, d, 0, 1, s->stream));
-    {
-      int rc = factor_async(s, 0);
-      if (rc) return rc;
-    }
     for (int d = 0; d < D; ++d) {
       Work w = w_sig(s, d, M);
       LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
@@ -517,12 +476,10 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
         {
           Work w = w_rhs(s, d, M);
           LAUNCH(s, CTD_K_RHS, w.flops, w.bytes, launch_rhs(s->I, d, M, s->stream));
-          int rc = solve_after_factor(s, d, it, M);
-          if (rc) return rc;
+          Work ws = w_solve(s, d);
+          LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
         }
         if (d < D - 1) {
-          int rc0 = factor_async(s, d + 1);
-          if (rc0) return rc0;
           Work w = w_sig(s, d, M);
           LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
           int rc = cubic_after(s, d, d + 1);
@@ -539,8 +496,6 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
         if (conv) last = true;
       }
       if (!last) {
-        int rc0 = factor_async(s, 0);
-        if (rc0) return rc0;
         Work w = w_sig(s, D - 1, M);
         LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
         int rc = cubic_after(s, D - 1, 0);
@@ -636,11 +591,6 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
   {
     hipError_t ce = configure_kernels();
     if (ce != hipSuccess) { g_init_error = hipGetErrorString(ce); return CTD_EDEVICE; }
-    for (int d = 0; d < p->dim; ++d)
-      if (p->nodes[d] > solve_lds_max_n(2 * p->patch_s + 1)) {
-        g_init_error = "nodes per axis exceed the LDS-resident banded solve";
-        return CTD_EUNSUPPORTED;
-      }
     if (p->dim == 3) {
       DevInst probe{};
       probe.mixed = p->precision == CTD_PREC_MIXED;
@@ -813,12 +763,8 @@ const char* ctd_last_error(const ctd_solver* s) {
 void ctd_destroy(ctd_solver* s) {
   if (!s) return;
   (void)hipStreamSynchronize(s->stream);
-  if (s->fstream) (void)hipStreamSynchronize(s->fstream);
   s->arena.release();
   s->prof.release();
-  if (s->ev_fixed) (void)hipEventDestroy(s->ev_fixed);
-  if (s->ev_fac) (void)hipEventDestroy(s->ev_fac);
-  if (s->fstream) (void)hipStreamDestroy(s->fstream);
   if (s->sc_host) (void)hipHostFree(s->sc_host);
   delete s;
 }
@@ -828,7 +774,6 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb, const double*
                           double* x, int32_t count, void* hip_stream) {
   if (n < bw + 1 || (bw != 3 && bw != 5 && bw != 7) || count < 0) return CTD_EINVAL;
   if (!Mb || !Kb || !alpha || !beta || !b || !x) return CTD_EINVAL;
-  if (n > solve_lds_max_n(bw)) return CTD_EUNSUPPORTED;
   if (count == 0) return CTD_OK;
   if (configure_kernels() != hipSuccess) return CTD_EDEVICE;
   hipError_t e = launch_band_solve_batch(n, bw, Mb, Kb, alpha, beta, b, x, count, (hipStream_t)hip_stream);

@@ -23,7 +23,7 @@ SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
 KERNELS = ["cubic_g", "cubic_h", "rhs", "solve", "signature", "gemv",
-           "mxy_build", "energy", "quad_eval", "other", "factor"]
+           "mxy_build", "energy", "quad_eval", "other"]
 
 
 class CtdError(RuntimeError):

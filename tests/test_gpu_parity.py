@@ -47,7 +47,8 @@ def test_band_solve_kernel(ctd):
     import torch
     import scipy.linalg as sla
     from oracle.cfe1d import Axis
-    for s, n in ((1, 37), (2, 100), (2, 1031), (3, 515)):
+    # the last two exceed the LDS and run on a device workspace
+    for s, n in ((1, 37), (2, 100), (2, 1031), (3, 515), (2, 2048), (3, 1300)):
         ax = Axis(n, 0.0, 1.0, s=s, p=min(s, 2), a=12.0, ng=5)
         bw = 2 * s + 1
         Mb, Kb = ax.banded(ax.M), ax.banded(ax.K)
@@ -67,7 +68,7 @@ def test_band_solve_kernel(ctd):
             assert rel(xh[k], ref) < 1e-12
 
 
-@pytest.mark.parametrize("dim,n,m0,steps", [(2, 37, 3, 3), (3, 21, 3, 2)])
+@pytest.mark.parametrize("dim,n,m0,steps", [(2, 37, 3, 3), (3, 21, 3, 2), (2, (1500, 24), 3, 2)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_step_replay_parity(ctd, dim, n, m0, steps, prec):
     inst = small_instance(dim=dim, n=n, m0=m0, kmax=4, eps=0.05, dt=1e-3, max_modes=24)
