@@ -157,20 +157,34 @@ const char* ctd_last_error(const ctd_solver* s);
 
 void ctd_destroy(ctd_solver* s);   /* NULL-safe; synchronises the stream */
 
+/* Device bytes an instance of this problem with m0 initial modes holds
+ * (the allocation ctd_init makes; host tables and pinned scalars excluded).
+ * Used for admission by HBM footprint.  Works without a device (then the
+ * LDS limit is taken as 64 KiB, which can only over-estimate). */
+int ctd_footprint_bytes(const ctd_problem* p, int32_t m0, uint64_t* bytes);
+
 /* ---------------------------------------------------------------------- *
- * Batched execution: many independent instances stepped together, their
- * launches fused per phase (one grid covers every instance's work items).
+ * Batched execution (many independent, uneven instances; the batched
+ * workload of the paper's comparisons is its own).  The instances advance
+ * concurrently: a pool of worker threads, each with its own non-blocking
+ * HIP stream, takes instances longest-first (cost ~ sweeps x directions x
+ * per-sweep work, from the shape and mode cap) so that the GPU runs several
+ * instances' kernels at once.  Each instance's arithmetic is that of a
+ * single ctd_solver: a result does not depend on the batch around it.
  * ---------------------------------------------------------------------- */
 typedef struct ctd_batch ctd_batch;
 
 /* problems[i], m0[i], inits[i] (dim pointers), amps[i] (or NULL) as in
- * ctd_init.  All instances share the stream. */
+ * ctd_init.  Instances are set up on hip_stream; stepping uses the pool. */
 int ctd_batch_create(int32_t count, const ctd_problem* problems,
                      const int32_t* m0, const double* const* const* inits,
                      const double* const* amps, void* hip_stream,
                      ctd_batch** out);
+/* Worker threads (and streams) of the pool, 1..64; default 8. */
+int ctd_batch_set_workers(ctd_batch* b, int32_t workers);
 /* Advance every instance nsteps steps; info: count * nsteps entries
- * (instance-major) or NULL. */
+ * (instance-major) or NULL.  Returns when all are done (or on the first
+ * error, after the running instances reach a step boundary). */
 int ctd_batch_step(ctd_batch* b, int32_t nsteps, ctd_step_info* info);
 int ctd_batch_get_modes(ctd_batch* b, int32_t i, int32_t* m, double* amp,
                         double* const* out, int32_t cap);
@@ -178,6 +192,61 @@ int ctd_batch_reconstruct(ctd_batch* b, int32_t i, void* out, int32_t dtype,
                           int32_t on_device);
 const char* ctd_batch_last_error(const ctd_batch* b);
 void ctd_batch_destroy(ctd_batch* b);
+
+/* ---------------------------------------------------------------------- *
+ * Served execution with continuous batching.  Requests (a problem, its
+ * initial modes and a step count) are queued in arrival order; worker
+ * threads, each with its own non-blocking HIP stream, admit the oldest
+ * request as soon as a worker is idle and the summed device footprint of
+ * the admitted-but-unfetched requests plus its own stays within the HBM
+ * budget, so requests that arrive while others run are started as slots and
+ * memory free up and their work overlaps on the device.  Results (the
+ * modes) stay device-resident until fetched.  A request's arithmetic is that
+ * of a single ctd_solver on its own stream: the same alone and in any mix.
+ * ---------------------------------------------------------------------- */
+typedef struct ctd_server ctd_server;
+
+enum { CTD_REQ_QUEUED = 0, CTD_REQ_RUNNING = 1, CTD_REQ_DONE = 2, CTD_REQ_FAILED = 3 };
+
+typedef struct {
+  int32_t state;           /* CTD_REQ_*                                        */
+  int32_t steps_done;
+  int32_t modes;           /* modes of the current field                        */
+  int32_t error;           /* CTD_* code when FAILED                            */
+  double t_submit_ms;      /* times on the server's monotonic clock, ms since    */
+  double t_start_ms;       /* ctd_server_create; 0 when not reached yet          */
+  double t_done_ms;
+  uint64_t footprint;      /* admitted device bytes                             */
+} ctd_request_status;
+
+typedef struct {
+  int64_t submitted, completed, failed, queued, running;
+  uint64_t bytes_in_use, budget;
+  int64_t steps_done;
+  double busy_ms;          /* wall time with at least one request running        */
+} ctd_server_stats;
+
+/* budget_bytes: device bytes the admitted requests may hold (0: 80% of the
+ * free device memory); workers: 1..64 concurrent requests. */
+int ctd_server_create(uint64_t budget_bytes, int32_t workers, ctd_server** out);
+/* Copies the problem and the initial modes (host, as in ctd_init).  A
+ * request larger than the whole budget fails at once (CTD_ENOMEM). */
+int ctd_server_submit(ctd_server* srv, const ctd_problem* p, int32_t m0,
+                      const double* const* init, const double* amp,
+                      int32_t nsteps, int64_t* ticket);
+int ctd_server_status(ctd_server* srv, int64_t ticket, ctd_request_status* st);
+/* Block until the request is DONE or FAILED, or timeout_ms passes
+ * (< 0: no limit); CTD_EAGAIN on timeout. */
+int ctd_server_wait(ctd_server* srv, int64_t ticket, double timeout_ms);
+/* Modes of a DONE request (host buffers as in ctd_get_modes, cap >= modes);
+ * release != 0 frees its device memory and forgets the ticket. */
+int ctd_server_fetch(ctd_server* srv, int64_t ticket, int32_t* m, double* amp,
+                     double* const* out, int32_t cap, int32_t release);
+int ctd_server_get_stats(ctd_server* srv, ctd_server_stats* st);
+const char* ctd_server_last_error(const ctd_server* srv);   /* never NULL */
+/* Stops admitting, lets running requests finish their current step, frees
+ * everything.  NULL-safe. */
+void ctd_server_destroy(ctd_server* srv);
 
 /* ---------------------------------------------------------------------- *
  * Low-level kernel entry points on caller device memory (tests, tuning).

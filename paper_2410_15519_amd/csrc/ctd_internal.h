@@ -147,4 +147,8 @@ hipError_t configure_kernels();
 int max_lds_bytes();
 int num_cus();
 
+// Instance plumbing for the executors (batch, server).
+void solver_bind_stream(ctd_solver* s, hipStream_t st);   // between ctd_step calls
+size_t solver_device_bytes(const ctd_solver* s);
+
 }  // namespace ctd

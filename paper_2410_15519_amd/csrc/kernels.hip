@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 namespace ctd {
 
@@ -1572,7 +1573,9 @@ static int g_num_cus = 256;
 // Kernels whose dynamic LDS can exceed 64 KiB (the banded solve stages the
 // whole band; the FP64 cubic h kernel stages a 64 x Mkp tile plus an S tile).
 hipError_t configure_kernels() {
+  static std::mutex mu;
   static bool done = false;
+  std::lock_guard<std::mutex> lock(mu);
   if (done) return hipSuccess;
   int dev = 0, lds = 0;
   hipError_t e = hipGetDevice(&dev);

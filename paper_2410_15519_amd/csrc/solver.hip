@@ -24,21 +24,34 @@ namespace {
 
 thread_local std::string g_init_error = "no error";
 
+// Device memory of one instance.  Buffers are cleared on the instance's
+// stream; in the dry mode only the byte count is kept (footprint queries).
 struct DeviceArena {
   std::vector<void*> ptrs;
   size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  bool dry = false;
   hipError_t alloc(void** p, size_t n) {
     if (n == 0) n = 8;
-    hipError_t e = hipMalloc(p, n);
+    n = (n + 255) / 256 * 256;
+    if (dry) {
+      *p = nullptr;
+      bytes += n;
+      return hipSuccess;
+    }
+    // stream-ordered: no device-wide synchronisation when other instances'
+    // work is in flight on other streams
+    hipError_t e = hipMallocAsync(p, n, stream);
     if (e == hipSuccess) {
       ptrs.push_back(*p);
       bytes += n;
-      e = hipMemset(*p, 0, n);
+      e = hipMemsetAsync(*p, 0, n, stream);
     }
     return e;
   }
   void release() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
+    if (!ptrs.empty()) (void)hipStreamSynchronize(stream);
     ptrs.clear();
   }
 };
@@ -158,6 +171,15 @@ hipError_t sync_collect(ctd_solver* s) {
   return e;
 }
 
+// Copy ordered on the instance's stream, complete on return (host buffers
+// may be pageable temporaries).
+hipError_t copy_sync(ctd_solver* s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
+  if (s->arena.dry || bytes == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  return e;
+}
+
 // Algorithmic work of each launch (minimal operation counts from shapes).
 struct Work { double flops, bytes; };
 double tsz(const ctd_solver* s) { return s->I.mixed ? 4.0 : 8.0; }
@@ -255,6 +277,32 @@ void update_view(ctd_solver* s) {
   }
 }
 
+// Coefficients, defaults and the host CFE tables of every axis.
+int setup_host(ctd_solver* s, const ctd_problem* p, void* hip_stream, std::string& err) {
+  s->P = *p;
+  if (s->P.dilation_a == 0.0) s->P.dilation_a = 12.0;
+  if (s->P.gauss_points == 0) s->P.gauss_points = 5;
+  if (s->P.fp_tol == 0.0) s->P.fp_tol = 1e-2;
+  if (s->P.fp_max_iter == 0) s->P.fp_max_iter = 20;
+  s->dim = p->dim;
+  if (std::isfinite(p->L)) {
+    s->L = p->L; s->kappa = p->kappa; s->a0 = p->a0; s->alpha = p->alpha;
+  } else {
+    s->L = 1.0; s->kappa = p->eps * p->eps; s->a0 = 0.25; s->alpha = p->S;
+  }
+  s->c = 1.0 / p->dt + s->alpha * s->L;
+  s->lam = s->L * s->kappa;
+  s->omega = 4.0 * s->a0 * s->L;
+  s->stream = (hipStream_t)hip_stream;
+  s->arena.stream = s->stream;
+  for (int d = 0; d < s->dim; ++d) {
+    int rc = build_axis(p->nodes[d], p->lo[d], p->hi[d], p->patch_s, p->poly_p,
+                        s->P.dilation_a, s->P.gauss_points, s->ax[d], err);
+    if (rc) return rc;
+  }
+  return CTD_OK;
+}
+
 int alloc_instance(ctd_solver* s, int m0) {
   DeviceArena& A = s->arena;
   DevInst& I = s->I;
@@ -263,7 +311,13 @@ int alloc_instance(ctd_solver* s, int m0) {
   s->Mkp_max = std::max(kTile, round_up(s->Mcap, kTile));
   const int nbmax = s->Mkp_max / kTile;
   s->ntri_max = tri_count(nbmax);
-  s->nsplit_g_cap = 1024 + s->ntri_max;
+  {
+    // split-K partial tiles of g: at most ~1024 workgroups, and no more
+    // splits than 64-point chunks on the shortest axis
+    int nqmin = 1 << 30;
+    for (int d = 0; d < s->dim; ++d) nqmin = std::min(nqmin, s->ax[d].nq);
+    s->nsplit_g_cap = std::min(1024 + s->ntri_max, s->ntri_max * ((nqmin + 63) / 64));
+  }
   const size_t Tsz = mixed ? sizeof(float) : sizeof(double);
   I.dim = s->dim;
   I.Mcap = s->Mcap;
@@ -311,17 +365,17 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.gmk, sizeof(double) * M);
     if (s->dim == 3) AL(X.g, Tsz * (size_t)s->ntri_max * kTileSq * kTile);
     std::vector<float> pf(T.phi.begin(), T.phi.end());
-    HIPCHK(s, hipMemcpy(X.phi, T.phi.data(), sizeof(double) * nq * T.SW, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(X.phif, pf.data(), sizeof(float) * nq * T.SW, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(X.w, T.w.data(), sizeof(double) * nq, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(X.Mb, T.Mb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
-    HIPCHK(s, hipMemcpy(X.Kb, T.Kb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, X.phi, T.phi.data(), sizeof(double) * nq * T.SW, hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, X.phif, pf.data(), sizeof(float) * nq * T.SW, hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, X.w, T.w.data(), sizeof(double) * nq, hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, X.Mb, T.Mb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, X.Kb, T.Kb.data(), sizeof(double) * (T.B + 1) * n, hipMemcpyHostToDevice));
   }
   if (s->dim == 3) {
     std::vector<int4> tri = make_triples(nbmax);
     int4* td;
     AL(td, sizeof(int4) * tri.size());
-    HIPCHK(s, hipMemcpy(td, tri.data(), sizeof(int4) * tri.size(), hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, td, tri.data(), sizeof(int4) * tri.size(), hipMemcpyHostToDevice));
     I.tri = td;
     AL(I.gpart, Tsz * (size_t)s->nsplit_g_cap * kTileSq * kTile);
     AL(I.S, Tsz * (size_t)s->ntri_max * kTileSq * kTile);
@@ -346,7 +400,7 @@ int alloc_instance(ctd_solver* s, int m0) {
       if (!bcr_fits(s->ax[d].n, s->ax[d].B)) ws = std::max(ws, bcr_lds_bytes(s->ax[d].n, s->ax[d].B));
     if (ws) HIPCHK(s, A.alloc((void**)&I.bcr_ws, ws));
   }
-  HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  if (!A.dry) HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
   return CTD_OK;
 }
 
@@ -605,26 +659,8 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
     if (!init[d]) { g_init_error = "init factor pointer is NULL"; return CTD_EINVAL; }
   ctd_solver* s = new (std::nothrow) ctd_solver();
   if (!s) { g_init_error = "out of host memory"; return CTD_ENOMEM; }
-  s->P = *p;
-  if (s->P.dilation_a == 0.0) s->P.dilation_a = 12.0;
-  if (s->P.gauss_points == 0) s->P.gauss_points = 5;
-  if (s->P.fp_tol == 0.0) s->P.fp_tol = 1e-2;
-  if (s->P.fp_max_iter == 0) s->P.fp_max_iter = 20;
-  s->dim = p->dim;
-  if (std::isfinite(p->L)) {
-    s->L = p->L; s->kappa = p->kappa; s->a0 = p->a0; s->alpha = p->alpha;
-  } else {
-    s->L = 1.0; s->kappa = p->eps * p->eps; s->a0 = 0.25; s->alpha = p->S;
-  }
-  s->c = 1.0 / p->dt + s->alpha * s->L;
-  s->lam = s->L * s->kappa;
-  s->omega = 4.0 * s->a0 * s->L;
-  s->stream = (hipStream_t)hip_stream;
-  for (int d = 0; d < s->dim; ++d) {
-    rc = build_axis(p->nodes[d], p->lo[d], p->hi[d], p->patch_s, p->poly_p,
-                    s->P.dilation_a, s->P.gauss_points, s->ax[d], err);
-    if (rc) { g_init_error = err; delete s; return rc; }
-  }
+  rc = setup_host(s, p, hip_stream, err);
+  if (rc) { g_init_error = err; delete s; return rc; }
   rc = alloc_instance(s, m0);
   if (rc) { g_init_error = s->err; s->arena.release(); if (s->sc_host) (void)hipHostFree(s->sc_host); delete s; return rc; }
   // initial modes: fold amplitude signs into axis 0, |amp| into sk
@@ -638,7 +674,7 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
         double a = amp ? amp[m] : 1.0;
         if (a < 0) for (size_t i = 0; i < n; ++i) buf[(size_t)m * n + i] = -buf[(size_t)m * n + i];
       }
-    hipError_t e = hipMemcpy(s->I.ax[d].Xk, buf.data(), sizeof(double) * n * m0, hipMemcpyHostToDevice);
+    hipError_t e = copy_sync(s, s->I.ax[d].Xk, buf.data(), sizeof(double) * n * m0, hipMemcpyHostToDevice);
     if (e != hipSuccess) { g_init_error = hipGetErrorString(e); ctd_destroy(s); return CTD_EDEVICE; }
   }
   for (int m = 0; m < m0; ++m) {
@@ -646,7 +682,7 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
     if (!std::isfinite(a)) { g_init_error = "non-finite amplitude"; ctd_destroy(s); return CTD_EINVAL; }
     sk[m] = std::fabs(a);
   }
-  hipError_t e = hipMemcpy(s->I.sk, sk.data(), sizeof(double) * m0, hipMemcpyHostToDevice);
+  hipError_t e = copy_sync(s, s->I.sk, sk.data(), sizeof(double) * m0, hipMemcpyHostToDevice);
   if (e != hipSuccess) { g_init_error = hipGetErrorString(e); ctd_destroy(s); return CTD_EDEVICE; }
   s->Mk = m0;
   for (int d = 0; d < s->dim; ++d) {
@@ -705,13 +741,13 @@ int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device) 
   void* dst = out;
   void* tmp = nullptr;
   if (!on_device) {
-    HIPCHK(s, hipMalloc(&tmp, bytes));
+    HIPCHK(s, hipMallocAsync(&tmp, bytes, s->stream));
     dst = tmp;
   }
   hipError_t e = launch_reconstruct(V, s->Mk, dst, dtype, s->stream);
   if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+  if (tmp) (void)hipFreeAsync(tmp, s->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return s->hip_fail(e, "reconstruct");
   return CTD_OK;
 }
@@ -721,11 +757,11 @@ int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out, in
   *m = s->Mk;
   if (cap < s->Mk) return (amp || out) ? s->fail(CTD_EINVAL, "cap smaller than mode count") : CTD_OK;
   HIPCHK(s, sync_collect(s));
-  if (amp) HIPCHK(s, hipMemcpy(amp, s->I.sk, sizeof(double) * s->Mk, hipMemcpyDeviceToHost));
+  if (amp) HIPCHK(s, copy_sync(s, amp, s->I.sk, sizeof(double) * s->Mk, hipMemcpyDeviceToHost));
   if (out)
     for (int d = 0; d < s->dim; ++d)
       if (out[d])
-        HIPCHK(s, hipMemcpy(out[d], s->I.ax[d].Xk, sizeof(double) * s->ax[d].n * s->Mk, hipMemcpyDeviceToHost));
+        HIPCHK(s, copy_sync(s, out[d], s->I.ax[d].Xk, sizeof(double) * s->ax[d].n * s->Mk, hipMemcpyDeviceToHost));
   return CTD_OK;
 }
 
@@ -781,6 +817,33 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb, const double*
 }
 
 }  // extern "C"
+
+extern "C" int ctd_footprint_bytes(const ctd_problem* p, int32_t m0, uint64_t* bytes) {
+  if (!bytes) return CTD_EINVAL;
+  *bytes = 0;
+  std::string err;
+  int rc = validate(p, err);
+  if (rc) return rc;
+  if (m0 < 1) return CTD_EINVAL;
+  (void)configure_kernels();   // without a device the LDS limit stays conservative
+  (void)hipGetLastError();
+  ctd_solver tmp;
+  rc = setup_host(&tmp, p, nullptr, err);
+  if (rc) return rc;
+  tmp.arena.dry = true;
+  rc = alloc_instance(&tmp, m0);
+  if (rc) return rc;
+  *bytes = tmp.arena.bytes;
+  return CTD_OK;
+}
+
+namespace ctd {
+void solver_bind_stream(ctd_solver* s, hipStream_t st) {
+  s->stream = st;
+  s->arena.stream = st;
+}
+size_t solver_device_bytes(const ctd_solver* s) { return s->arena.bytes; }
+}  // namespace ctd
 
 extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u, double* out) {
   if (!s || !u || !out || d < 0 || d >= s->dim) return CTD_EINVAL;

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libctd.so")
 
 CTD_OK = 0
+CTD_EAGAIN = -7
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENONFINITE",
           -5: "ESTATE", -6: "EUNSUPPORTED", -7: "EAGAIN"}
 PREC = {"fp64": 0, "mixed": 1}
@@ -61,6 +62,29 @@ class StepInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+REQ_STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
+class RequestStatus(C.Structure):
+    _fields_ = [("state", C.c_int32), ("steps_done", C.c_int32), ("modes", C.c_int32),
+                ("error", C.c_int32), ("t_submit_ms", C.c_double), ("t_start_ms", C.c_double),
+                ("t_done_ms", C.c_double), ("footprint", C.c_uint64)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["state"] = REQ_STATE.get(self.state, self.state)
+        return d
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int64), ("running", C.c_int64), ("bytes_in_use", C.c_uint64),
+                ("budget", C.c_uint64), ("steps_done", C.c_int64), ("busy_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
@@ -83,7 +107,19 @@ def _load():
         "ctd_destroy": (None, [vp]),
         "ctd_batch_create": (C.c_int, [C.c_int32, P(Problem), P(C.c_int32), P(P(P(C.c_double))),
                                        P(P(C.c_double)), vp, P(vp)]),
+        "ctd_batch_set_workers": (C.c_int, [vp, C.c_int32]),
         "ctd_batch_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
+        "ctd_footprint_bytes": (C.c_int, [P(Problem), C.c_int32, P(C.c_uint64)]),
+        "ctd_server_create": (C.c_int, [C.c_uint64, C.c_int32, P(vp)]),
+        "ctd_server_submit": (C.c_int, [vp, P(Problem), C.c_int32, P(P(C.c_double)), P(C.c_double),
+                                        C.c_int32, P(C.c_int64)]),
+        "ctd_server_status": (C.c_int, [vp, C.c_int64, P(RequestStatus)]),
+        "ctd_server_wait": (C.c_int, [vp, C.c_int64, C.c_double]),
+        "ctd_server_fetch": (C.c_int, [vp, C.c_int64, P(C.c_int32), P(C.c_double), P(P(C.c_double)),
+                                       C.c_int32, C.c_int32]),
+        "ctd_server_get_stats": (C.c_int, [vp, P(ServerStats)]),
+        "ctd_server_last_error": (C.c_char_p, [vp]),
+        "ctd_server_destroy": (None, [vp]),
         "ctd_batch_get_modes": (C.c_int, [vp, C.c_int32, P(C.c_int32), P(C.c_double),
                                           P(P(C.c_double)), C.c_int32]),
         "ctd_batch_reconstruct": (C.c_int, [vp, C.c_int32, vp, C.c_int32, C.c_int32]),
@@ -313,6 +349,24 @@ class Batch:
             raise CtdError(rc, LIB.ctd_batch_last_error(None).decode())
         self.h = h
 
+    def set_workers(self, workers):
+        rc = LIB.ctd_batch_set_workers(self.h, int(workers))
+        if rc != CTD_OK:
+            raise CtdError(rc, "ctd_batch_set_workers")
+
+    def modes(self, i):
+        m = C.c_int32()
+        rc = LIB.ctd_batch_get_modes(self.h, i, C.byref(m), None, None, 0)
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
+        inst = self.insts[i]
+        amp, outs, ptrs = _mode_buffers(inst.nodes[: inst.dim], m.value)
+        rc = LIB.ctd_batch_get_modes(self.h, i, C.byref(m), amp.ctypes.data_as(C.POINTER(C.c_double)),
+                                     ptrs, m.value)
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
+        return amp, outs
+
     def step(self, nsteps=1):
         n = len(self.insts)
         info = (StepInfo * max(n * nsteps, 1))()
@@ -339,6 +393,97 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _mode_buffers(nodes, M):
+    amp = np.empty(M)
+    outs = [np.empty((int(n), M), order="F") for n in nodes]
+    ptrs = (C.POINTER(C.c_double) * 3)()
+    for d, a in enumerate(outs):
+        ptrs[d] = a.ctypes.data_as(C.POINTER(C.c_double))
+    return amp, outs, ptrs
+
+
+def footprint_bytes(inst, m0=None, **kw):
+    """Device bytes ctd_init allocates for this instance (ctd_footprint_bytes)."""
+    p = make_problem(inst, **kw)
+    b = C.c_uint64()
+    rc = LIB.ctd_footprint_bytes(C.byref(p), int(len(inst.amp) if m0 is None else m0), C.byref(b))
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_footprint_bytes")
+    return b.value
+
+
+class Server:
+    """Served execution with continuous batching (ctd_server_*)."""
+
+    def __init__(self, budget_bytes=0, workers=8):
+        h = C.c_void_p()
+        rc = LIB.ctd_server_create(int(budget_bytes), int(workers), C.byref(h))
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_server_last_error(None).decode())
+        self.h = h
+        self._nodes = {}
+
+    def _check(self, rc):
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_server_last_error(self.h).decode())
+
+    def submit(self, inst, nsteps=None, **kw):
+        p = make_problem(inst, **kw)
+        arrs, ptrs = _factor_ptrs(inst.factors)
+        amp = np.ascontiguousarray(inst.amp, dtype=np.float64)
+        t = C.c_int64()
+        self._check(LIB.ctd_server_submit(self.h, C.byref(p), len(amp), ptrs,
+                                          amp.ctypes.data_as(C.POINTER(C.c_double)),
+                                          int(inst.steps if nsteps is None else nsteps), C.byref(t)))
+        self._nodes[t.value] = tuple(int(n) for n in inst.nodes[: inst.dim])
+        return t.value
+
+    def status(self, ticket):
+        st = RequestStatus()
+        self._check(LIB.ctd_server_status(self.h, ticket, C.byref(st)))
+        return st.as_dict()
+
+    def wait(self, ticket, timeout_ms=-1.0):
+        rc = LIB.ctd_server_wait(self.h, ticket, float(timeout_ms))
+        if rc == CTD_EAGAIN:
+            return False
+        self._check(rc)
+        return True
+
+    def fetch(self, ticket, release=True):
+        m = C.c_int32()
+        self._check(LIB.ctd_server_fetch(self.h, ticket, C.byref(m), None, None, 0, 0))
+        amp, outs, ptrs = _mode_buffers(self._nodes[ticket], m.value)
+        self._check(LIB.ctd_server_fetch(self.h, ticket, C.byref(m),
+                                         amp.ctypes.data_as(C.POINTER(C.c_double)), ptrs, m.value,
+                                         1 if release else 0))
+        if release:
+            self._nodes.pop(ticket, None)
+        return amp, outs
+
+    def stats(self):
+        st = ServerStats()
+        self._check(LIB.ctd_server_get_stats(self.h, C.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.ctd_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def band_solve(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):

@@ -47,3 +47,32 @@ def test_binding_struct_layout_and_validation():
     bad = ctd.make_problem(patch_s=1, poly_p=2)
     rc = ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h))
     assert rc == -1
+
+
+def test_footprint_query_without_device():
+    """ctd_footprint_bytes sizes an instance from its shape alone (no GPU needed)."""
+    from paper_2410_15519_amd import ctd
+    from workloads import small_instance
+    f = lambda inst, **kw: ctd.footprint_bytes(inst, **kw)
+    small, big = small_instance(2, 24), small_instance(2, 200)
+    assert 0 < f(small) < f(big)
+    assert f(small, max_modes=8) < f(small, max_modes=32)
+    three = small_instance(3, 21, max_modes=16)
+    # 3D adds the tile-triple Grams; FP32 tables halve those
+    assert f(three, precision="mixed") < f(three, precision="fp64")
+    # every buffer is rounded to 256 bytes
+    assert f(small) % 256 == 0
+    bad = ctd.make_problem(dim=4)
+    b = ctypes.c_uint64()
+    assert ctd.LIB.ctd_footprint_bytes(ctypes.byref(bad), 1, ctypes.byref(b)) == -1
+    assert ctd.LIB.ctd_footprint_bytes(ctypes.byref(ctd.make_problem()), 0, ctypes.byref(b)) == -1
+
+
+def test_server_and_batch_argument_checks():
+    from paper_2410_15519_amd import ctd
+    h = ctypes.c_void_p()
+    assert ctd.LIB.ctd_server_create(0, 0, ctypes.byref(h)) == -1 and not h.value
+    assert ctd.LIB.ctd_server_create(0, 65, ctypes.byref(h)) == -1 and not h.value
+    assert ctd.LIB.ctd_batch_set_workers(None, 4) == -1
+    ctd.LIB.ctd_server_destroy(None)
+    assert ctd.LIB.ctd_server_last_error(None)

@@ -1,0 +1,112 @@
+"""Batched and served execution on the GPU: concurrency must not change results.
+
+Each instance's arithmetic is that of one ctd_solver on one stream, so a
+result is compared bitwise: standalone vs inside a concurrent batch, and a
+served request alone vs in a mix of other requests.  One standalone result
+is also pinned to the oracle by the replay parity tests; here the
+standalone solver is the reference.
+"""
+import numpy as np
+import pytest
+
+from workloads import small_instance, make_batch, make_requests
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_15519_amd import ctd as mod
+    return mod
+
+
+def standalone(ctd, inst, steps, **kw):
+    with ctd.Solver(inst, **kw) as s:
+        s.step(steps)
+        return s.modes()
+
+
+def same_modes(a, b):
+    (amp_a, fa), (amp_b, fb) = a, b
+    return (amp_a.shape == amp_b.shape and np.array_equal(amp_a, amp_b)
+            and all(np.array_equal(x, y) for x, y in zip(fa, fb)))
+
+
+def uneven_2d(count, seed=11):
+    # the batched workload's generator, sizes capped so the test stays short
+    return make_batch(seed=seed, count=count, nodes_range=(24, 160), max_modes=12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batch_concurrent_equals_standalone(ctd, prec):
+    insts = uneven_2d(6)
+    print(f"batch sizes {[i.nodes[0] for i in insts]} prec={prec}", flush=True)
+    b = ctd.Batch(insts, precision=prec)
+    try:
+        b.set_workers(4)
+        b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        assert same_modes(got[i], standalone(ctd, inst, 2, precision=prec)), f"instance {i}"
+
+
+def test_served_alone_equals_mix(ctd):
+    target = small_instance(dim=2, n=40, m0=3, kmax=4, seed=5, max_modes=12)
+    target3 = small_instance(dim=3, n=17, m0=3, kmax=4, seed=6, max_modes=8)
+    others = [inst for _, inst in make_requests(seed=3, count=8, nodes2d_range=(24, 96),
+                                                nodes3d_range=(12, 20), steps_range=(1, 3),
+                                                max_modes=10)]
+    ref = standalone(ctd, target, 3, precision="mixed")
+    ref3 = standalone(ctd, target3, 2, precision="mixed")
+    with ctd.Server(workers=1) as srv:
+        t = srv.submit(target, nsteps=3, precision="mixed")
+        assert srv.wait(t, 60000)
+        alone = srv.fetch(t)
+    assert same_modes(alone, ref)
+    with ctd.Server(workers=4) as srv:
+        tickets = [srv.submit(o, precision="mixed") for o in others[:4]]
+        t = srv.submit(target, nsteps=3, precision="mixed")
+        t3 = srv.submit(target3, nsteps=2, precision="mixed")
+        tickets += [srv.submit(o, precision="mixed") for o in others[4:]]
+        for k in tickets + [t, t3]:
+            assert srv.wait(k, 120000)
+        mixed = srv.fetch(t)
+        mixed3 = srv.fetch(t3)
+        st = [srv.status(k) for k in tickets]
+        assert all(s["state"] == "done" for s in st)
+        assert all(s["t_done_ms"] >= s["t_start_ms"] >= s["t_submit_ms"] for s in st)
+        for k in tickets:
+            srv.fetch(k)
+        stats = srv.stats()
+        assert stats["completed"] == len(tickets) + 2 and stats["failed"] == 0
+        assert stats["bytes_in_use"] == 0
+    assert same_modes(mixed, ref)
+    assert same_modes(mixed3, ref3)
+
+
+def test_server_admits_by_footprint(ctd):
+    a = small_instance(dim=2, n=48, m0=3, kmax=4, seed=8, max_modes=8)
+    b = small_instance(dim=2, n=48, m0=3, kmax=4, seed=9, max_modes=8)
+    fa = ctd.footprint_bytes(a)
+    fb = ctd.footprint_bytes(b)
+    assert fa == fb > 0
+    with ctd.Server(budget_bytes=fa + fb // 2, workers=2) as srv:
+        ta = srv.submit(a, nsteps=1)
+        tb = srv.submit(b, nsteps=1)
+        assert srv.wait(ta, 60000)
+        # a is done but holds its memory until fetched: b cannot be admitted
+        assert not srv.wait(tb, 300)
+        assert srv.status(tb)["state"] == "queued"
+        assert srv.stats()["bytes_in_use"] == fa
+        srv.fetch(ta)
+        assert srv.wait(tb, 60000)
+        assert srv.status(tb)["footprint"] == fb
+        srv.fetch(tb)
+    with ctd.Server(budget_bytes=fa // 2, workers=1) as srv:
+        with pytest.raises(ctd.CtdError):
+            srv.submit(a, nsteps=1)
