@@ -18,8 +18,17 @@ Legs (rank 0, one GPU):
      its decisions; (c) for scale, FP64 against FP64 started from u0 with
      amplitudes perturbed by 1e-14 (same decisions): the capped greedy
      decomposition amplifies any difference from step to step.
+     (d) the same for a single step: FP64 from the FP64 u^k with amplitudes
+     perturbed by 1e-14, same decisions.
   4. CPU baseline: the oracle (numpy/scipy FP64) timed on a bounded sample of
      the same workload on the host cores.
+  5. batched sample: uneven 2D instances from the batched workload's generator
+     stepped concurrently by ctd_batch_step (worker streams), against one
+     worker; reported as instance-steps/s.
+  6. served sample: a Poisson request stream from the served workload's
+     generator (request count and step counts scaled down, sizes and rate as
+     generated) through ctd_server_*; p50/p99 latency from arrival to
+     completion and aggregate steps/s.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -34,6 +43,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
+# HBM traffic per launch measured with rocprofv3 counters on this workload
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ctd_step_ac3d_n1024_mixed_hbm_traffic.md")
+# kernel [grid work-items] of each class at the timed shape (M_k = 128)
+KERNEL_NAMES = {"cubic_g": "k_cubic_g<float> [276480]", "cubic_h": "k_cubic_h32 [245760]",
+                "solve": "k_solve_bcr<5, false> [576]", "cubic_gred": "k_cubic_gred<float> [491520]"}
 
 
 def log(*a):
@@ -69,22 +83,31 @@ def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True):
     return s, infos, t1 - t0, prof, dec
 
 
-def roofline_of(prof, precision):
+def traffic_of(name, precision, workload):
+    if workload != "ac3d_n1024" or precision != "mixed":
+        return None
+    from paper_2410_15519_amd.profsum import traffic_from_summary
+    k = KERNEL_NAMES.get(name)
+    return traffic_from_summary(TRAFFIC_SUMMARY, k) if k else None
+
+
+def roofline_of(prof, precision, workload="ac3d_n1024"):
     # dominant kernel = largest summed device time
     name, v = max(prof.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = v["ms"] / v["launches"]
+    traffic = traffic_of(name, precision, workload)
     if name in ("cubic_g", "cubic_h", "energy", "mxy_build"):
         peak = PEAK["fp32_mfma"] if (precision == "mixed" and name != "energy") else PEAK["fp64_mfma"]
         per_launch = v["flops"] / v["launches"]
         achieved = per_launch / (avg_ms * 1e-3)
         return name, {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                       "kernel": name, "avg_launch_us": avg_ms * 1e3,
                       "algorithmic_per_launch": per_launch}
     per_launch = v["bytes"] / v["launches"]
     achieved = per_launch / (avg_ms * 1e-3)
     return name, {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm"] / 1e9,
-                  "unit": "GB/s", "frac": achieved / PEAK["hbm"], "traffic": None,
+                  "unit": "GB/s", "frac": achieved / PEAK["hbm"], "traffic": traffic,
                   "kernel": name, "avg_launch_us": avg_ms * 1e3,
                   "algorithmic_per_launch": per_launch}
 
@@ -132,6 +155,64 @@ def cpu_baseline(inst, sweeps_per_step, budget_s=20.0):
                        f"{sweeps_per_step:.0f} sweeps x {inst.dim} directions per step measured on the GPU")}
 
 
+def batched_leg(ctd, count=24, steps=2, workers=8):
+    """Instance-steps/s of a concurrent batch (and of the same batch on one worker)."""
+    import torch
+    from workloads import make_batch
+    insts = make_batch(count=count)
+    out = {"instances": count, "steps": steps,
+           "nodes": sorted(int(i.nodes[0]) for i in insts)}
+    for w in (1, workers):
+        b = ctd.Batch(insts, precision="mixed")
+        b.set_workers(w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        b.close()
+        out[f"instance_steps_per_s_w{w}"] = count * steps / el
+        log(f"  [batched] {count} instances x {steps} steps, {w} workers: {el:.2f} s")
+    return out
+
+
+def served_leg(ctd, count=32, step_scale=20, workers=8):
+    """Poisson arrivals into the server; latency from arrival to completion."""
+    import numpy as np
+    from workloads import make_requests, CONFIGS
+    cfg = CONFIGS["serve_mix"]
+    lo, hi = cfg["steps_range"]
+    reqs = make_requests(count=count, steps_range=(max(1, lo // step_scale), max(1, hi // step_scale)))
+    srv = ctd.Server(workers=workers)
+    t0 = time.perf_counter()
+    tickets = []
+    for t_arr, inst in reqs:
+        dt = t_arr - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append((srv.submit(inst, precision="mixed"), inst))
+    for t, _ in tickets:
+        srv.wait(t)
+    st = [srv.status(t) for t, _ in tickets]
+    stats = srv.stats()
+    for t, _ in tickets:
+        srv.fetch(t)
+    srv.close()
+    lat = np.array([s["t_done_ms"] - s["t_submit_ms"] for s in st])
+    steps = sum(s["steps_done"] for s in st)
+    span = max(s["t_done_ms"] for s in st) - min(s["t_submit_ms"] for s in st)
+    log(f"  [served] {count} requests, {steps} steps in {span / 1e3:.2f} s; "
+        f"p50 {np.percentile(lat, 50):.0f} ms p99 {np.percentile(lat, 99):.0f} ms")
+    return {"requests": count, "workers": workers, "rate_per_s": cfg["rate"],
+            "steps_range": [max(1, lo // step_scale), max(1, hi // step_scale)],
+            "p3d": cfg["p3d"], "steps_total": int(steps),
+            "latency_ms_p50": float(np.percentile(lat, 50)),
+            "latency_ms_p99": float(np.percentile(lat, 99)),
+            "steps_per_s": steps / (span / 1e3), "busy_ms": stats["busy_ms"],
+            "sample": (f"{count} requests of the served workload's generator, step counts "
+                       f"divided by {step_scale}")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,10 +221,13 @@ def main():
     ap.add_argument("--workload", default="ac3d_n1024")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
+                    help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the CTD step of one instance is not sharded "
-              "across GPUs in this build (see DESIGN.md for how it would shard).", file=sys.stderr)
+              "across GPUs; independent instances would run one server per GPU.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -153,6 +237,15 @@ def main():
     from paper_2410_15519_amd import ctd
     from workloads import make_instance
 
+    if args.copy_calibration > 0:
+        nb = int(args.copy_calibration * 2 ** 20) // 16 * 16
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        ctd.kernel_copy(dst, src)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src)
+        del src, dst
+        torch.cuda.empty_cache()
     inst = make_instance(args.workload)
     log(f"workload {args.workload}: dim={inst.dim} nodes={inst.nodes} eps={inst.eps} dt={inst.dt} "
         f"max_modes={inst.max_modes}")
@@ -160,7 +253,7 @@ def main():
     # leg 1: mixed, adaptive (the headline)
     s_mix, infos, elapsed, prof, dec_all = run_leg(ctd, inst, "mixed", args.warmup, args.steps)
     value = args.steps / elapsed
-    dom, roof = roofline_of(prof, "mixed")
+    dom, roof = roofline_of(prof, "mixed", args.workload)
     sweeps_per_step = float(np.mean([i["sweeps"] for i in infos]))
     extra = {"kernels": {k: {"launches": v["launches"], "ms_total": round(v["ms"], 3),
                              "avg_us": round(1e3 * v["ms"] / v["launches"], 2)}
@@ -184,7 +277,7 @@ def main():
         s64.close()
         s64, infos64, el64, prof64, dec64 = run_leg(ctd, inst, "fp64", args.warmup, args.steps)
         fp64 = {"steps_per_s": args.steps / el64,
-                "dominant": roofline_of(prof64, "fp64")[1]}
+                "dominant": roofline_of(prof64, "fp64", args.workload)[1]}
         U64 = torch.empty(n, dtype=torch.float64, device="cuda")
         s64.reconstruct("f64", out=U64)
         s64.close()
@@ -201,6 +294,17 @@ def main():
         one.reconstruct("f64", out=U1)
         one.close()
         fp64["rel_l2_step_mixed_vs_fp64"] = float(torch.linalg.norm(U1 - U64) / torch.linalg.norm(U64))
+        del U1
+        # leg 3d: the same single step in FP64 from u^k with amplitudes perturbed by 1e-14
+        stp = Instance(**{**st.__dict__, "amp": amp_prev * (1.0 + 1e-14)})
+        onep = ctd.Solver(stp, precision="fp64", schedule="replay")
+        onep.step_index = k_prev
+        onep.set_decisions(dec64[-1:])
+        onep.step(1)
+        U1 = torch.empty(n, dtype=torch.float64, device="cuda")
+        onep.reconstruct("f64", out=U1)
+        onep.close()
+        fp64["rel_l2_step_fp64_uk_perturbed_1e-14"] = float(torch.linalg.norm(U1 - U64) / torch.linalg.norm(U64))
         del U1
         # leg 3b: accumulated difference of the mixed run against FP64 replaying its decisions
         sref, _, _, _, _ = run_leg(ctd, inst, "fp64", 0, args.warmup + args.steps,
@@ -222,6 +326,10 @@ def main():
         fp64["accuracy_steps"] = args.warmup + args.steps
         del Up, Uref, U64
         torch.cuda.empty_cache()
+    batched = served = None
+    if not args.no_serve:
+        batched = batched_leg(ctd)
+        served = served_leg(ctd)
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",
@@ -236,6 +344,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": fp64,
+        "served": served,
+        "batched": batched,
         "detail": extra,
     }
     print(json.dumps(out))

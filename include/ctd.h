@@ -43,7 +43,7 @@ enum {
   CTD_EDEVICE = -3,       /* HIP runtime error                              */
   CTD_ENONFINITE = -4,    /* a mode amplitude became NaN/Inf                */
   CTD_ESTATE = -5,        /* call not valid in the handle's current state   */
-  CTD_EUNSUPPORTED = -6,  /* valid but outside what this build supports      */
+  CTD_EUNSUPPORTED = -6,  /* valid but outside what the library supports    */
   CTD_EAGAIN = -7         /* server: not finished / no free slot            */
 };
 
@@ -252,6 +252,11 @@ void ctd_server_destroy(ctd_server* srv);
  * Low-level kernel entry points on caller device memory (tests, tuning).
  * ---------------------------------------------------------------------- */
 
+/* Plain device-to-device copy by a kernel (16 bytes per lane and pass; bytes
+ * a multiple of 16): a transfer of known size, used to scale hardware
+ * traffic counters. */
+int ctd_kernel_copy(void* dst, const void* src, uint64_t bytes, void* hip_stream);
+
 /* Symmetric positive definite banded solve, FP64: count independent systems
  * A_k x_k = b_k, A_k = alpha[k] Mb + beta[k] Kb with Mb, Kb in lower band
  * storage ((bw+1) x n, row t holds A[i+t, i] at [t*n + i]).  b, x: device,
@@ -269,8 +274,9 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
  * bytes of those launches (the minimal work of the operation, counted from
  * the shapes, not the executed instruction count). */
 enum {
-  CTD_K_CUBIC_G = 0,   /* cubic Gram g_e of a fresh factor and S = w g_e g_f
-                          (3D, MFMA split-K launch + its reduction)       */
+  CTD_K_CUBIC_G = 0,   /* cubic Gram g_e of a fresh factor (3D, MFMA,
+                          split-K partials)                               */
+  CTD_K_CUBIC_GRED,    /* split-K reduction of g, S = w g_e g_f          */
   CTD_K_CUBIC_H,       /* cubic evaluation h_d at the Gauss points (MFMA)*/
   CTD_K_RHS,           /* right-hand side assembly + nonlinear projection */
   CTD_K_SOLVE,         /* banded solve (block cyclic reduction) + normalisation */

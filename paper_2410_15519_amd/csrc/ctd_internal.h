@@ -121,8 +121,9 @@ hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_o
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
 int rhs_chunks(const DevInst& I, int M, int load_only);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
-// g_d (split-K partials, then their reduction) and S = w g_d g_other
-hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st);
+// g_d as split-K partials, then their reduction into g_d and S = w g_d g_other
+hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
+hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st);
 size_t cubic_h_lds(const DevInst& I);   // dynamic LDS bytes of the h kernel
 int cubic_h_rows(const DevInst& I);     // Gauss points per workgroup of the h kernel
 int cubic_h_blocks_per_cu(const DevInst& I);   // resident h workgroups per CU
@@ -140,6 +141,7 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* Kb, const double* alpha,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
 bool bcr_fits(int n, int B);                       // block data fit in LDS
 __host__ __device__ size_t bcr_lds_bytes(int n, int B);   // block data bytes of one system
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);

@@ -846,6 +846,23 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
   return e;
 }
 
+// ------------------------------------------------------------ copy
+// Plain 16-byte-per-lane copy: reads and writes exactly `bytes` once (the
+// reference transfer against which the HBM traffic counters are scaled).
+__global__ __launch_bounds__(256) void k_copy16(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                size_t words) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t words = bytes / 16;
+  const size_t want = (words + 255) / 256;
+  const int blocks = (int)std::min<size_t>(want, (size_t)num_cus() * 16);
+  k_copy16<<<blocks, 256, 0, st>>>((uint4*)dst, (const uint4*)src, words);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ append
 // Append the converged rank-one term as mode M and take the enrichment
 // decision: stop when its nodal max sigma * prod max|u_d| <= enrich_tol, or
@@ -1003,7 +1020,16 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
   if (idx >= total) return;
   const T* gp = (const T*)I.gpart;
   double s = 0.0;
-  for (int sp = 0; sp < I.nsplit_g; ++sp) s += (double)gp[(size_t)sp * total + idx];
+  // fixed split order; eight loads in flight at a time
+  int sp = 0;
+  for (; sp + 8 <= I.nsplit_g; sp += 8) {
+    T v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = gp[(size_t)(sp + u) * total + idx];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += (double)v[u];
+  }
+  for (; sp < I.nsplit_g; ++sp) s += (double)gp[(size_t)sp * total + idx];
   ((T*)I.ax[d].g)[idx] = (T)s;
   if (e_other >= 0) {
     const int t = (int)(idx / per);
@@ -1242,12 +1268,14 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   }
 }
 
-hipError_t launch_cubic_g(const DevInst& I, int d, int e_other, hipStream_t st) {
+hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st) {
   dim3 grid(I.ntri, I.nsplit_g);
   if (I.mixed) k_cubic_g<float><<<grid, 256, 0, st>>>(I, d);
   else k_cubic_g<double><<<grid, 256, 0, st>>>(I, d);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st) {
   const size_t total = (size_t)I.ntri * kTileSq * kTile;
   const int blocks = (int)((total + 255) / 256);
   if (I.mixed) k_cubic_gred<float><<<blocks, 256, 0, st>>>(I, d, e_other);

@@ -188,6 +188,10 @@ Work w_cubic(const ctd_solver* s, int d) {   // g or h: one FMA per (q, a<=b<=c)
   const double nq = s->I.ax[d].nq, M = s->I.Mk;
   return {2.0 * nq * symT(s->I.Mk), tsz(s) * (nq * M + symT(s->I.Mk)) + 8.0 * nq};
 }
+Work w_gred(const ctd_solver* s, bool with_s) {   // read partials (+ g_other), write g (+ S)
+  const double tiles = (double)s->I.ntri * kTileSq * kTile;
+  return {0.0, tsz(s) * tiles * (s->I.nsplit_g + 1 + (with_s ? 2 : 0))};
+}
 Work w_rhs(const ctd_solver* s, int d, int M) {
   const double n = s->I.ax[d].n, c = s->I.Mk + 2.0 * M;
   return {2.0 * n * c, 8.0 * n * (c + 2)};
@@ -431,8 +435,9 @@ int cubic_after(ctd_solver* s, int d, int next) {
   if (next >= 0)
     for (int e = 0; e < 3; ++e)
       if (e != d && e != next) other = e;
-  Work w = w_cubic(s, d);
-  LAUNCH(s, CTD_K_CUBIC_G, w.flops, w.bytes, launch_cubic_g(s->I, d, other, s->stream));
+  Work w = w_cubic(s, d), wr = w_gred(s, other >= 0);
+  LAUNCH(s, CTD_K_CUBIC_G, w.flops, w.bytes, launch_cubic_g(s->I, d, s->stream));
+  LAUNCH(s, CTD_K_CUBIC_GRED, wr.flops, wr.bytes, launch_cubic_gred(s->I, d, other, s->stream));
   return CTD_OK;
 }
 
@@ -803,6 +808,13 @@ void ctd_destroy(ctd_solver* s) {
   s->prof.release();
   if (s->sc_host) (void)hipHostFree(s->sc_host);
   delete s;
+}
+
+int ctd_kernel_copy(void* dst, const void* src, uint64_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes % 16 != 0) return CTD_EINVAL;
+  if (bytes == 0) return CTD_OK;
+  hipError_t e = launch_copy16(dst, src, bytes, (hipStream_t)hip_stream);
+  return e == hipSuccess ? CTD_OK : CTD_EDEVICE;
 }
 
 int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb, const double* Kb,

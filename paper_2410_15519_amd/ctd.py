@@ -23,7 +23,7 @@ PREC = {"fp64": 0, "mixed": 1}
 SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
-KERNELS = ["cubic_g", "cubic_h", "rhs", "solve", "signature", "gemv",
+KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
            "mxy_build", "energy", "quad_eval", "other"]
 
 
@@ -128,6 +128,7 @@ def _load():
         "ctd_kernel_band_solve": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
                                             C.c_int32, vp]),
         "ctd_nonlinear_load": (C.c_int, [vp, C.c_int32, P(P(C.c_double)), P(C.c_double)]),
+        "ctd_kernel_copy": (C.c_int, [vp, vp, C.c_uint64, vp]),
         "ctd_profile_enable": (C.c_int, [vp, C.c_int32]),
         "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
                                        P(C.c_double), P(C.c_double)]),
@@ -484,6 +485,16 @@ class Server:
 
     def __exit__(self, *a):
         self.close()
+
+
+def kernel_copy(dst, src, stream=None):
+    """ctd_kernel_copy between torch device tensors (same byte size)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    rc = LIB.ctd_kernel_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                             stream if stream is not None else current_stream())
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_kernel_copy")
 
 
 def band_solve(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):

@@ -1,0 +1,127 @@
+"""Short text summaries of rocprofv3 output (kernel traces and counter runs).
+
+    python -m paper_2410_15519_amd.profsum trace DB TITLE CMD > summary.md
+    python -m paper_2410_15519_amd.profsum pmc FETCH_CSV WRITE_CSV COPY_MIB TITLE CMD > summary.md
+
+`trace` groups the kernel records of a rocpd database by kernel name and
+grid.  `pmc` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
+over two counter runs of the same command, scales each by what the counter
+reads for the plain copy kernel k_copy16 of COPY_MIB MiB, and prints the
+HBM traffic per launch of every kernel with the sha256 of the kernel source
+it was taken on (a reader of the summary can tell when the kernels changed).
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kernels.hip")
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    name = name.replace("ctd::", "")
+    name = re.sub(r"\(.*$", "", name)
+    return name.replace("void ", "").strip()
+
+
+def trace(db: str, title: str, cmd: str) -> str:
+    con = sqlite3.connect(db)
+    rows = list(con.execute(
+        "select name, grid_x, grid_y, workgroup_x, count(*), avg(duration)/1000.0, "
+        "min(duration)/1000.0, max(duration)/1000.0, sum(duration)/1e6, lds_size, "
+        "vgpr_count, accum_vgpr_count, scratch_size from kernels "
+        "group by name, grid_x, grid_y order by sum(duration) desc limit 16"))
+    total = sum(r[0] for r in con.execute("select sum(duration)/1e6 from kernels"))
+    out = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
+           "```", cmd, "```", "",
+           "Summary of the rocpd database it wrote: kernel records grouped by name and grid "
+           "(grid in work-items, durations in microseconds).", "",
+           f"Total kernel time in the trace: {total:.1f} ms", "",
+           "| kernel | grid (x, y) | wg | launches | avg us | min us | max us | total ms | LDS B | VGPR | AGPR | scratch |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| {short_name(r[0])} | ({r[1]}, {r[2]}) | {r[3]} | {r[4]} | {r[5]:.1f} | "
+                   f"{r[6]:.1f} | {r[7]:.1f} | {r[8]:.1f} | {r[9]} | {r[10]} | {r[11]} | {r[12]} |")
+    return "\n".join(out) + "\n"
+
+
+def _per_kernel(path: str, counter: str):
+    """{kernel [grid]: (dispatches, mean counter value per dispatch)} from a
+    counter CSV; one entry per kernel name and grid size (work-items)."""
+    acc = collections.defaultdict(float)
+    disp = collections.defaultdict(set)
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = short_name(row.get("Kernel_Name", ""))
+            k = name if name == "k_copy16" else f"{name} [{row.get('Grid_Size', '?')}]"
+            acc[k] += float(row["Counter_Value"])
+            disp[k].add(row.get("Dispatch_Id", row.get("Correlation_Id", "")))
+    return {k: (len(disp[k]), acc[k] / max(1, len(disp[k]))) for k in acc}
+
+
+def pmc(fetch_csv: str, write_csv: str, copy_mib: float, title: str, cmd: str) -> str:
+    fe = _per_kernel(fetch_csv, "FETCH_SIZE")
+    wr = _per_kernel(write_csv, "WRITE_SIZE")
+    copy_kib = copy_mib * 1024.0
+    if "k_copy16" not in fe or "k_copy16" not in wr:
+        raise SystemExit("no k_copy16 dispatch in the counter runs")
+    f_scale = copy_kib / fe["k_copy16"][1]
+    w_scale = copy_kib / wr["k_copy16"][1]
+    names = sorted(set(fe) & set(wr), key=lambda k: -(fe[k][0] * (fe[k][1] + wr[k][1])))
+    out = [f"# {title}", "", "Commands (run from the repository root on one MI355X, one counter per run):",
+           "", "```", cmd, "```", "",
+           f"Counter values are KiB per dispatch, averaged per kernel name and grid size.  Scale: the plain copy "
+           f"kernel k_copy16 of {copy_mib:g} MiB reads FETCH_SIZE {fe['k_copy16'][1]:.0f} KiB and "
+           f"WRITE_SIZE {wr['k_copy16'][1]:.0f} KiB, so FETCH_SIZE x {f_scale:.4f} and WRITE_SIZE x "
+           f"{w_scale:.4f} give bytes moved to and from HBM.", "",
+           f"kernel source sha256 (first 16 hex): {kernel_source_sha()}", "",
+           "| kernel [grid work-items] | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM read MB | HBM write MB | traffic MB/launch |",
+           "|---|---|---|---|---|---|---|"]
+    for k in names[:16]:
+        rd = fe[k][1] * f_scale * 1024 / 1e6
+        wt = wr[k][1] * w_scale * 1024 / 1e6
+        out.append(f"| {k} | {fe[k][0]} | {fe[k][1]:.1f} | {wr[k][1]:.1f} | {rd:.3f} | {wt:.3f} | {rd + wt:.3f} |")
+    out.append("")
+    for k in names:
+        tb = (fe[k][1] * f_scale + wr[k][1] * w_scale) * 1024
+        out.append(f"traffic_bytes_per_launch {k} = {tb:.0f}")
+    return "\n".join(out) + "\n"
+
+
+def traffic_from_summary(path: str, kernel: str):
+    """Traffic per launch recorded for `kernel` ("name [grid]"), or None when
+    the summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel source sha256 \(first 16 hex\): (\w+)", text)
+    if not m or m.group(1) != kernel_source_sha():
+        return None
+    m = re.search(r"^traffic_bytes_per_launch " + re.escape(kernel) + r" = (\d+)$", text, flags=re.M)
+    return float(m.group(1)) if m else None
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "trace":
+        sys.stdout.write(trace(argv[1], argv[2], argv[3]))
+    elif len(argv) >= 6 and argv[0] == "pmc":
+        sys.stdout.write(pmc(argv[1], argv[2], float(argv[3]), argv[4], argv[5]))
+    else:
+        raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
