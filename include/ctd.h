@@ -51,6 +51,13 @@ enum { CTD_PREC_FP64 = 0, CTD_PREC_MIXED = 1 };
 enum { CTD_SCHED_ADAPTIVE = 0, CTD_SCHED_REPLAY = 1 };
 enum { CTD_INIT_HASH = 0, CTD_INIT_WARM = 1 };
 enum { CTD_DTYPE_F64 = 0, CTD_DTYPE_F32 = 1 };
+/* Directional banded solve: block cyclic reduction (any n), or fast
+ * diagonalisation with the axis' generalised eigenvectors (dense n x n FP64
+ * per axis shape, host set-up O(n^3) once per process and shape).  AUTO takes
+ * fast diagonalisation for 3D instances with n <= 1024 on every axis (many
+ * thousands of solves per step amortise the set-up) and cyclic reduction
+ * otherwise. */
+enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
 
 /*
  * Problem statement (Sec. 2.1-2.5, Sec. 3.2 parameters p, a, s; Sec. 3.3
@@ -88,7 +95,7 @@ typedef struct ctd_problem {
   int32_t schedule;         /* CTD_SCHED_ADAPTIVE | CTD_SCHED_REPLAY */
   int32_t init_mode;        /* CTD_INIT_HASH | CTD_INIT_WARM */
   int32_t energy_each_step; /* nonzero: ctd_step fills info.energy */
-  int32_t reserved;
+  int32_t solve_method;     /* CTD_SOLVE_AUTO | CTD_SOLVE_BCR | CTD_SOLVE_FD */
   uint64_t seed;            /* keys the counter-based mode initialisation */
 } ctd_problem;
 
@@ -252,6 +259,14 @@ void ctd_server_destroy(ctd_server* srv);
  * Low-level kernel entry points on caller device memory (tests, tuning).
  * ---------------------------------------------------------------------- */
 
+/* Generalised eigenvectors of the axis' stiffness and mass matrices (host,
+ * FP64): V^T M V = I, V^T K V = diag(mu), used by the fast-diagonalisation
+ * directional solve.  Axis as in ctd_problem (nodes, box, patch_s, poly_p,
+ * dilation_a, gauss_points; 0 = default).  V: host, n x n row-major (entry i
+ * of eigenvector k at V[i*n + k]); mu: host, n values; caller-owned. */
+int ctd_axis_fast_diag(int64_t n, double lo, double hi, int32_t s, int32_t p, double a,
+                       int32_t ng, double* V, double* mu);
+
 /* Plain device-to-device copy by a kernel (16 bytes per lane and pass; bytes
  * a multiple of 16): a transfer of known size, used to scale hardware
  * traffic counters. */
@@ -286,9 +301,16 @@ enum {
   CTD_K_ENERGY,        /* separated energy                                */
   CTD_K_QUAD,          /* Gauss-point tables of u^k (once per step)       */
   CTD_K_OTHER,         /* init/append/reset                               */
+  CTD_K_FINALIZE,      /* normalisation + fixed-point test after a fast-
+                          diagonalisation solve (fused into the cyclic
+                          reduction kernel otherwise)                     */
   CTD_K_COUNT
 };
 int ctd_profile_enable(ctd_solver* s, int32_t on);
+/* As ctd_profile_enable, timing only the classes whose bit (1u << class) is
+ * set in mask (each bracketed launch adds two event records to the stream;
+ * timing one class keeps the others' launch cadence). */
+int ctd_profile_select(ctd_solver* s, uint32_t mask);
 int ctd_profile_read(ctd_solver* s, int32_t kernel, int64_t* launches,
                      double* ms, double* flops, double* bytes);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,14 @@ struct AxisTables {
 int build_axis(int64_t n, double lo, double hi, int s, int p, double a, int ng,
                AxisTables& ax, std::string& err);
 void gauss_legendre(int ng, std::vector<double>& x, std::vector<double>& w);
+
+// Generalised eigenvectors of (K, M) of an axis: V^T M V = I, V^T K V =
+// diag(mu); V row-major n x n (V[i*n + k] = entry i of eigenvector k).
+struct FastDiag {
+  std::vector<double> V, mu;
+};
+bool fast_diag(const AxisTables& T, std::vector<double>& V, std::vector<double>& mu, std::string& err);
+std::shared_ptr<const FastDiag> fast_diag_cached(const AxisTables& T, std::string& err);
 
 // Device buffers of one axis of one instance.
 struct DevAxis {
@@ -56,6 +65,10 @@ struct DevAxis {
   double* gk;       // Mcap: u . KX[:, m]
   double* gmk;      // Mcap: u . MXk[:, j]
   void* g;          // cubic Gram of u (3D): ntri x 256 x 16 (T)
+  // fast-diagonalisation solve (null when the axis uses cyclic reduction)
+  const double* fdV;   // n x n row-major generalised eigenvectors
+  const double* fdmu;  // n eigenvalues
+  double* fdz;         // kFdSplit x n partial projections V^T b
 };
 
 // Scalars shared by kernels of one instance (device memory).
@@ -142,6 +155,10 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
+constexpr int kFdSplit = 8;   // row splits of the projection V^T b
+// x = V diag(1 / (alpha + beta mu)) V^T b into ax[d].u, alpha/beta from the
+// fixed factors (two launches; the normalisation follows separately)
+hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st);
 bool bcr_fits(int n, int B);                       // block data fit in LDS
 __host__ __device__ size_t bcr_lds_bytes(int n, int B);   // block data bytes of one system
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);

@@ -173,48 +173,94 @@ hipError_t launch_init_mode(const DevInst& I, int64_t step, int mode, int warm,
 // Normalise the raw factor in A.u to unit M-norm, cache M u, K u and the dot
 // products used by the fixed-point test; at the last direction of a sweep
 // evaluate the relative Frobenius change of the rank-one term.
-__device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, double* red) {
+// Fixed-order block reduction of NS sums and one max in one pass (two
+// barriers); red: >= 16 (NS + 1) doubles.
+template <int NS>
+__device__ void block_sums_max(double (&v)[NS], double& mx, double* red) {
+#pragma unroll
+  for (int j = 0; j < NS; ++j) v[j] = wave_sum(v[j]);
+  mx = wave_max(mx);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (l == 0) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) red[j * 16 + w] = v[j];
+    red[NS * 16 + w] = mx;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += red[j * 16 + i];
+    v[j] = t;
+  }
+  mx = red[NS * 16];
+  for (int i = 1; i < nw; ++i) mx = fmax(mx, red[NS * 16 + i]);
+}
+
+// Symmetric band row i of (lower band storage) times x, x in LDS; B fixed so
+// that the band loads are issued together.
+// Branch-free: the band storage holds exact zeros past the last row, and
+// the entries before the first row are replaced by zero.
+template <int B>
+__device__ __forceinline__ double band_row_lds(const double* band, int n, const double* x, int i) {
+  double y = band[i] * x[i];
+#pragma unroll
+  for (int t = 1; t <= B; ++t) {
+    const int ip = i + t < n ? i + t : n - 1;
+    const int im = i - t >= 0 ? i - t : 0;
+    const double up = band[(size_t)t * n + i];
+    const double lo = band[(size_t)t * n + im];
+    y += up * x[ip];
+    y += (i - t >= 0 ? lo : 0.0) * x[im];
+  }
+  return y;
+}
+
+// Normalise the solved factor u_d to unit M-norm (sigma = its norm), cache
+// M u, K u, and the Gram scalars of the fixed-point test.  One fused pass:
+// the sums of the unnormalised u are rescaled by 1/sigma afterwards.
+// red: >= 96 doubles of LDS; ul: 3n doubles of scratch (LDS) for u, M u, K u.
+template <int B>
+__device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, double* red, double* ul) {
   DevAxis& A = I.ax[d];
   DevScalars* sc = I.sc;
   const int n = A.n;
-  double s2 = 0.0;
+  double* ml = ul + n;
+  double* kl = ul + 2 * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) ul[i] = A.u[i];
+  __syncthreads();
+  // u.Mu, u.Ku, u.u, u.up, up.up and max|u|
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  double um = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double mu = band_row(A.Mb, n, A.B, A.u, i);
-    double ku = band_row(A.Kb, n, A.B, A.u, i);
-    A.Mu[i] = mu;
-    A.Ku[i] = ku;
-    s2 += A.u[i] * mu;
+    const double mu = band_row_lds<B>(A.Mb, n, ul, i);
+    const double ku = band_row_lds<B>(A.Kb, n, ul, i);
+    ml[i] = mu;
+    kl[i] = ku;
+    const double u = ul[i], up = A.up[i];
+    acc[0] += u * mu;
+    acc[1] += u * ku;
+    acc[2] += u * u;
+    acc[3] += u * up;
+    acc[4] += up * up;
+    um = fmax(um, fabs(u));
   }
-  s2 = block_sum(s2, red);
+  block_sums_max<5>(acc, um, red);
+  const double s2 = acc[0];
   const double sigma = sqrt(s2);
   const bool bad = !(sigma == sigma) || isinf(sigma);
   const bool zero = sigma == 0.0;
   const double inv = (bad || zero) ? 0.0 : 1.0 / sigma;
-  double m = 0, k = 0, uu = 0, uup = 0, upup = 0, um = 0;
+  const double m = s2 * inv * inv, k = acc[1] * inv * inv, uu = acc[2] * inv * inv;
+  const double uup = acc[3] * inv, upup = acc[4];
+  um *= inv;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double u = A.u[i] * inv;
-    double mu = A.Mu[i] * inv, ku = A.Ku[i] * inv;
-    double up = A.up[i];
-    m += u * mu;
-    k += u * ku;
-    uu += u * u;
-    uup += u * up;
-    upup += up * up;
-    um = fmax(um, fabs(u));
-  }
-  m = block_sum(m, red);
-  k = block_sum(k, red);
-  uu = block_sum(uu, red);
-  uup = block_sum(uup, red);
-  upup = block_sum(upup, red);
-  um = block_max(um, red);
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double u = A.u[i] * inv;
+    double u = ul[i] * inv;
     A.u[i] = u;
     A.up[i] = u;
-    A.Mu[i] *= inv;
-    A.Ku[i] *= inv;
+    A.Mu[i] = ml[i] * inv;
+    A.Ku[i] = kl[i] * inv;
   }
   if (threadIdx.x == 0) {
     sc->m[d] = m;
@@ -250,14 +296,24 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
   }
 }
 
-__global__ void k_finalize(DevInst I, int d, int sweep, int from_init) {
-  __shared__ double red[16];
-  finalize_body(I, d, sweep, from_init, red);
+template <int B>
+__global__ __launch_bounds__(1024) void k_finalize(DevInst I, int d, int sweep, int from_init) {
+  __shared__ double red[96];
+  extern __shared__ double ul[];
+  finalize_body<B>(I, d, sweep, from_init, red, ul);
 }
 
 hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
                            hipStream_t st) {
-  k_finalize<<<1, 256, 0, st>>>(I, d, sweep, from_init);
+  const int n = I.ax[d].n;
+  const size_t shm = sizeof(double) * 3 * (size_t)n;
+  const int nt = n >= 1024 ? 1024 : (n + 63) / 64 * 64;
+  switch (I.ax[d].B) {
+    case 3: k_finalize<3><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
+    case 5: k_finalize<5><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
+    case 7: k_finalize<7><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -752,6 +808,23 @@ __host__ __device__ size_t bcr_lds_bytes(int n, int B) {
 
 bool bcr_fits(int n, int B) { return bcr_lds_bytes(n, B) + 1024 <= (size_t)max_lds_bytes(); }
 
+// alpha_d, beta_d of K_d = alpha_d M_d + beta_d K_d (eq. KxQx, 3D analogue)
+// from the fixed factors' m_e = u_e.M.u_e, k_e = u_e.K.u_e.
+__device__ __forceinline__ void directional_coeffs(const DevInst& I, int d, double& al, double& be) {
+  double pm = 1.0, grad = 0.0;
+  for (int e = 0; e < I.dim; ++e)
+    if (e != d) pm *= I.sc->m[e];
+  for (int e = 0; e < I.dim; ++e) {
+    if (e == d) continue;
+    double t = I.sc->k[e];
+    for (int f = 0; f < I.dim; ++f)
+      if (f != d && f != e) t *= I.sc->m[f];
+    grad += t;
+  }
+  al = I.c * pm + I.lam * grad;
+  be = I.lam * pm;
+}
+
 // Directional solve by block cyclic reduction: alpha_d, beta_d from the
 // fixed factors, solve, then normalisation and the fixed-point test.
 // GWS: block data in the global workspace (a separate instantiation, so that
@@ -760,28 +833,17 @@ template <int B, bool GWS>
 __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk, double* gws) {
   extern __shared__ double lds[];
   double* sm = GWS ? gws : lds;
-  __shared__ double red[16];
+  __shared__ double red[96];
   __shared__ double ab[2];
   DevAxis& A = I.ax[d];
   if (threadIdx.x == 0) {
-    double pm = 1.0, grad = 0.0;
-    for (int e = 0; e < I.dim; ++e)
-      if (e != d) pm *= I.sc->m[e];
-    for (int e = 0; e < I.dim; ++e) {
-      if (e == d) continue;
-      double t = I.sc->k[e];
-      for (int f = 0; f < I.dim; ++f)
-        if (f != d && f != e) t *= I.sc->m[f];
-      grad += t;
-    }
-    ab[0] = I.c * pm + I.lam * grad;
-    ab[1] = I.lam * pm;
+    directional_coeffs(I, d, ab[0], ab[1]);
     I.sc->alpha[d] = ab[0];
     I.sc->beta[d] = ab[1];
   }
   __syncthreads();
   bcr_solve_par<B>(A.n, A.Mb, A.Kb, ab[0], ab[1], A.rpart, nchunk, A.u, sm);
-  finalize_body(I, d, sweep, 0, red);
+  finalize_body<B>(I, d, sweep, 0, red, sm);
 }
 
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st) {
@@ -844,6 +906,117 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
     if (e == hipSuccess) e = f;
   }
   return e;
+}
+
+// ---- fast diagonalisation: x = V diag(1 / (alpha + beta mu)) V^T b ----
+// Projection: workgroup (64 eigenvector columns, one of kFdSplit row ranges);
+// lane = column, waves interleave the rows.  The right-hand side of the
+// row range is summed from its partials into LDS first (same order as the
+// cyclic reduction takes them); eight rows' loads are in flight per thread.
+__global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk) {
+  const DevAxis& A = I.ax[d];
+  const int n = A.n;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + l;
+  const int per = (n + kFdSplit - 1) / kFdSplit;
+  const int i0 = blockIdx.y * per;
+  const int i1 = i0 + per < n ? i0 + per : n;
+  extern __shared__ double bl[];    // per doubles
+  __shared__ double part[4][64];
+  for (int r = threadIdx.x; r < i1 - i0; r += blockDim.x) {
+    double b = 0.0;
+    for (int y = 0; y <= nchunk; ++y) b += A.rpart[(size_t)y * n + i0 + r];
+    bl[r] = b;
+  }
+  __syncthreads();
+  double acc = 0.0;
+  const int kk = k < n ? k : n - 1;    // past the end: read in range, never stored
+  for (int r0 = w; r0 < i1 - i0; r0 += 32) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = r0 + 4 * u;
+      v[u] = r < i1 - i0 ? A.fdV[(size_t)(i0 + r) * n + kk] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int r = r0 + 4 * u;
+      if (r < i1 - i0) acc += v[u] * bl[r];
+    }
+  }
+  part[w][l] = acc;
+  __syncthreads();
+  if (w == 0 && k < n)
+    A.fdz[(size_t)blockIdx.y * n + k] = part[0][l] + part[1][l] + part[2][l] + part[3][l];
+}
+
+// Back-projection: workgroup of 16 rows, 4 per wave computed together (lanes
+// along the eigenvector index); every workgroup rebuilds the scaled
+// coefficients z_k / (alpha + beta mu_k) in LDS (kFdSplit partials, fixed
+// order).
+__global__ __launch_bounds__(256) void k_fd_apply(DevInst I, int d) {
+  DevAxis& A = I.ax[d];
+  const int n = A.n;
+  extern __shared__ double zs[];
+  __shared__ double ab[2];
+  if (threadIdx.x == 0) {
+    directional_coeffs(I, d, ab[0], ab[1]);
+    if (blockIdx.x == 0) {
+      I.sc->alpha[d] = ab[0];
+      I.sc->beta[d] = ab[1];
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    double z[kFdSplit];
+#pragma unroll
+    for (int s = 0; s < kFdSplit; ++s) z[s] = A.fdz[(size_t)s * n + k];
+    double t = 0.0;
+#pragma unroll
+    for (int s = 0; s < kFdSplit; ++s) t += z[s];
+    zs[k] = t / (ab[0] + ab[1] * A.fdmu[k]);
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ib = blockIdx.x * 16 + w * 4;
+  int rows[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) rows[r] = ib + r < n ? ib + r : n - 1;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = l; k0 < n; k0 += 256) {
+    double v[4][4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int k = k0 + 64 * h;
+        v[h][r] = k < n ? A.fdV[(size_t)rows[r] * n + k] : 0.0;
+      }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int k = k0 + 64 * h;
+      const double z = k < n ? zs[k] : 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] += v[h][r] * z;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double t = wave_sum(acc[r]);
+    if (l == 0 && ib + r < n) A.u[ib + r] = t;
+  }
+}
+
+hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st) {
+  const DevAxis& A = I.ax[d];
+  if (!A.fdV || !A.fdmu || !A.fdz) return hipErrorInvalidValue;
+  const int n = A.n;
+  const size_t per = (size_t)(n + kFdSplit - 1) / kFdSplit;
+  k_fd_project<<<dim3((n + 63) / 64, kFdSplit), 256, sizeof(double) * per, st>>>(I, d, rhs_chunks(I, M, 0));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_fd_apply<<<(n + 15) / 16, 256, sizeof(double) * (size_t)n, st>>>(I, d);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------ copy
@@ -934,7 +1107,18 @@ __global__ __launch_bounds__(256) void k_cubic_g(DevInst I, int d) {
   const T* Y = (const T*)(sizeof(T) == 4 ? (const void*)A.Xhf : (const void*)A.Xh);
   const T* vq = (const T*)(sizeof(T) == 4 ? (const void*)A.vf : (const void*)A.v);
   const int ldh = I.Mkp;
-  const int t = blockIdx.x, split = blockIdx.y;
+  // Workgroups are dealt to the 8 XCDs round-robin by linear id; with the
+  // split count a multiple of 8, XCD x takes the splits x, x+8, ... of every
+  // triple, so each XCD's L2 holds only its own Gauss-point range of Y.
+  int t, split;
+  if ((I.nsplit_g & 7) == 0) {
+    const int b = blockIdx.x, m = I.nsplit_g >> 3, r = b >> 3;
+    split = (b & 7) + 8 * (r % m);
+    t = r / m;
+  } else {
+    t = blockIdx.x % I.ntri;
+    split = blockIdx.x / I.ntri;
+  }
   const int4 tr = I.tri[t];
   const int col0[3] = {tr.x * kTile, tr.y * kTile, tr.z * kTile};
   const int nq = A.nq;
@@ -1269,7 +1453,7 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
 }
 
 hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st) {
-  dim3 grid(I.ntri, I.nsplit_g);
+  const int grid = I.ntri * I.nsplit_g;
   if (I.mixed) k_cubic_g<float><<<grid, 256, 0, st>>>(I, d);
   else k_cubic_g<double><<<grid, 256, 0, st>>>(I, d);
   return hipGetLastError();

@@ -59,6 +59,7 @@ struct DeviceArena {
 // Launch timing with HIP events on the handle's stream.
 struct Profiler {
   bool on = false;
+  uint32_t mask = ~0u;   // kernel classes bracketed with events
   struct Pending { int id; int ev; double flops, bytes; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
@@ -128,6 +129,8 @@ struct ctd_solver {
   double* energy_partial = nullptr;
   size_t energy_partial_cap = 0;
   std::vector<double> host_tmp;
+  bool use_fd[kMaxDim] = {};                            // fast-diagonalisation solve per axis
+  std::shared_ptr<const FastDiag> fd[kMaxDim];          // host eigenvectors (process cache)
   Profiler prof;
 
   int fail(int code, const std::string& msg) {
@@ -150,7 +153,7 @@ struct ctd_solver {
 // with events and book it under kernel class `id` with algorithmic work.
 #define LAUNCH_ON(s, st, id, fl, by, expr)                                   \
   do {                                                                       \
-    if ((s)->prof.on) {                                                      \
+    if ((s)->prof.on && (((s)->prof.mask >> (id)) & 1u)) {                   \
       int _ev = 0;                                                           \
       HIPCHK(s, (s)->prof.event_pair(_ev));                                  \
       HIPCHK(s, hipEventRecord((s)->prof.pool[_ev], (st)));                  \
@@ -198,6 +201,8 @@ Work w_rhs(const ctd_solver* s, int d, int M) {
 }
 Work w_solve(const ctd_solver* s, int d) {
   const double n = s->I.ax[d].n, B = s->I.ax[d].B;
+  // fast diagonalisation: two dense n x n products over the eigenvectors
+  if (s->use_fd[d]) return {4.0 * n * n, 8.0 * (2.0 * n * n + 4.0 * n)};
   return {n * (B * B + 6 * B + 8 * B), 8.0 * n * (2 * (B + 1) + 6)};
 }
 Work w_sig(const ctd_solver* s, int d, int M) {
@@ -269,8 +274,10 @@ void update_view(ctd_solver* s) {
   if (s->dim == 3) {
     int nqmin = 1 << 30;
     for (int d = 0; d < 3; ++d) nqmin = std::min(nqmin, I.ax[d].nq);
-    // g: about 1024 workgroups of 64-point chunks
+    // g: about 1024 workgroups of 64-point chunks; a multiple of 8 splits
+    // when there are at least 8 (XCD-aware split mapping in the kernel)
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
+    if (ng >= 8) ng = ng / 8 * 8;
     ng = std::min(ng, s->nsplit_g_cap / I.ntri);
     I.nsplit_g = std::max(1, ng);
     // h: one round of resident workgroups, triples split evenly
@@ -396,14 +403,53 @@ int alloc_instance(ctd_solver* s, int m0) {
   const int npt = nbmx * (nbmx + 1) / 2;
   s->energy_partial_cap = std::max<size_t>((size_t)npt * (npt + 1) / 2 * 16, 2 * (size_t)s->Mcap) + 16;
   AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
-#undef AL
   {
+    // directional solve per axis: fast diagonalisation (eigenvectors shared
+    // by the axes of one shape) or cyclic reduction
+    bool all_small = true;
+    for (int d = 0; d < s->dim; ++d) all_small = all_small && s->ax[d].n <= 1024;
+    const int method = s->P.solve_method;
+    for (int d = 0; d < s->dim; ++d)
+      s->use_fd[d] = method == CTD_SOLVE_FD || (method == CTD_SOLVE_AUTO && s->dim == 3 && all_small);
+    for (int d = 0; d < s->dim; ++d) {
+      if (!s->use_fd[d]) continue;
+      const AxisTables& T = s->ax[d];
+      const size_t n = T.n;
+      DevAxis& X = I.ax[d];
+      AL(X.fdz, sizeof(double) * kFdSplit * n);
+      int same = -1;
+      for (int e = 0; e < d; ++e) {
+        const AxisTables& U = s->ax[e];
+        if (s->use_fd[e] && U.n == T.n && U.lo == T.lo && U.hi == T.hi && U.s == T.s &&
+            U.p == T.p && U.a == T.a && U.ng == T.ng)
+          same = e;
+      }
+      if (same >= 0) {
+        X.fdV = I.ax[same].fdV;
+        X.fdmu = I.ax[same].fdmu;
+        s->fd[d] = s->fd[same];
+        continue;
+      }
+      double *V = nullptr, *mu = nullptr;
+      AL(V, sizeof(double) * n * n);
+      AL(mu, sizeof(double) * n);
+      X.fdV = V;
+      X.fdmu = mu;
+      if (A.dry) continue;
+      std::string ferr;
+      s->fd[d] = fast_diag_cached(T, ferr);
+      if (!s->fd[d]) return s->fail(CTD_EUNSUPPORTED, "fast diagonalisation: " + ferr);
+      HIPCHK(s, copy_sync(s, V, s->fd[d]->V.data(), sizeof(double) * n * n, hipMemcpyHostToDevice));
+      HIPCHK(s, copy_sync(s, mu, s->fd[d]->mu.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    }
     // cyclic-reduction block data of axes too large for LDS live in HBM
     size_t ws = 0;
     for (int d = 0; d < s->dim; ++d)
-      if (!bcr_fits(s->ax[d].n, s->ax[d].B)) ws = std::max(ws, bcr_lds_bytes(s->ax[d].n, s->ax[d].B));
-    if (ws) HIPCHK(s, A.alloc((void**)&I.bcr_ws, ws));
+      if (!s->use_fd[d] && !bcr_fits(s->ax[d].n, s->ax[d].B))
+        ws = std::max(ws, bcr_lds_bytes(s->ax[d].n, s->ax[d].B));
+    if (ws) AL(I.bcr_ws, ws);
   }
+#undef AL
   if (!A.dry) HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
   return CTD_OK;
 }
@@ -536,7 +582,12 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
           Work w = w_rhs(s, d, M);
           LAUNCH(s, CTD_K_RHS, w.flops, w.bytes, launch_rhs(s->I, d, M, s->stream));
           Work ws = w_solve(s, d);
-          LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
+          if (s->use_fd[d]) {
+            LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_fd(s->I, d, M, s->stream));
+            LAUNCH(s, CTD_K_FINALIZE, 0.0, 0.0, launch_finalize(s->I, d, it, 0, s->stream));
+          } else {
+            LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
+          }
         }
         if (d < D - 1) {
           Work w = w_sig(s, d, M);
@@ -886,10 +937,15 @@ extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const*
 }
 
 extern "C" int ctd_profile_enable(ctd_solver* s, int32_t on) {
+  return ctd_profile_select(s, on ? ~0u : 0u);
+}
+
+extern "C" int ctd_profile_select(ctd_solver* s, uint32_t mask) {
   if (!s) return CTD_EINVAL;
   HIPCHK(s, hipStreamSynchronize(s->stream));
   s->prof.reset();
-  s->prof.on = on != 0;
+  s->prof.on = mask != 0;
+  s->prof.mask = mask;
   return CTD_OK;
 }
 

@@ -23,8 +23,9 @@ PREC = {"fp64": 0, "mixed": 1}
 SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
+SOLVE = {"auto": 0, "bcr": 1, "fd": 2}
 KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
-           "mxy_build", "energy", "quad_eval", "other"]
+           "mxy_build", "energy", "quad_eval", "other", "finalize"]
 
 
 class CtdError(RuntimeError):
@@ -45,7 +46,7 @@ class Problem(C.Structure):
         ("fp_tol", C.c_double), ("enrich_tol", C.c_double),
         ("max_modes", C.c_int32), ("precision", C.c_int32),
         ("schedule", C.c_int32), ("init_mode", C.c_int32),
-        ("energy_each_step", C.c_int32), ("reserved", C.c_int32),
+        ("energy_each_step", C.c_int32), ("solve_method", C.c_int32),
         ("seed", C.c_uint64),
     ]
 
@@ -129,7 +130,10 @@ def _load():
                                             C.c_int32, vp]),
         "ctd_nonlinear_load": (C.c_int, [vp, C.c_int32, P(P(C.c_double)), P(C.c_double)]),
         "ctd_kernel_copy": (C.c_int, [vp, vp, C.c_uint64, vp]),
+        "ctd_axis_fast_diag": (C.c_int, [C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                         C.c_double, C.c_int32, P(C.c_double), P(C.c_double)]),
         "ctd_profile_enable": (C.c_int, [vp, C.c_int32]),
+        "ctd_profile_select": (C.c_int, [vp, C.c_uint32]),
         "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
                                        P(C.c_double), P(C.c_double)]),
     }
@@ -155,7 +159,7 @@ def current_stream():
 
 
 def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash",
-                 energy=False, **over) -> Problem:
+                 energy=False, solve="auto", **over) -> Problem:
     """ctd_problem from a workloads.Instance (epsilon form) plus overrides."""
     p = Problem()
     rc = LIB.ctd_problem_default(C.byref(p))
@@ -178,6 +182,7 @@ def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash
     p.schedule = SCHED[schedule]
     p.init_mode = INIT[init]
     p.energy_each_step = 1 if energy else 0
+    p.solve_method = SOLVE[solve]
     for k, v in over.items():
         if k in ("nodes", "lo", "hi"):
             for d, x in enumerate(v):
@@ -260,9 +265,18 @@ class Solver:
         self._check(LIB.ctd_nonlinear_load(self.h, d, ptrs, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
-    def profile(self, on=True):
-        """Enable (and reset) or disable per-kernel HIP-event timing."""
-        self._check(LIB.ctd_profile_enable(self.h, 1 if on else 0))
+    def profile(self, on=True, classes=None):
+        """Enable (and reset) or disable per-kernel HIP-event timing; classes:
+        names from KERNELS to time (default all)."""
+        if not on:
+            self._check(LIB.ctd_profile_select(self.h, 0))
+        elif classes is None:
+            self._check(LIB.ctd_profile_enable(self.h, 1))
+        else:
+            mask = 0
+            for c in classes:
+                mask |= 1 << KERNELS.index(c)
+            self._check(LIB.ctd_profile_select(self.h, mask))
 
     def profile_read(self):
         out = {}

@@ -76,3 +76,32 @@ def test_server_and_batch_argument_checks():
     assert ctd.LIB.ctd_batch_set_workers(None, 4) == -1
     ctd.LIB.ctd_server_destroy(None)
     assert ctd.LIB.ctd_server_last_error(None)
+
+
+@pytest.mark.parametrize("n,s", [(7, 2), (37, 1), (64, 2), (129, 3)])
+def test_axis_fast_diag_against_scipy(n, s):
+    """The library's host eigen-decomposition for the fast-diagonalisation
+    solve: V^T M V = I, V^T K V = diag(mu), and mu against scipy's symmetric-
+    definite eigenvalues (an independent LAPACK implementation)."""
+    import numpy as np
+    import scipy.linalg as sla
+    from paper_2410_15519_amd import ctd
+    from oracle.cfe1d import Axis
+    V = np.zeros((n, n))
+    mu = np.zeros(n)
+    rc = ctd.LIB.ctd_axis_fast_diag(n, 0.0, 1.0, s, min(s, 2), 12.0, 5,
+                                    V.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    mu.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert rc == 0
+    ax = Axis(n, 0.0, 1.0, s=s, p=min(s, 2), a=12.0, ng=5)
+    assert np.abs(V.T @ ax.M @ V - np.eye(n)).max() < 1e-12
+    D = V.T @ ax.K @ V
+    assert np.abs(D - np.diag(mu)).max() < 1e-12 * np.abs(mu).max()
+    ref = sla.eigh(ax.K, ax.M, eigvals_only=True)
+    assert np.abs(np.sort(mu) - ref).max() < 1e-12 * np.abs(ref).max()
+    # the solve it enables equals a banded solve
+    al, be = 5002.0, 2.5e-5
+    b = np.random.default_rng(n).standard_normal(n)
+    x = V @ ((V.T @ b) / (al + be * mu))
+    ref = sla.solveh_banded(ax.banded(al * ax.M + be * ax.K), b, lower=True)
+    assert np.linalg.norm(x - ref) < 1e-12 * np.linalg.norm(ref)

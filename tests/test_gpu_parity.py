@@ -68,13 +68,16 @@ def test_band_solve_kernel(ctd):
             assert rel(xh[k], ref) < 1e-12
 
 
-@pytest.mark.parametrize("dim,n,m0,steps", [(2, 37, 3, 3), (3, 21, 3, 2), (2, (1500, 24), 3, 2)])
+@pytest.mark.parametrize("dim,n,m0,steps,solve", [(2, 37, 3, 3, "auto"), (3, 21, 3, 2, "bcr"),
+                                                  (3, 21, 3, 2, "fd"), (2, (1500, 24), 3, 2, "auto"),
+                                                  (3, (40, 17, 23), 3, 2, "fd")])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_step_replay_parity(ctd, dim, n, m0, steps, prec):
+def test_step_replay_parity(ctd, dim, n, m0, steps, solve, prec):
     inst = small_instance(dim=dim, n=n, m0=m0, kmax=4, eps=0.05, dt=1e-3, max_modes=24)
     pr, st, fields, logs = oracle_run(inst, steps)
-    print(f"replay dim={dim} n={n} prec={prec} modes={[len(l.iters) for l in logs]}", flush=True)
-    with ctd.Solver(inst, precision=prec, schedule="replay") as s:
+    print(f"replay dim={dim} n={n} solve={solve} prec={prec} modes={[len(l.iters) for l in logs]}",
+          flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", solve=solve) as s:
         s.set_decisions([lg.iters for lg in logs])
         for k in range(steps):
             info = s.step(1)[0]
@@ -85,11 +88,12 @@ def test_step_replay_parity(ctd, dim, n, m0, steps, prec):
             assert err < TOL[prec]
 
 
-@pytest.mark.parametrize("dim,n,m0,steps", [(2, 37, 3, 3), (3, 21, 3, 2)])
-def test_adaptive_decisions_match_oracle(ctd, dim, n, m0, steps):
+@pytest.mark.parametrize("dim,n,m0,steps,solve", [(2, 37, 3, 3, "auto"), (3, 21, 3, 2, "bcr"),
+                                                  (3, 21, 3, 2, "fd")])
+def test_adaptive_decisions_match_oracle(ctd, dim, n, m0, steps, solve):
     inst = small_instance(dim=dim, n=n, m0=m0, kmax=4, eps=0.05, dt=1e-3, max_modes=24)
     pr, st, fields, logs = oracle_run(inst, steps)
-    with ctd.Solver(inst, precision="fp64") as s:
+    with ctd.Solver(inst, precision="fp64", solve=solve) as s:
         s.step(steps)
         dec = s.decisions()
         U = s.reconstruct()
