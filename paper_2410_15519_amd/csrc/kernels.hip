@@ -1243,8 +1243,10 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
 // lane's Gauss point come from L2 straight into VGPRs, and the S tile and
 // factor values of the next triple are fetched while the MFMAs of the
 // current one run.
-constexpr int kHQ = 64;   // Gauss points per workgroup
+constexpr int kHRows = 1;              // 16-point MFMA blocks per wave (2 measured slower: occupancy)
+constexpr int kHQ = 64 * kHRows;       // Gauss points per workgroup
 
+template <int HR>
 __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
   extern __shared__ unsigned char smraw[];
   constexpr int TW = kTileSq * kTile / 4;   // 16-byte words per S tile
@@ -1254,54 +1256,72 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
   const int nq = A.nq;
   float4* sb = (float4*)smraw;           // 2 x TW words
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int q0 = blockIdx.x * kHQ;
+  const int q0 = blockIdx.x * (64 * HR);
+  const int qw = q0 + w * 16 * HR;       // first Gauss point of this wave
   const int split = blockIdx.y;
   const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
   const int t0 = split * per;
   const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
-  // A-operand row of this lane; rows past the end read the last point (their
+  // A-operand rows of this lane; rows past the end read the last point (their
   // MFMA output rows are never stored)
-  int qa = q0 + w * 16 + (l & 15);
-  qa = qa < nq ? qa : nq - 1;
-  const float* xrow = X + (size_t)qa * ldh;
+  const float* xrow[HR];
+#pragma unroll
+  for (int rb = 0; rb < HR; ++rb) {
+    int qa = qw + rb * 16 + (l & 15);
+    qa = qa < nq ? qa : nq - 1;
+    xrow[rb] = X + (size_t)qa * ldh;
+  }
   // prefetch registers; loads use a clamped triple index so they are
   // unconditional (the surplus S words land in the idle buffer)
   const int tlast = t1 > t0 ? t1 - 1 : 0;
   const float4* Sp = (const float4*)I.S;
   float4 pre[TW / 256];
-  float4 xa4[4], xan[4];
-  float xb[4], xbn[4];
+  float4 xa4[HR][4], xan[HR][4];
+  float xb[HR][4], xbn[HR][4];
 #define H32_FETCH(tt, XA, XB)                                                    \
   do {                                                                          \
     const int4 tr_ = I.tri[tt];                                                 \
     const size_t base_ = (size_t)(tt) * TW + tid;                               \
     _Pragma("unroll") for (int v = 0; v < TW / 256; ++v) pre[v] = Sp[base_ + v * 256]; \
-    const float4* ar_ = (const float4*)(xrow + tr_.x * kTile);                   \
-    _Pragma("unroll") for (int v = 0; v < 4; ++v) XA[v] = ar_[v];                \
-    _Pragma("unroll") for (int m = 0; m < 4; ++m) XB[m] = xrow[tr_.y * kTile + 4 * m + (l >> 4)]; \
+    _Pragma("unroll") for (int rb = 0; rb < HR; ++rb) {                         \
+      const float4* ar_ = (const float4*)(xrow[rb] + tr_.x * kTile);            \
+      _Pragma("unroll") for (int v = 0; v < 4; ++v) XA[rb][v] = ar_[v];         \
+      _Pragma("unroll") for (int m = 0; m < 4; ++m)                             \
+        XB[rb][m] = xrow[rb][tr_.y * kTile + 4 * m + (l >> 4)];                 \
+    }                                                                           \
   } while (0)
   H32_FETCH(t0 < tlast ? t0 : tlast, xa4, xb);
 #pragma unroll
   for (int v = 0; v < TW / 256; ++v) sb[v * 256 + tid] = pre[v];
   __syncthreads();
-  double hq[4] = {0, 0, 0, 0};
-  f4 acc[2] = {f4{0, 0, 0, 0}, f4{0, 0, 0, 0}};
+  double hq[HR][4];
+  f4 acc[HR][2];
+#pragma unroll
+  for (int rb = 0; rb < HR; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) hq[rb][r] = 0.0;
+    acc[rb][0] = f4{0, 0, 0, 0};
+    acc[rb][1] = f4{0, 0, 0, 0};
+  }
   int curC = -1;
   auto close_c = [&]() {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int q = q0 + w * 16 + mfma_row<float>(l, r);
-      q = q < nq ? q : nq - 1;
-      double v = ((double)acc[0][r] + (double)acc[1][r]) *
-                 (double)X[(size_t)q * ldh + curC * kTile + (l & 15)];
-      v += __shfl_xor(v, 8, 64);
-      v += __shfl_xor(v, 4, 64);
-      v += __shfl_xor(v, 2, 64);
-      v += __shfl_xor(v, 1, 64);
-      hq[r] += v;
+    for (int rb = 0; rb < HR; ++rb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int q = qw + rb * 16 + mfma_row<float>(l, r);
+        q = q < nq ? q : nq - 1;
+        double v = ((double)acc[rb][0][r] + (double)acc[rb][1][r]) *
+                   (double)X[(size_t)q * ldh + curC * kTile + (l & 15)];
+        v += __shfl_xor(v, 8, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 1, 64);
+        hq[rb][r] += v;
+      }
+      acc[rb][0] = f4{0, 0, 0, 0};
+      acc[rb][1] = f4{0, 0, 0, 0};
     }
-    acc[0] = f4{0, 0, 0, 0};
-    acc[1] = f4{0, 0, 0, 0};
   };
   for (int t = t0; t < t1; ++t) {
     const int cz = I.tri[t].z;
@@ -1317,7 +1337,9 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int ks = 4 * j + u;
-        acc[u & 1] = mfma16(xa4[ks >> 4][(ks >> 2) & 3] * xb[ks & 3], b4[u], acc[u & 1]);
+#pragma unroll
+        for (int rb = 0; rb < HR; ++rb)
+          acc[rb][u & 1] = mfma16(xa4[rb][ks >> 4][(ks >> 2) & 3] * xb[rb][ks & 3], b4[u], acc[rb][u & 1]);
       }
     }
     {
@@ -1326,16 +1348,20 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
       for (int v = 0; v < TW / 256; ++v) dst[v * 256 + tid] = pre[v];
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) { xa4[v] = xan[v]; xb[v] = xbn[v]; }
+    for (int rb = 0; rb < HR; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) { xa4[rb][v] = xan[rb][v]; xb[rb][v] = xbn[rb][v]; }
     __syncthreads();
   }
   if (curC >= 0) close_c();
   if ((l & 15) == 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int q = q0 + w * 16 + mfma_row<float>(l, r);
-      if (q < nq) I.hpart[(size_t)split * nq + q] = hq[r];
-    }
+    for (int rb = 0; rb < HR; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = qw + rb * 16 + mfma_row<float>(l, r);
+        if (q < nq) I.hpart[(size_t)split * nq + q] = hq[rb][r];
+      }
   }
 #undef H32_FETCH
 }
@@ -1483,7 +1509,7 @@ int cubic_h_blocks_per_cu(const DevInst& I) {
   const size_t shm = cubic_h_lds(I);
   if (last_shm[k] != shm) {
     int nb = 0;
-    const void* f = I.mixed ? (const void*)k_cubic_h32 : (const void*)k_cubic_h<double>;
+    const void* f = I.mixed ? (const void*)k_cubic_h32<kHRows> : (const void*)k_cubic_h<double>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, shm) != hipSuccess || nb < 1) {
       (void)hipGetLastError();
       nb = std::max(1, (int)((size_t)max_lds_bytes() / shm));
@@ -1499,7 +1525,7 @@ hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
   const int rows = cubic_h_rows(I);
   dim3 grid((nq + rows - 1) / rows, I.nsplit_h);
   if (I.mixed) {
-    k_cubic_h32<<<grid, 256, cubic_h_lds(I), st>>>(I, d);
+    k_cubic_h32<kHRows><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   } else {
     k_cubic_h<double><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   }
@@ -1767,10 +1793,84 @@ __global__ void k_reconstruct(DevInst I, int M, T* out) {
   out[idx] = (T)s;
 }
 
+// Tiled reconstruction: a workgroup owns a 64 x 64 tile of the last two
+// axes, keeps both factor tiles (M x 64, mode-major) in LDS and walks its
+// range of slabs of the first axis (3D; one slab in 2D); per slab each thread
+// forms a 4 x 4 block of nodes, sum over modes in FP64, mode order.
+template <class T>
+__global__ __launch_bounds__(256) void k_reconstruct_tile(DevInst I, int M, T* out) {
+  const int D = I.dim;
+  const DevAxis& AY = I.ax[D - 2];
+  const DevAxis& AZ = I.ax[D - 1];
+  const int nj = AY.n, nl = AZ.n;
+  const int ni = D == 3 ? I.ax[0].n : 1;
+  extern __shared__ double lds[];
+  double* ys = lds;            // M x 64
+  double* zs = ys + M * 64;    // M x 64
+  double* sx = zs + M * 64;    // M
+  const int j0 = blockIdx.y * 64, l0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  for (int idx = tid; idx < M * 64; idx += blockDim.x) {
+    const int m = idx >> 6, c = idx & 63;
+    ys[idx] = j0 + c < nj ? AY.X[(size_t)m * nj + j0 + c] : 0.0;
+    zs[idx] = l0 + c < nl ? AZ.X[(size_t)m * nl + l0 + c] : 0.0;
+  }
+  const int per = (ni + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int i0 = blockIdx.z * per;
+  const int i1 = i0 + per < ni ? i0 + per : ni;
+  for (int i = i0; i < i1; ++i) {
+    __syncthreads();
+    for (int m = tid; m < M; m += blockDim.x)
+      sx[m] = D == 3 ? I.sn[m] * I.ax[0].X[(size_t)m * ni + i] : I.sn[m];
+    __syncthreads();
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const double s = sx[m];
+      double a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = ys[m * 64 + ty * 4 + r] * s;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = zs[m * 64 + tx + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = j0 + ty * 4 + r;
+      if (j >= nj) continue;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int l = l0 + tx + 16 * c;
+        if (l < nl) out[((size_t)i * nj + j) * nl + l] = (T)acc[r][c];
+      }
+    }
+  }
+}
+
+size_t reconstruct_tile_lds(int M) { return sizeof(double) * ((size_t)M * 128 + M); }
+
 hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
                               hipStream_t st) {
   size_t total = 1;
   for (int d = 0; d < I.dim; ++d) total *= (size_t)I.ax[d].n;
+  if (M >= 1 && reconstruct_tile_lds(M) <= (size_t)max_lds_bytes()) {
+    const int nj = I.ax[I.dim - 2].n, nl = I.ax[I.dim - 1].n;
+    const int ni = I.dim == 3 ? I.ax[0].n : 1;
+    const int tiles = ((nl + 63) / 64) * ((nj + 63) / 64);
+    int zs = std::max(1, std::min(ni, (4 * num_cus() + tiles - 1) / tiles));
+    dim3 grid((nl + 63) / 64, (nj + 63) / 64, zs);
+    const size_t shm = reconstruct_tile_lds(M);
+    if (dtype == CTD_DTYPE_F32) k_reconstruct_tile<float><<<grid, 256, shm, st>>>(I, M, (float*)out);
+    else k_reconstruct_tile<double><<<grid, 256, shm, st>>>(I, M, (double*)out);
+    return hipGetLastError();
+  }
+  // very many modes: node-parallel form
   const int blocks = (int)((total + 255) / 256);
   if (dtype == CTD_DTYPE_F32) k_reconstruct<float><<<blocks, 256, 0, st>>>(I, M, (float*)out);
   else k_reconstruct<double><<<blocks, 256, 0, st>>>(I, M, (double*)out);
@@ -1803,7 +1903,8 @@ hipError_t configure_kernels() {
                       (const void*)k_solve_bcr<7, false>, (const void*)k_band_solve_bcr<3, false>,
                       (const void*)k_band_solve_bcr<5, false>, (const void*)k_band_solve_bcr<7, false>,
                       (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>,
-                      (const void*)k_cubic_h32};
+                      (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
+                      (const void*)k_reconstruct_tile<double>};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipGetLastError();

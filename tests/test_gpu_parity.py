@@ -139,3 +139,21 @@ def test_00_device_limits(ctd):
     print("device:", p.name, "LDS/block:", getattr(p, "shared_memory_per_block", None),
           "LDS/block optin:", getattr(p, "shared_memory_per_block_optin", None),
           "CUs:", p.multi_processor_count, flush=True)
+
+
+@pytest.mark.parametrize("dim,n,m0", [(3, (37, 45, 70), 60), (3, (20, 33, 66), 170),
+                                      (2, (100, 130), 12)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_reconstruct_matches_definition(ctd, dim, n, m0, dtype):
+    """Nodal field sum_m amp_m prod_d X_d[:, m] (Kronecker property: nodal
+    values are the coefficients), ragged 64 x 64 tiles; 170 modes exceed the
+    tiled kernel's LDS and take the node-parallel form."""
+    inst = small_instance(dim=dim, n=n, m0=m0, kmax=6, max_modes=m0)
+    with ctd.Solver(inst) as s:
+        U = s.reconstruct(dtype)
+    if dim == 3:
+        ref = np.einsum("m,im,jm,lm->ijl", inst.amp, *inst.factors)
+    else:
+        ref = np.einsum("m,im,jm->ij", inst.amp, *inst.factors)
+    assert U.shape == ref.shape
+    assert rel(U, ref) < (1e-14 if dtype == "f64" else 1e-7)
