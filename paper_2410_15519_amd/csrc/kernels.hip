@@ -409,53 +409,72 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
       coef[tid] = v;
     }
     __syncthreads();
+    // 16 columns per wave, all loads issued before the sum (fixed order)
     double acc = 0.0;
     if (i < n) {
-#pragma unroll 4
+      double v[16];
+#pragma unroll
       for (int cc = 0; cc < 16; ++cc) {
         const int c = y * 64 + w * 16 + cc;
-        if (c >= ctot) break;
         const double* col = c < I.Mk ? A.MXk + (size_t)c * n
                                      : (c < I.Mk + M ? A.MX + (size_t)(c - I.Mk) * n
                                                      : A.KX + (size_t)(c - I.Mk - M) * n);
-        acc += coef[w * 16 + cc] * col[i];
+        v[cc] = c < ctot ? col[i] : 0.0;
       }
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc += coef[w * 16 + cc] * v[cc];
     }
     part[tid] = acc;
     __syncthreads();
     if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
     return;
   }
-  // chunk nchunk: the projected nonlinear load
+  // chunk nchunk: the projected nonlinear load F_i = omega sum_q Phi[q, i] W_q h_q
+  // over the elements around the 64 rows; h and the Phi rows of those
+  // elements are staged in LDS, and the elements of a row are split over the
+  // four waves (summed in wave order).
   double F = 0.0;
   if (I.dim == 3) {
     const int ne = n - 1;
-    const int e_lo = r0 - A.SW > 0 ? r0 - A.SW : 0;
-    const int e_hi = r0 + 63 + A.SW < ne - 1 ? r0 + 63 + A.SW : ne - 1;
+    const int SW = A.SW;
+    const int e_lo = r0 - SW > 0 ? r0 - SW : 0;
+    const int e_hi = r0 + 63 + SW < ne - 1 ? r0 + 63 + SW : ne - 1;
     const int q_lo = e_lo * A.ng, qcount = (e_hi - e_lo + 1) * A.ng;
+    double* phl = hl + qcount;    // qcount x SW
     for (int idx = tid; idx < qcount; idx += blockDim.x) {
       const int q = q_lo + idx;
+      double hp[16];
+      const int ns = I.nsplit_h;
+#pragma unroll
+      for (int sp = 0; sp < 16; ++sp) hp[sp] = sp < ns ? I.hpart[(size_t)sp * A.nq + q] : 0.0;
       double h = 0.0;
-      for (int sp = 0; sp < I.nsplit_h; ++sp) h += I.hpart[(size_t)sp * A.nq + q];
+#pragma unroll
+      for (int sp = 0; sp < 16; ++sp) h += hp[sp];
+      for (int sp = 16; sp < ns; ++sp) h += I.hpart[(size_t)sp * A.nq + q];
       hl[idx] = h * A.w[q];
     }
+    for (int idx = tid; idx < qcount * SW; idx += blockDim.x)
+      phl[idx] = A.phi[(size_t)q_lo * SW + idx];
     __syncthreads();
-    if (w == 0 && i < n) {
-      int e0 = i - A.SW;
+    double Fw = 0.0;
+    if (i < n) {
+      int e0 = i - SW;
       e0 = e0 < e_lo ? e_lo : e0;
-      int e1 = i + A.SW;
+      int e1 = i + SW;
       e1 = e1 > e_hi ? e_hi : e1;
-      for (int e = e0; e <= e1; ++e) {
-        const int st = elem_start(e, A.s, n, A.SW);
+      for (int e = e0 + w; e <= e1; e += 4) {
+        const int st = elem_start(e, A.s, n, SW);
         const int jj = i - st;
-        if (jj < 0 || jj >= A.SW) continue;
+        if (jj < 0 || jj >= SW) continue;
         for (int g = 0; g < A.ng; ++g) {
-          const int qq = e * A.ng + g;
-          F += A.phi[(size_t)qq * A.SW + jj] * hl[qq - q_lo];
+          const int qq = e * A.ng + g - q_lo;
+          Fw += phl[qq * SW + jj] * hl[qq];
         }
       }
-      F *= I.omega;
     }
+    part[tid] = Fw;
+    __syncthreads();
+    if (w == 0) F = I.omega * (part[l] + part[64 + l] + part[128 + l] + part[192 + l]);
   } else if (i < n) {
     F = A.F[i];
   }
@@ -471,7 +490,8 @@ hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_o
   const DevAxis& A = I.ax[d];
   const int nchunk = rhs_chunks(I, M, load_only);
   dim3 grid((A.n + 63) / 64, nchunk + 1);
-  const size_t shm = sizeof(double) * (size_t)(64 + 2 * A.SW + 2) * A.ng;
+  // h (qcount) and the Phi rows (qcount x SW) of the elements around a row block
+  const size_t shm = sizeof(double) * (size_t)(64 + 2 * A.SW + 2) * A.ng * (1 + A.SW);
   k_rhs<<<grid, 256, shm, st>>>(I, d, M, load_only, nchunk);
   return hipGetLastError();
 }
@@ -1092,17 +1112,28 @@ hipError_t launch_reset_scalars(const DevInst& I, hipStream_t st) {
 // is an MFMA product with K = q (g) or K = 256 mode pairs (h).
 constexpr int kGChunk = 64;
 
-// g over one tile triple and one Gauss-point range (split-K).  Y rows of the
-// A, B, C tiles (the C tile pre-multiplied by v) are staged in 64-point
-// chunks, the next chunk fetched into registers while the MFMAs of the
-// current one run.  Each workgroup writes its split partial.
+// LDS address space pointer for the direct global-to-LDS loads
+#define CTD_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// g over one tile triple and one Gauss-point range (split-K).  The Y rows of
+// the A, B, C tiles and v are staged in 64-point chunks, each chunk loaded
+// straight from global memory into LDS (global_load_lds, 16-byte words, the
+// 64 lanes of a wave filling 64 consecutive words per instruction) while the
+// MFMAs of the previous chunk run.  The two chunk buffers are separate arrays
+// and the chunk loop is unrolled by two, so that the compiler can tell the
+// reads of one buffer from the loads into the other and does not wait on
+// them.  The Gauss-point tables Y and v have their row count padded to a
+// multiple of 64 with zero rows, so a chunk never reads past them.  Each
+// workgroup writes its split partial.
 template <class T>
-__global__ __launch_bounds__(256) void k_cubic_g(DevInst I, int d) {
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst I, int d) {
   typedef typename Vec4<T>::type V;
   constexpr int TS = kTileSq * kTile;
-  constexpr int WPS = (int)sizeof(T);              // 16-byte words per 16-wide row segment
-  constexpr int NW = 3 * WPS * kGChunk / 256;      // words per thread per chunk
-  constexpr int EPW = 16 / (int)sizeof(T);         // elements per word
+  constexpr int WPS = (int)sizeof(T);               // 16-byte words per 16-wide row segment
+  constexpr int RW = 3 * WPS;                       // words per Gauss point: A, B, C segments
+  constexpr int NW = RW * kGChunk / 256;            // words per thread per chunk
+  constexpr int EPW = 16 / (int)sizeof(T);          // elements per word
+  constexpr int VW = kGChunk * (int)sizeof(T) / 16; // words of v per chunk
   const DevAxis& A = I.ax[d];
   const T* Y = (const T*)(sizeof(T) == 4 ? (const void*)A.Xhf : (const void*)A.Xh);
   const T* vq = (const T*)(sizeof(T) == 4 ? (const void*)A.vf : (const void*)A.v);
@@ -1126,59 +1157,56 @@ __global__ __launch_bounds__(256) void k_cubic_g(DevInst I, int d) {
   const int qbeg = split * per;
   const int qend = qbeg + per < nq ? qbeg + per : nq;
   const int nchunk = qend > qbeg ? (qend - qbeg + kGChunk - 1) / kGChunk : 0;
-  __shared__ T ys[2][3][kGChunk][kTile];
+  // chunk buffers: point row, then the A, B, C segments of 16 values
+  __shared__ uint4 ysA[kGChunk * RW], ysB[kGChunk * RW];
+  __shared__ uint4 vsA[VW], vsB[VW];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  // word f of a chunk: row f / (3 WPS), array (f % (3 WPS)) / WPS, part f % WPS
-  auto load_chunk = [&](int q0, uint4* r) {
+  // word f = tid + 256 k of a chunk: point f / RW, segment (f % RW) / WPS,
+  // part f % WPS; it lands at word f of the buffer
+  auto load_chunk = [&](int q0, uint4* ys, uint4* vs) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       const int f = tid + 256 * k;
-      const int row = f / (3 * WPS), rem = f % (3 * WPS), arr = rem / WPS, part = rem % WPS;
-      const int q = q0 + row;
-      uint4 val = make_uint4(0, 0, 0, 0);
-      if (q < qend) {
-        val = *(const uint4*)(Y + (size_t)q * ldh + col0[arr] + part * EPW);
-        if (arr == 2) {
-          T* e = (T*)&val;
-          const T vv = vq[q];
-#pragma unroll
-          for (int x = 0; x < EPW; ++x) e[x] *= vv;
-        }
-      }
-      r[k] = val;
+      const int row = f / RW, rem = f % RW, arr = rem / WPS, part = rem % WPS;
+      const T* src = Y + (size_t)(q0 + row) * ldh + col0[arr] + part * EPW;
+      __builtin_amdgcn_global_load_lds((const void*)src, CTD_LDS(ys + 256 * k + 64 * w), 16, 0, 0);
     }
-  };
-  auto store_chunk = [&](int buf, const uint4* r) {
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      const int f = tid + 256 * k;
-      const int row = f / (3 * WPS), rem = f % (3 * WPS), arr = rem / WPS, part = rem % WPS;
-      *(uint4*)&ys[buf][arr][row][part * EPW] = r[k];
-    }
+    if (w == 0 && l < VW)
+      __builtin_amdgcn_global_load_lds((const void*)((const uint4*)(vq + q0) + l), CTD_LDS(vs), 16, 0, 0);
   };
   V acc[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) acc[r] = V{0, 0, 0, 0};
-  uint4 pre[NW];
-  load_chunk(qbeg, pre);
-  store_chunk(0, pre);
-  __syncthreads();
-  for (int ci = 0; ci < nchunk; ++ci) {
-    load_chunk(qbeg + (ci + 1) * kGChunk, pre);   // beyond qend: zeros, unused
-    const int b = ci & 1;
-#pragma unroll 4
+  auto compute = [&](const uint4* ysw, const uint4* vsw) {
+    const T* ys = (const T*)ysw;
+    const T* vs = (const T*)vsw;
+#pragma unroll
     for (int ks = 0; ks < kGChunk / 4; ++ks) {
       const int qq = ks * 4 + (l >> 4);
-      const T bval = ys[b][2][qq][l & 15];
-      const T ybv = ys[b][1][qq][l & 15];
+      const T* yr = ys + qq * (3 * kTile);
+      const T bval = yr[2 * kTile + (l & 15)];
+      const T ybv = yr[kTile + (l & 15)] * vs[qq];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T aval = ys[b][0][qq][w * 4 + r] * ybv;
+        const T aval = yr[w * 4 + r] * ybv;
         acc[r] = mfma16(aval, bval, acc[r]);
       }
     }
-    store_chunk(b ^ 1, pre);
+  };
+  auto step = [&](int ci, const uint4* ys, const uint4* vs, uint4* ysn, uint4* vsn) {
+    if (ci + 1 < nchunk) load_chunk(qbeg + (ci + 1) * kGChunk, ysn, vsn);
+    // the next chunk's loads are issued before the MFMAs
+    __builtin_amdgcn_sched_barrier(0);
+    compute(ys, vs);
+    // the next chunk has landed (the compiler's wait before the barrier
+    // covers the direct loads) and every wave is done with this buffer
     __syncthreads();
+  };
+  if (nchunk > 0) load_chunk(qbeg, ysA, vsA);
+  __syncthreads();
+  for (int ci = 0; ci < nchunk; ci += 2) {
+    step(ci, ysA, vsA, ysB, vsB);
+    if (ci + 1 < nchunk) step(ci + 1, ysB, vsB, ysA, vsA);
   }
   T* out = (T*)I.gpart + ((size_t)split * I.ntri + t) * TS;
 #pragma unroll
@@ -1507,7 +1535,7 @@ int cubic_h_blocks_per_cu(const DevInst& I) {
   static thread_local int last_nb[2] = {0, 0};
   const int k = I.mixed ? 1 : 0;
   const size_t shm = cubic_h_lds(I);
-  if (last_shm[k] != shm) {
+  if (last_nb[k] == 0 || last_shm[k] != shm) {
     int nb = 0;
     const void* f = I.mixed ? (const void*)k_cubic_h32<kHRows> : (const void*)k_cubic_h<double>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, shm) != hipSuccess || nb < 1) {

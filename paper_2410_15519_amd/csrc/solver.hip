@@ -357,8 +357,11 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.Xk, sizeof(double) * n * M);
     AL(X.MXk, sizeof(double) * n * M);
     AL(s->KXk[d], sizeof(double) * n * M);
-    AL(X.Xh, sizeof(double) * nq * s->Mkp_max);
-    if (mixed) AL(X.Xhf, sizeof(float) * nq * s->Mkp_max);
+    // Gauss-point tables: rows padded to a multiple of 64 with zero rows
+    // (the cubic g kernel loads whole 64-point chunks)
+    const size_t nqp = (nq + 63) / 64 * 64;
+    AL(X.Xh, sizeof(double) * nqp * s->Mkp_max);
+    if (mixed) AL(X.Xhf, sizeof(float) * nqp * s->Mkp_max);
     AL(X.X, sizeof(double) * n * M);
     AL(X.MX, sizeof(double) * n * M);
     AL(X.KX, sizeof(double) * n * M);
@@ -369,8 +372,8 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.rhs, sizeof(double) * n);
     AL(X.rpart, sizeof(double) * n * (size_t)((3 * s->Mcap + 63) / 64 + 1));
     AL(X.F, sizeof(double) * n);
-    AL(X.v, sizeof(double) * nq);
-    if (mixed) AL(X.vf, sizeof(float) * nq);
+    AL(X.v, sizeof(double) * nqp);
+    if (mixed) AL(X.vf, sizeof(float) * nqp);
     AL(X.gm, sizeof(double) * M);
     AL(X.gk, sizeof(double) * M);
     AL(X.gmk, sizeof(double) * M);
