@@ -69,6 +69,7 @@ struct DevAxis {
   const double* fdV;   // n x n row-major generalised eigenvectors
   const double* fdmu;  // n eigenvalues
   double* fdz;         // kFdSplit x n partial projections V^T b
+  double* fdu;         // kFdKb x n partial back-projections (split over eigenvectors)
 };
 
 // Scalars shared by kernels of one instance (device memory).
@@ -128,7 +129,7 @@ hipError_t launch_band_mv(const DevAxis& A, const double* band, const double* X,
 hipError_t launch_init_mode(const DevInst& I, int64_t step, int mode, int warm,
                             hipStream_t st);
 hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
-                           hipStream_t st);
+                           hipStream_t st, int nparts = 0);
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
@@ -138,6 +139,7 @@ hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
 hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st);
 size_t cubic_h_lds(const DevInst& I);   // dynamic LDS bytes of the h kernel
+size_t cubic_h_lds_total(const DevInst& I);   // dynamic + static LDS bytes of the h kernel
 int cubic_h_rows(const DevInst& I);     // Gauss points per workgroup of the h kernel
 int cubic_h_blocks_per_cu(const DevInst& I);   // resident h workgroups per CU
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st);
@@ -156,6 +158,7 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    double* x, int count, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
 constexpr int kFdSplit = 8;   // row splits of the projection V^T b
+constexpr int kFdKb = 8;      // eigenvector splits of the back-projection V z
 // x = V diag(1 / (alpha + beta mu)) V^T b into ax[d].u, alpha/beta from the
 // fixed factors (two launches; the normalisation follows separately)
 hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st);

@@ -87,7 +87,7 @@ __device__ __forceinline__ double band_row(const double* band, int n, int B,
 // ------------------------------------------------------------ quad eval
 // Xh[q, a] = sk_a^pw * sum_j Phi[q, j] X^k[st + j, a]; zero for a >= Mk.
 __global__ void k_quad_eval(DevAxis A, int Mk, int ldh, const double* sk,
-                            double pw, int mixed) {
+                            double pw, int mixed, int tile_major) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)A.nq * ldh;
   if (idx >= total) return;
@@ -102,7 +102,19 @@ __global__ void k_quad_eval(DevAxis A, int Mk, int ldh, const double* sk,
     val *= pow(sk[a], pw);
   }
   A.Xh[idx] = val;
-  if (mixed) A.Xhf[idx] = (float)val;
+  if (mixed) {
+    // The FP32 copy of the 3D path is tile-major over the 64-padded point
+    // count, [a / 16][q][slot]: a tile's values at consecutive points are
+    // contiguous.  Inside a tile, mode i sits in slot 4 (i % 4) + i / 4, so
+    // that the 16-byte word g holds modes g, g+4, g+8, g+12.
+    size_t dst = idx;
+    if (tile_major) {
+      const size_t nqp = (size_t)(A.nq + 63) / 64 * 64;
+      const int i = a & 15;
+      dst = ((size_t)(a >> 4) * nqp + q) * kTile + ((i & 3) << 2) + (i >> 2);
+    }
+    A.Xhf[dst] = (float)val;
+  }
 }
 
 hipError_t launch_quad_eval(const DevInst& I, int d, hipStream_t st) {
@@ -110,7 +122,7 @@ hipError_t launch_quad_eval(const DevInst& I, int d, hipStream_t st) {
   size_t total = (size_t)A.nq * I.Mkp;
   int blocks = (int)((total + 255) / 256);
   if (blocks == 0) return hipSuccess;
-  k_quad_eval<<<blocks, 256, 0, st>>>(A, I.Mk, I.Mkp, I.sk, 1.0 / I.dim, I.mixed);
+  k_quad_eval<<<blocks, 256, 0, st>>>(A, I.Mk, I.Mkp, I.sk, 1.0 / I.dim, I.mixed, I.dim == 3);
   return hipGetLastError();
 }
 
@@ -222,13 +234,27 @@ __device__ __forceinline__ double band_row_lds(const double* band, int n, const 
 // the sums of the unnormalised u are rescaled by 1/sigma afterwards.
 // red: >= 96 doubles of LDS; ul: 3n doubles of scratch (LDS) for u, M u, K u.
 template <int B>
-__device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, double* red, double* ul) {
+__device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, double* red, double* ul,
+                              int nparts = 0) {
   DevAxis& A = I.ax[d];
   DevScalars* sc = I.sc;
   const int n = A.n;
   double* ml = ul + n;
   double* kl = ul + 2 * n;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) ul[i] = A.u[i];
+  // the solved factor: u, or the sum of the back-projection partials (fixed order)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double v = 0.0;
+    if (nparts == 0) {
+      v = A.u[i];
+    } else {
+      double p[kFdKb];
+#pragma unroll
+      for (int k = 0; k < kFdKb; ++k) p[k] = A.fdu[(size_t)k * n + i];
+#pragma unroll
+      for (int k = 0; k < kFdKb; ++k) v += p[k];
+    }
+    ul[i] = v;
+  }
   __syncthreads();
   // u.Mu, u.Ku, u.u, u.up, up.up and max|u|
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -297,21 +323,21 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
 }
 
 template <int B>
-__global__ __launch_bounds__(1024) void k_finalize(DevInst I, int d, int sweep, int from_init) {
+__global__ __launch_bounds__(1024) void k_finalize(DevInst I, int d, int sweep, int from_init, int nparts) {
   __shared__ double red[96];
   extern __shared__ double ul[];
-  finalize_body<B>(I, d, sweep, from_init, red, ul);
+  finalize_body<B>(I, d, sweep, from_init, red, ul, nparts);
 }
 
 hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
-                           hipStream_t st) {
+                           hipStream_t st, int nparts) {
   const int n = I.ax[d].n;
   const size_t shm = sizeof(double) * 3 * (size_t)n;
   const int nt = n >= 1024 ? 1024 : (n + 63) / 64 * 64;
   switch (I.ax[d].B) {
-    case 3: k_finalize<3><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
-    case 5: k_finalize<5><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
-    case 7: k_finalize<7><<<1, nt, shm, st>>>(I, d, sweep, from_init); break;
+    case 3: k_finalize<3><<<1, nt, shm, st>>>(I, d, sweep, from_init, nparts); break;
+    case 5: k_finalize<5><<<1, nt, shm, st>>>(I, d, sweep, from_init, nparts); break;
+    case 7: k_finalize<7><<<1, nt, shm, st>>>(I, d, sweep, from_init, nparts); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -335,6 +361,7 @@ __global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v
     else if (idx < 2 * M) { col = A.KX + (size_t)(idx - M) * n; out = A.gk + (idx - M); }
     else { col = A.MXk + (size_t)(idx - 2 * M) * n; out = A.gmk + (idx - 2 * M); }
     double s = 0.0;
+#pragma unroll 16
     for (int i = l; i < n; i += 64) s += col[i] * A.u[i];
     s = wave_sum(s);
     if (l == 0) *out = s;
@@ -970,60 +997,65 @@ __global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk
     A.fdz[(size_t)blockIdx.y * n + k] = part[0][l] + part[1][l] + part[2][l] + part[3][l];
 }
 
-// Back-projection: workgroup of 16 rows, 4 per wave computed together (lanes
-// along the eigenvector index); every workgroup rebuilds the scaled
-// coefficients z_k / (alpha + beta mu_k) in LDS (kFdSplit partials, fixed
-// order).
+// Back-projection, split over the eigenvectors: workgroup (row block of 32,
+// eigenvector block kb of ceil(n / kFdKb)) forms its scaled coefficients
+// z_k / (alpha + beta mu_k) in LDS (kFdSplit projection partials, fixed
+// order) and writes the partial sums over its block of 8 rows per wave (lanes
+// along k, all loads of a lane issued together); the finalize pass adds the
+// kFdKb partials in fixed order.
 __global__ __launch_bounds__(256) void k_fd_apply(DevInst I, int d) {
   DevAxis& A = I.ax[d];
   const int n = A.n;
-  extern __shared__ double zs[];
+  const int K = (n + kFdKb - 1) / kFdKb;
+  const int k0 = blockIdx.y * K;
+  const int kn = k0 + K < n ? K : (n > k0 ? n - k0 : 0);
+  extern __shared__ double zs[];    // K doubles
   __shared__ double ab[2];
   if (threadIdx.x == 0) {
     directional_coeffs(I, d, ab[0], ab[1]);
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
       I.sc->alpha[d] = ab[0];
       I.sc->beta[d] = ab[1];
     }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+  for (int j = threadIdx.x; j < kn; j += blockDim.x) {
     double z[kFdSplit];
 #pragma unroll
-    for (int s = 0; s < kFdSplit; ++s) z[s] = A.fdz[(size_t)s * n + k];
+    for (int s = 0; s < kFdSplit; ++s) z[s] = A.fdz[(size_t)s * n + k0 + j];
     double t = 0.0;
 #pragma unroll
     for (int s = 0; s < kFdSplit; ++s) t += z[s];
-    zs[k] = t / (ab[0] + ab[1] * A.fdmu[k]);
+    zs[j] = t / (ab[0] + ab[1] * A.fdmu[k0 + j]);
   }
   __syncthreads();
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ib = blockIdx.x * 16 + w * 4;
-  int rows[4];
+  const int ib = blockIdx.x * 32 + w * 8;
+  double acc[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) rows[r] = ib + r < n ? ib + r : n - 1;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k0 = l; k0 < n; k0 += 256) {
-    double v[4][4];
+  for (int r = 0; r < 8; ++r) acc[r] = 0.0;
+  for (int j0 = l; j0 < kn; j0 += 128) {
+    double v[2][8];
 #pragma unroll
-    for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = k0 + 64 * h;
-        v[h][r] = k < n ? A.fdV[(size_t)rows[r] * n + k] : 0.0;
+      for (int r = 0; r < 8; ++r) {
+        const int j = j0 + 64 * h;
+        const int row = ib + r < n ? ib + r : n - 1;
+        v[h][r] = j < kn ? A.fdV[(size_t)row * n + k0 + j] : 0.0;
       }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int k = k0 + 64 * h;
-      const double z = k < n ? zs[k] : 0.0;
+    for (int h = 0; h < 2; ++h) {
+      const int j = j0 + 64 * h;
+      const double z = j < kn ? zs[j] : 0.0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] += v[h][r] * z;
+      for (int r = 0; r < 8; ++r) acc[r] += v[h][r] * z;
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < 8; ++r) {
     const double t = wave_sum(acc[r]);
-    if (l == 0 && ib + r < n) A.u[ib + r] = t;
+    if (l == 0 && ib + r < n) A.fdu[(size_t)blockIdx.y * n + ib + r] = t;
   }
 }
 
@@ -1035,7 +1067,8 @@ hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st) {
   k_fd_project<<<dim3((n + 63) / 64, kFdSplit), 256, sizeof(double) * per, st>>>(I, d, rhs_chunks(I, M, 0));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_fd_apply<<<(n + 15) / 16, 256, sizeof(double) * (size_t)n, st>>>(I, d);
+  const size_t K = (size_t)(n + kFdKb - 1) / kFdKb;
+  k_fd_apply<<<dim3((n + 31) / 32, kFdKb), 256, sizeof(double) * K, st>>>(I, d);
   return hipGetLastError();
 }
 
@@ -1157,18 +1190,30 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
   const int qbeg = split * per;
   const int qend = qbeg + per < nq ? qbeg + per : nq;
   const int nchunk = qend > qbeg ? (qend - qbeg + kGChunk - 1) / kGChunk : 0;
-  // chunk buffers: point row, then the A, B, C segments of 16 values
+  // chunk buffers.  FP32 (tile-major table): segment (A, B, C), then point,
+  // then the 16 slots of the tile; FP64 (row-major table): point, then
+  // segments of 16 values.
+  constexpr bool TM = sizeof(T) == 4;
   __shared__ uint4 ysA[kGChunk * RW], ysB[kGChunk * RW];
   __shared__ uint4 vsA[VW], vsB[VW];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  // word f = tid + 256 k of a chunk: point f / RW, segment (f % RW) / WPS,
-  // part f % WPS; it lands at word f of the buffer
+  const size_t nqp = (size_t)(nq + 63) / 64 * 64;
+  // word f = tid + 256 k of a chunk lands at word f of the buffer.  FP32:
+  // segment f / 256 (= k), point (f % 256) / 4, part f % 4, so the 64 lanes
+  // of a wave read 1 KB of consecutive memory; FP64: point f / RW, segment
+  // (f % RW) / WPS, part f % WPS.
   auto load_chunk = [&](int q0, uint4* ys, uint4* vs) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       const int f = tid + 256 * k;
-      const int row = f / RW, rem = f % RW, arr = rem / WPS, part = rem % WPS;
-      const T* src = Y + (size_t)(q0 + row) * ldh + col0[arr] + part * EPW;
+      const T* src;
+      if (TM) {
+        const int arr = f >> 8, row = (f & 255) >> 2, part = f & 3;
+        src = Y + ((size_t)(col0[arr] >> 4) * nqp + q0 + row) * kTile + part * EPW;
+      } else {
+        const int row = f / RW, rem = f % RW, arr = rem / WPS, part = rem % WPS;
+        src = Y + (size_t)(q0 + row) * ldh + col0[arr] + part * EPW;
+      }
       __builtin_amdgcn_global_load_lds((const void*)src, CTD_LDS(ys + 256 * k + 64 * w), 16, 0, 0);
     }
     if (w == 0 && l < VW)
@@ -1180,15 +1225,21 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
   auto compute = [&](const uint4* ysw, const uint4* vsw) {
     const T* ys = (const T*)ysw;
     const T* vs = (const T*)vsw;
+    // mode e of segment s at point qq: FP32 slot 4 (e % 4) + e / 4
+    constexpr int SS = TM ? kGChunk * kTile : kTile;   // segment stride
+    constexpr int PS = TM ? kTile : 3 * kTile;         // point stride
+    const int e = l & 15;
+    const int es = TM ? ((e & 3) << 2) + (e >> 2) : e;
 #pragma unroll
     for (int ks = 0; ks < kGChunk / 4; ++ks) {
       const int qq = ks * 4 + (l >> 4);
-      const T* yr = ys + qq * (3 * kTile);
-      const T bval = yr[2 * kTile + (l & 15)];
-      const T ybv = yr[kTile + (l & 15)] * vs[qq];
+      const T* yr = ys + qq * PS;
+      const T bval = yr[2 * SS + es];
+      const T ybv = yr[SS + es] * vs[qq];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const T aval = yr[w * 4 + r] * ybv;
+        // mode 4 w + r of the A segment
+        const T aval = yr[TM ? (r << 2) + w : w * 4 + r] * ybv;
         acc[r] = mfma16(aval, bval, acc[r]);
       }
     }
@@ -1246,12 +1297,22 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
   if (e_other >= 0) {
     const int t = (int)(idx / per);
     const T* go = (const T*)I.ax[e_other].g;
-    const T val = (T)((double)I.tri[t].w * s * (double)go[idx]);
+    const int4 tr = I.tri[t];
+    const int e = (int)(idx - (size_t)t * per);
+    // tile element e = (a 16 + b) 16 + c.  When the first two tiles coincide
+    // the h contraction runs over pairs a <= b only: weight 2 off the
+    // diagonal, 1 on it, 0 below (S is symmetric in a, b there).
+    double wt = (double)tr.w;
+    if (tr.x == tr.y) {
+      const int a = e >> 8, b = (e >> 4) & 15;
+      wt *= a < b ? 2.0 : (a == b ? 1.0 : 0.0);
+    }
+    const T val = (T)(wt * s * (double)go[idx]);
     size_t dst = idx;
     if (sizeof(T) == 4) {
       // element e = 64 ks + l of the tile (k-step ks, lane l) goes where lane l
       // finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
-      const int e = (int)(idx - (size_t)t * per), ks = e >> 6, l = e & 63;
+      const int ks = e >> 6, l = e & 63;
       dst = (size_t)t * per + ((((ks >> 2) << 6) + l) << 2) + (ks & 3);
     }
     ((T*)I.S)[dst] = val;
@@ -1259,18 +1320,17 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
 }
 
 
-// h over a 64-row Gauss-point tile and a contiguous range of tile triples.
-// The S tile of the next triple is fetched into registers while the MFMAs of
-// the current one run, then stored to the other LDS buffer (one barrier per
-// triple).
 // h for the FP32 path.  A workgroup of 4 waves owns 64 Gauss points (a
 // 16-point MFMA block per wave) and walks its share of the tile triples.
 // Only the S tiles are staged in LDS (32 KB, double-buffered; in the order
 // k_cubic_gred<float> writes them: lane l finds k-steps 4j..4j+3 in one
 // 16-byte word), so several workgroups share a CU.  The factor values of a
-// lane's Gauss point come from L2 straight into VGPRs, and the S tile and
-// factor values of the next triple are fetched while the MFMAs of the
-// current one run.
+// lane's Gauss point come from L2 straight into VGPRs (the tile-major table
+// makes the 16 points of a wave one contiguous kilobyte per tile, and puts a
+// lane group's four B-operand modes in one 16-byte word); the factor values
+// of the next triple are fetched while the MFMAs of the current one run, the
+// S tile of the next triple is loaded and stored to the other buffer after
+// them (one barrier per triple).
 constexpr int kHRows = 1;              // 16-point MFMA blocks per wave (2 measured slower: occupancy)
 constexpr int kHQ = 64 * kHRows;       // Gauss points per workgroup
 
@@ -1291,14 +1351,16 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
   const int t0 = split * per;
   const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
   // A-operand rows of this lane; rows past the end read the last point (their
-  // MFMA output rows are never stored)
-  const float* xrow[HR];
+  // MFMA output rows are never stored).  The table is tile-major over the
+  // 64-padded point count, mode i of a tile in slot 4 (i % 4) + i / 4.
+  const size_t nqp = (size_t)(nq + 63) / 64 * 64;
+  int qa[HR];
 #pragma unroll
   for (int rb = 0; rb < HR; ++rb) {
-    int qa = qw + rb * 16 + (l & 15);
-    qa = qa < nq ? qa : nq - 1;
-    xrow[rb] = X + (size_t)qa * ldh;
+    const int q = qw + rb * 16 + (l & 15);
+    qa[rb] = q < nq ? q : nq - 1;
   }
+  const int es = (((l & 15) & 3) << 2) + ((l & 15) >> 2);   // slot of mode l % 16
   // prefetch registers; loads use a clamped triple index so they are
   // unconditional (the surplus S words land in the idle buffer)
   const int tlast = t1 > t0 ? t1 - 1 : 0;
@@ -1312,10 +1374,10 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
     const size_t base_ = (size_t)(tt) * TW + tid;                               \
     _Pragma("unroll") for (int v = 0; v < TW / 256; ++v) pre[v] = Sp[base_ + v * 256]; \
     _Pragma("unroll") for (int rb = 0; rb < HR; ++rb) {                         \
-      const float4* ar_ = (const float4*)(xrow[rb] + tr_.x * kTile);            \
+      const float4* ar_ = (const float4*)(X + ((size_t)tr_.x * nqp + qa[rb]) * kTile); \
       _Pragma("unroll") for (int v = 0; v < 4; ++v) XA[rb][v] = ar_[v];         \
-      _Pragma("unroll") for (int m = 0; m < 4; ++m)                             \
-        XB[rb][m] = xrow[rb][tr_.y * kTile + 4 * m + (l >> 4)];                 \
+      const float4 b_ = *(const float4*)(X + ((size_t)tr_.y * nqp + qa[rb]) * kTile + 4 * (l >> 4)); \
+      XB[rb][0] = b_.x; XB[rb][1] = b_.y; XB[rb][2] = b_.z; XB[rb][3] = b_.w;    \
     }                                                                           \
   } while (0)
   H32_FETCH(t0 < tlast ? t0 : tlast, xa4, xb);
@@ -1340,7 +1402,7 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
         int q = qw + rb * 16 + mfma_row<float>(l, r);
         q = q < nq ? q : nq - 1;
         double v = ((double)acc[rb][0][r] + (double)acc[rb][1][r]) *
-                   (double)X[(size_t)q * ldh + curC * kTile + (l & 15)];
+                   (double)X[((size_t)curC * nqp + q) * kTile + es];
         v += __shfl_xor(v, 8, 64);
         v += __shfl_xor(v, 4, 64);
         v += __shfl_xor(v, 2, 64);
@@ -1367,7 +1429,8 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
         const int ks = 4 * j + u;
 #pragma unroll
         for (int rb = 0; rb < HR; ++rb)
-          acc[rb][u & 1] = mfma16(xa4[rb][ks >> 4][(ks >> 2) & 3] * xb[rb][ks & 3], b4[u], acc[rb][u & 1]);
+          // mode a = ks / 4 of the first tile: word a % 4, slot a / 4
+          acc[rb][u & 1] = mfma16(xa4[rb][(ks >> 2) & 3][ks >> 4] * xb[rb][ks & 3], b4[u], acc[rb][u & 1]);
       }
     }
     {
@@ -1472,8 +1535,11 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
     for (int a = 0; a < kTile; ++a) xa[a] = xs[rowA * ldx + A0 + a];
 #pragma unroll
     for (int m = 0; m < 4; ++m) xb[m] = xs[rowA * ldx + B0 + 4 * m + (l >> 4)];
+    // symmetric pair skip when the first two tiles coincide (as in the FP32 kernel)
+    const bool full = tr.x != tr.y;
 #pragma unroll
     for (int ks = 0; ks < kTileSq / 4; ++ks) {
+      if ((ks & 3) < (ks >> 4) && !full) continue;
       const T aval = xa[ks >> 2] * xb[ks & 3];
       const T bval = ss[(4 * ks + (l >> 4)) * kTile + (l & 15)];
       acc = mfma16(aval, bval, acc);
@@ -1527,6 +1593,8 @@ size_t cubic_h_lds(const DevInst& I) {
 }
 
 int cubic_h_rows(const DevInst& I) { return I.mixed ? kHQ : 64; }
+
+size_t cubic_h_lds_total(const DevInst& I) { return cubic_h_lds(I); }
 
 int cubic_h_blocks_per_cu(const DevInst& I) {
   // resident workgroups per CU as the runtime computes them (registers and
@@ -1930,7 +1998,7 @@ hipError_t configure_kernels() {
   const void* ks[] = {(const void*)k_solve_bcr<3, false>, (const void*)k_solve_bcr<5, false>,
                       (const void*)k_solve_bcr<7, false>, (const void*)k_band_solve_bcr<3, false>,
                       (const void*)k_band_solve_bcr<5, false>, (const void*)k_band_solve_bcr<7, false>,
-                      (const void*)k_cubic_h<double>, (const void*)k_cubic_h<float>,
+                      (const void*)k_cubic_h<double>,
                       (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
                       (const void*)k_reconstruct_tile<double>};
   for (const void* k : ks)

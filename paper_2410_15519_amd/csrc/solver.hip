@@ -420,6 +420,7 @@ int alloc_instance(ctd_solver* s, int m0) {
       const size_t n = T.n;
       DevAxis& X = I.ax[d];
       AL(X.fdz, sizeof(double) * kFdSplit * n);
+      AL(X.fdu, sizeof(double) * kFdKb * n);
       int same = -1;
       for (int e = 0; e < d; ++e) {
         const AxisTables& U = s->ax[e];
@@ -587,7 +588,7 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
           Work ws = w_solve(s, d);
           if (s->use_fd[d]) {
             LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_fd(s->I, d, M, s->stream));
-            LAUNCH(s, CTD_K_FINALIZE, 0.0, 0.0, launch_finalize(s->I, d, it, 0, s->stream));
+            LAUNCH(s, CTD_K_FINALIZE, 0.0, 0.0, launch_finalize(s->I, d, it, 0, s->stream, kFdKb));
           } else {
             LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
           }
@@ -708,7 +709,7 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
       DevInst probe{};
       probe.mixed = p->precision == CTD_PREC_MIXED;
       probe.Mkp = std::max(kTile, round_up(std::max(p->max_modes, m0), kTile));
-      if (cubic_h_lds(probe) > (size_t)max_lds_bytes()) {
+      if (cubic_h_lds_total(probe) > (size_t)max_lds_bytes()) {
         g_init_error = "max_modes exceeds the LDS-resident cubic evaluation of this precision";
         return CTD_EUNSUPPORTED;
       }
