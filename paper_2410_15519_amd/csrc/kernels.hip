@@ -229,6 +229,37 @@ __device__ __forceinline__ double band_row_lds(const double* band, int n, const 
   return y;
 }
 
+// The same product with the 2B+1 band values of row i loaded ahead (into
+// registers, before the vector x is ready); same summation order.
+template <int B>
+struct BandRow {
+  double c0, up[B], lo[B];
+};
+
+template <int B>
+__device__ __forceinline__ void band_row_load(const double* band, int n, int i, BandRow<B>& r) {
+  r.c0 = band[i];
+#pragma unroll
+  for (int t = 1; t <= B; ++t) {
+    const int im = i - t >= 0 ? i - t : 0;
+    r.up[t - 1] = band[(size_t)t * n + i];
+    r.lo[t - 1] = band[(size_t)t * n + im];
+  }
+}
+
+template <int B>
+__device__ __forceinline__ double band_row_apply(const BandRow<B>& r, int n, const double* x, int i) {
+  double y = r.c0 * x[i];
+#pragma unroll
+  for (int t = 1; t <= B; ++t) {
+    const int ip = i + t < n ? i + t : n - 1;
+    const int im = i - t >= 0 ? i - t : 0;
+    y += r.up[t - 1] * x[ip];
+    y += (i - t >= 0 ? r.lo[t - 1] : 0.0) * x[im];
+  }
+  return y;
+}
+
 // Normalise the solved factor u_d to unit M-norm (sigma = its norm), cache
 // M u, K u, and the Gram scalars of the fixed-point test.  One fused pass:
 // the sums of the unnormalised u are rescaled by 1/sigma afterwards.
@@ -241,6 +272,18 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
   const int n = A.n;
   double* ml = ul + n;
   double* kl = ul + 2 * n;
+  // one row per thread: the band rows and the previous factor value are
+  // requested before the solved factor is staged (bandwidths up to 5: wider
+  // rows would not fit the registers of a 1024-thread workgroup)
+  const bool one = B <= 5 && n <= (int)blockDim.x;
+  const int i1 = threadIdx.x < n ? threadIdx.x : n - 1;
+  BandRow<B> rm, rk;
+  double up1 = 0.0;
+  if (one) {
+    band_row_load<B>(A.Mb, n, i1, rm);
+    band_row_load<B>(A.Kb, n, i1, rk);
+    up1 = A.up[i1];
+  }
   // the solved factor: u, or the sum of the back-projection partials (fixed order)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double v = 0.0;
@@ -260,11 +303,11 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   double um = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double mu = band_row_lds<B>(A.Mb, n, ul, i);
-    const double ku = band_row_lds<B>(A.Kb, n, ul, i);
+    const double mu = one ? band_row_apply<B>(rm, n, ul, i) : band_row_lds<B>(A.Mb, n, ul, i);
+    const double ku = one ? band_row_apply<B>(rk, n, ul, i) : band_row_lds<B>(A.Kb, n, ul, i);
     ml[i] = mu;
     kl[i] = ku;
-    const double u = ul[i], up = A.up[i];
+    const double u = ul[i], up = one ? up1 : A.up[i];
     acc[0] += u * mu;
     acc[1] += u * ku;
     acc[2] += u * u;
@@ -412,6 +455,16 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
   const int y = blockIdx.y;
   if (y < nchunk) {
     const int ctot = rhs_columns(I, M, load_only);
+    // 16 columns per wave, loaded before the coefficients are ready
+    double cv[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = y * 64 + w * 16 + cc;
+      const double* col = c < I.Mk ? A.MXk + (size_t)c * n
+                                   : (c < I.Mk + M ? A.MX + (size_t)(c - I.Mk) * n
+                                                   : A.KX + (size_t)(c - I.Mk - M) * n);
+      cv[cc] = (c < ctot && i < n) ? col[i] : 0.0;
+    }
     const double ck = load_only ? -I.omega : (I.dim == 3 ? I.c + I.omega : I.c);
     if (tid < 64) {
       const int c = y * 64 + tid;
@@ -436,20 +489,10 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
       coef[tid] = v;
     }
     __syncthreads();
-    // 16 columns per wave, all loads issued before the sum (fixed order)
     double acc = 0.0;
     if (i < n) {
-      double v[16];
 #pragma unroll
-      for (int cc = 0; cc < 16; ++cc) {
-        const int c = y * 64 + w * 16 + cc;
-        const double* col = c < I.Mk ? A.MXk + (size_t)c * n
-                                     : (c < I.Mk + M ? A.MX + (size_t)(c - I.Mk) * n
-                                                     : A.KX + (size_t)(c - I.Mk - M) * n);
-        v[cc] = c < ctot ? col[i] : 0.0;
-      }
-#pragma unroll
-      for (int cc = 0; cc < 16; ++cc) acc += coef[w * 16 + cc] * v[cc];
+      for (int cc = 0; cc < 16; ++cc) acc += coef[w * 16 + cc] * cv[cc];
     }
     part[tid] = acc;
     __syncthreads();
@@ -970,6 +1013,16 @@ __global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk
   const int i1 = i0 + per < n ? i0 + per : n;
   extern __shared__ double bl[];    // per doubles
   __shared__ double part[4][64];
+  const int kk = k < n ? k : n - 1;    // past the end: read in range, never stored
+  // the first 32 rows of this wave's share of V are requested before the
+  // right-hand side is staged (rows r = w + 4 u)
+  constexpr int kPre = 32;
+  double vp[kPre];
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int r = w + 4 * u;
+    vp[u] = r < i1 - i0 ? A.fdV[(size_t)(i0 + r) * n + kk] : 0.0;
+  }
   for (int r = threadIdx.x; r < i1 - i0; r += blockDim.x) {
     double b = 0.0;
     for (int y = 0; y <= nchunk; ++y) b += A.rpart[(size_t)y * n + i0 + r];
@@ -977,8 +1030,12 @@ __global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk
   }
   __syncthreads();
   double acc = 0.0;
-  const int kk = k < n ? k : n - 1;    // past the end: read in range, never stored
-  for (int r0 = w; r0 < i1 - i0; r0 += 32) {
+#pragma unroll
+  for (int u = 0; u < kPre; ++u) {
+    const int r = w + 4 * u;
+    if (r < i1 - i0) acc += vp[u] * bl[r];
+  }
+  for (int r0 = w + 4 * kPre; r0 < i1 - i0; r0 += 32) {
     double v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1011,6 +1068,19 @@ __global__ __launch_bounds__(256) void k_fd_apply(DevInst I, int d) {
   const int kn = k0 + K < n ? K : (n > k0 ? n - k0 : 0);
   extern __shared__ double zs[];    // K doubles
   __shared__ double ab[2];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int ib = blockIdx.x * 32 + w * 8;
+  // the eigenvector values of the first 128 columns of the block are
+  // requested before the coefficients are formed
+  double vp[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int j = l + 64 * h;
+      const int row = ib + r < n ? ib + r : n - 1;
+      vp[h][r] = j < kn ? A.fdV[(size_t)row * n + k0 + j] : 0.0;
+    }
   if (threadIdx.x == 0) {
     directional_coeffs(I, d, ab[0], ab[1]);
     if (blockIdx.x == 0 && blockIdx.y == 0) {
@@ -1029,12 +1099,17 @@ __global__ __launch_bounds__(256) void k_fd_apply(DevInst I, int d) {
     zs[j] = t / (ab[0] + ab[1] * A.fdmu[k0 + j]);
   }
   __syncthreads();
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int ib = blockIdx.x * 32 + w * 8;
   double acc[8];
 #pragma unroll
   for (int r = 0; r < 8; ++r) acc[r] = 0.0;
-  for (int j0 = l; j0 < kn; j0 += 128) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int j = l + 64 * h;
+    const double z = j < kn ? zs[j] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) acc[r] += vp[h][r] * z;
+  }
+  for (int j0 = l + 128; j0 < kn; j0 += 128) {
     double v[2][8];
 #pragma unroll
     for (int h = 0; h < 2; ++h)

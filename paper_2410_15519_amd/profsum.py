@@ -53,6 +53,14 @@ def trace(db: str, title: str, cmd: str) -> str:
     for r in rows:
         out.append(f"| {short_name(r[0])} | ({r[1]}, {r[2]}) | {r[3]} | {r[4]} | {r[5]:.1f} | "
                    f"{r[6]:.1f} | {r[7]:.1f} | {r[8]:.1f} | {r[9]} | {r[10]} | {r[11]} | {r[12]} |")
+    by_name = collections.defaultdict(lambda: [0, 0.0])
+    for name, n, tot in con.execute("select name, count(*), sum(duration)/1e6 from kernels group by name, grid_x, grid_y"):
+        by_name[short_name(name)][0] += n
+        by_name[short_name(name)][1] += tot
+    out += ["", "All grids of a kernel together:", "",
+            "| kernel | launches | avg us | total ms |", "|---|---|---|---|"]
+    for name, (n, tot) in sorted(by_name.items(), key=lambda kv: -kv[1][1])[:20]:
+        out.append(f"| {name} | {n} | {1e3 * tot / max(1, n):.1f} | {tot:.1f} |")
     return "\n".join(out) + "\n"
 
 
