@@ -348,6 +348,20 @@ def main():
         fp64["accuracy_steps"] = args.warmup + args.steps
         del Up, Uref, U64
         torch.cuda.empty_cache()
+        # leg 3e: the arithmetic of the mixed cubic contraction alone, at the
+        # benchmarked size and mode count: the projected load of each
+        # direction for 128 seeded modes and a seeded factor, mixed against FP64
+        inst128 = make_instance(args.workload, m0=inst.max_modes)
+        rng = np.random.default_rng(17)
+        uu = [rng.uniform(-1.0, 1.0, int(m)) for m in inst128.nodes]
+        loads = {}
+        for prec in ("mixed", "fp64"):
+            with ctd.Solver(inst128, precision=prec) as sl:
+                loads[prec] = [sl.nonlinear_load(d, uu) for d in range(inst128.dim)]
+        fp64["rel_l2_cubic_load_mixed_vs_fp64"] = max(
+            float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(loads["mixed"], loads["fp64"]))
+        fp64["cubic_load_modes"] = int(inst.max_modes)
+        del loads, inst128
     batched = served = None
     if not args.no_serve:
         batched = batched_leg(ctd)
