@@ -1496,11 +1496,16 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
       curC = cz;
     }
     const float4* sq = sb + ((t - t0) & 1) * TW;
+    // k-step ks = 4 j + u pairs mode a = j of the first tile with b = 4 u + g
+    // of the second; when the two tiles coincide, the k-steps whose four b
+    // all lie below a (u < j / 4) meet only zero weights in S and are skipped
+    const bool full = I.tri[t].x != I.tri[t].y;
 #pragma unroll
     for (int j = 0; j < kTileSq / 16; ++j) {
       const float4 b4 = sq[j * 64 + l];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
+        if (u < (j >> 2) && !full) continue;
         const int ks = 4 * j + u;
 #pragma unroll
         for (int rb = 0; rb < HR; ++rb)
