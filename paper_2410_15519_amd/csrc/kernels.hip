@@ -272,6 +272,26 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
   const int n = A.n;
   double* ml = ul + n;
   double* kl = ul + 2 * n;
+  // the other directions' Gram scalars of the fixed-point test, requested
+  // at the start (they were written by earlier launches)
+  double puu_o = 1.0, pupup_o = 1.0, puup_o = 1.0, sigma_prev = 0.0;
+  if (threadIdx.x == 0 && !from_init && d == I.dim - 1) {
+    double a0[kMaxDim], a1[kMaxDim], a2[kMaxDim];
+#pragma unroll
+    for (int e = 0; e < kMaxDim; ++e) {
+      a0[e] = sc->uu[e];
+      a1[e] = sc->upup[e];
+      a2[e] = sc->uup[e];
+    }
+    sigma_prev = sc->sigma_prev;
+#pragma unroll
+    for (int e = 0; e < kMaxDim; ++e) {
+      if (e >= I.dim || e == d) continue;
+      puu_o *= a0[e];
+      pupup_o *= a1[e];
+      puup_o *= a2[e];
+    }
+  }
   // one row per thread: the band rows and the previous factor value are
   // requested before the solved factor is staged (bandwidths up to 5: wider
   // rows would not fit the registers of a 1024-thread workgroup)
@@ -344,15 +364,11 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
       if (zero) sc->zero = 1;
       if (d == I.dim - 1) {
         if (sweep >= 2) {
-          double puu = 1.0, pupup = 1.0, puup = 1.0;
-          for (int e = 0; e < I.dim; ++e) {
-            puu *= sc->uu[e];
-            pupup *= sc->upup[e];
-            puup *= sc->uup[e];
-          }
+          // products over the directions, in direction order (this one last)
+          const double puu = puu_o * uu, pupup = pupup_o * upup, puup = puup_o * uup;
           const double nn = sigma * sigma * puu;
-          const double oo = sc->sigma_prev * sc->sigma_prev * pupup;
-          const double no = sigma * sc->sigma_prev * puup;
+          const double oo = sigma_prev * sigma_prev * pupup;
+          const double no = sigma * sigma_prev * puup;
           double r2 = nn + oo - 2.0 * no;
           r2 = r2 > 0.0 ? r2 : 0.0;
           double r = nn > 0.0 ? sqrt(r2 / nn) : 0.0;
@@ -2031,10 +2047,120 @@ __global__ __launch_bounds__(256) void k_reconstruct_tile(DevInst I, int M, T* o
 
 size_t reconstruct_tile_lds(int M) { return sizeof(double) * ((size_t)M * 128 + M); }
 
+// MFMA reconstruction (the contraction over modes as a GEMM per slab of the
+// first axis): u[i, j, l] = sum_m (Y[j, m] s_m) Z[l, m] with s_m = sn_m X0[i, m]
+// (s_m = sn_m in 2D).  A workgroup owns a 64 x 64 (j, l) tile; its four
+// waves each compute a 32 x 32 quarter as 2 x 2 MFMA blocks of 16 x 16 with
+// K = modes (padded to 4 with zero rows).  Both factor tiles are staged in
+// LDS once (mode-major, rows padded so the four modes of a k-step fall in
+// distinct banks) in the arithmetic type T: FP32 MFMA with FP32 accumulation
+// for FP32 output, FP64 MFMA for FP64 output.
+template <class T>
+__host__ __device__ constexpr int recon_stride() { return 64 + (sizeof(T) == 4 ? 16 : 8); }
+
+template <class T>
+size_t reconstruct_mfma_lds(int M) {
+  const size_t Mp = (size_t)(M + 31) / 32 * 32;
+  return sizeof(T) * (2 * Mp * recon_stride<T>() + Mp);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_reconstruct_mfma(DevInst I, int M, T* out) {
+  typedef typename Vec4<T>::type V;
+  constexpr int RS = recon_stride<T>();
+  const int D = I.dim;
+  const DevAxis& AY = I.ax[D - 2];
+  const DevAxis& AZ = I.ax[D - 1];
+  const int nj = AY.n, nl = AZ.n;
+  const int ni = D == 3 ? I.ax[0].n : 1;
+  const int Mp = (M + 31) / 32 * 32;   // k-steps in blocks of 8 (zero rows past M)
+  extern __shared__ unsigned char smr[];
+  T* ys = (T*)smr;            // Mp x RS
+  T* zs = ys + Mp * RS;       // Mp x RS
+  T* sx = zs + Mp * RS;       // Mp
+  const int j0 = blockIdx.y * 64, l0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  for (int idx = tid; idx < Mp * 64; idx += blockDim.x) {
+    const int m = idx >> 6, c = idx & 63;
+    ys[m * RS + c] = (m < M && j0 + c < nj) ? (T)AY.X[(size_t)m * nj + j0 + c] : (T)0;
+    zs[m * RS + c] = (m < M && l0 + c < nl) ? (T)AZ.X[(size_t)m * nl + l0 + c] : (T)0;
+  }
+  const int wj = (w >> 1) * 32, wl = (w & 1) * 32;   // this wave's quarter
+  const int per = (ni + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int i0 = blockIdx.z * per;
+  const int i1 = i0 + per < ni ? i0 + per : ni;
+  // mode weights of slab i, fetched one slab ahead into registers (up to 4
+  // modes per thread: M <= 1024 here)
+  const double* X0 = I.ax[0].X;
+  auto weight = [&](int m, int i) -> T {
+    const int mc = m < M ? m : M - 1;
+    const double v = I.sn[mc] * (D == 3 ? X0[(size_t)mc * ni + i] : 1.0);
+    return m < M ? (T)v : (T)0;
+  };
+  T wr[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) wr[u] = i0 < i1 ? weight(tid + 256 * u, i0) : (T)0;
+  for (int i = i0; i < i1; ++i) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (tid + 256 * u < Mp) sx[tid + 256 * u] = wr[u];
+    __syncthreads();
+    if (i + 1 < i1) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) wr[u] = weight(tid + 256 * u, i + 1);
+    }
+    V acc[2][2];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = V{0, 0, 0, 0};
+    // blocks of 8 k-steps, unrolled (a runtime trip count per k-step makes
+    // the compiler shuffle the accumulators between iterations)
+    for (int kb = 0; kb < Mp / 32; ++kb) {
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) {
+        const int m = 32 * kb + 4 * kk + (l >> 4);
+        const T sm = sx[m];
+        const T* yr = ys + m * RS + wj + (l & 15);
+        const T* zr = zs + m * RS + wl + (l & 15);
+        const T a0 = yr[0] * sm, a1 = yr[16] * sm;
+        const T b0 = zr[0], b1 = zr[16];
+        acc[0][0] = mfma16(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16(a1, b1, acc[1][1]);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int lc = l0 + wl + cb * 16 + (l & 15);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int j = j0 + wj + rb * 16 + mfma_row<T>(l, k);
+          if (j < nj && lc < nl) out[((size_t)i * nj + j) * nl + lc] = acc[rb][cb][k];
+        }
+      }
+  }
+}
+
 hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
                               hipStream_t st) {
   size_t total = 1;
   for (int d = 0; d < I.dim; ++d) total *= (size_t)I.ax[d].n;
+  const size_t mlds = dtype == CTD_DTYPE_F32 ? reconstruct_mfma_lds<float>(M) : reconstruct_mfma_lds<double>(M);
+  if (M >= 1 && M <= 1024 && mlds <= (size_t)max_lds_bytes()) {
+    const int nj = I.ax[I.dim - 2].n, nl = I.ax[I.dim - 1].n;
+    const int ni = I.dim == 3 ? I.ax[0].n : 1;
+    const int tiles = ((nl + 63) / 64) * ((nj + 63) / 64);
+    int zs = std::max(1, std::min(ni, (4 * num_cus() + tiles - 1) / tiles));
+    dim3 grid((nl + 63) / 64, (nj + 63) / 64, zs);
+    if (dtype == CTD_DTYPE_F32) k_reconstruct_mfma<float><<<grid, 256, mlds, st>>>(I, M, (float*)out);
+    else k_reconstruct_mfma<double><<<grid, 256, mlds, st>>>(I, M, (double*)out);
+    return hipGetLastError();
+  }
   if (M >= 1 && reconstruct_tile_lds(M) <= (size_t)max_lds_bytes()) {
     const int nj = I.ax[I.dim - 2].n, nl = I.ax[I.dim - 1].n;
     const int ni = I.dim == 3 ? I.ax[0].n : 1;
@@ -2080,7 +2206,8 @@ hipError_t configure_kernels() {
                       (const void*)k_band_solve_bcr<5, false>, (const void*)k_band_solve_bcr<7, false>,
                       (const void*)k_cubic_h<double>,
                       (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
-                      (const void*)k_reconstruct_tile<double>};
+                      (const void*)k_reconstruct_tile<double>, (const void*)k_reconstruct_mfma<float>,
+                      (const void*)k_reconstruct_mfma<double>};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipGetLastError();
