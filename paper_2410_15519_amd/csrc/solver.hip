@@ -12,6 +12,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <limits>
 #include <string>
 #include <vector>
@@ -265,6 +267,21 @@ std::vector<int4> make_triples(int nb) {
   return t;
 }
 
+// ---- tuning table of the 3D cubic contraction (see ctd_tuning_set)
+namespace {
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, std::pair<int, int>> g_tune;   // (nb, nq) -> (nsplit_g, nsplit_h)
+}  // namespace
+
+bool tuning_lookup(int nb, int nq, int& ng, int& nh) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find({nb, nq});
+  if (it == g_tune.end()) return false;
+  ng = it->second.first;
+  nh = it->second.second;
+  return true;
+}
+
 void update_view(ctd_solver* s) {
   DevInst& I = s->I;
   I.Mk = s->Mk;
@@ -278,13 +295,21 @@ void update_view(ctd_solver* s) {
     // when there are at least 8 (XCD-aware split mapping in the kernel)
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
     if (ng >= 8) ng = ng / 8 * 8;
-    ng = std::min(ng, s->nsplit_g_cap / I.ntri);
-    I.nsplit_g = std::max(1, ng);
     // h: one round of resident workgroups, triples split evenly
     const int nqt = (nqmin + cubic_h_rows(I) - 1) / cubic_h_rows(I);
     const int per_cu = std::max(1, std::min(8, cubic_h_blocks_per_cu(I)));
     const int slots = num_cus() * per_cu;
-    I.nsplit_h = std::max(1, std::min(I.ntri, slots / nqt));
+    int nh = slots / nqt;
+    // a measured table entry for this shape replaces the heuristic
+    int tg = 0, th = 0;
+    if (tuning_lookup(I.nb, nqmin, tg, th)) {
+      ng = tg;
+      nh = th;
+    }
+    ng = std::min(ng, (nqmin + 63) / 64);
+    ng = std::min(ng, s->nsplit_g_cap / I.ntri);
+    I.nsplit_g = std::max(1, ng);
+    I.nsplit_h = std::max(1, std::min(I.ntri, nh));
   }
 }
 
@@ -912,9 +937,30 @@ void solver_bind_stream(ctd_solver* s, hipStream_t st) {
 size_t solver_device_bytes(const ctd_solver* s) { return s->arena.bytes; }
 }  // namespace ctd
 
+extern "C" int ctd_tuning_set(int32_t nb, int32_t nq, int32_t nsplit_g, int32_t nsplit_h) {
+  if (nb < 1 || nq < 1 || nsplit_g < 1 || nsplit_h < 1) return CTD_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[{nb, nq}] = {nsplit_g, nsplit_h};
+  return CTD_OK;
+}
+
+extern "C" int ctd_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+  return CTD_OK;
+}
+
+extern "C" int ctd_tuning_current(ctd_solver* s, int32_t* nsplit_g, int32_t* nsplit_h) {
+  if (!s || !nsplit_g || !nsplit_h) return CTD_EINVAL;
+  *nsplit_g = s->dim == 3 ? s->I.nsplit_g : 0;
+  *nsplit_h = s->dim == 3 ? s->I.nsplit_h : 0;
+  return CTD_OK;
+}
+
 extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u, double* out) {
   if (!s || !u || !out || d < 0 || d >= s->dim) return CTD_EINVAL;
   const int D = s->dim;
+  update_view(s);
   for (int e = 0; e < D; ++e) {
     if (e == d) continue;
     if (!u[e]) return s->fail(CTD_EINVAL, "u[e] is NULL");

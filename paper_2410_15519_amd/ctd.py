@@ -134,6 +134,9 @@ def _load():
                                          C.c_double, C.c_int32, P(C.c_double), P(C.c_double)]),
         "ctd_profile_enable": (C.c_int, [vp, C.c_int32]),
         "ctd_profile_select": (C.c_int, [vp, C.c_uint32]),
+        "ctd_tuning_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "ctd_tuning_clear": (C.c_int, []),
+        "ctd_tuning_current": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
         "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
                                        P(C.c_double), P(C.c_double)]),
     }
@@ -145,6 +148,35 @@ def _load():
 
 
 LIB = _load()
+
+TUNING_PATH = os.path.join(HERE, "tuning.json")
+
+
+def tuning_set(nb, nq, nsplit_g, nsplit_h):
+    """ctd_tuning_set: split counts of the 3D cubic contraction for (nb, nq)."""
+    rc = LIB.ctd_tuning_set(int(nb), int(nq), int(nsplit_g), int(nsplit_h))
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_tuning_set")
+
+
+def tuning_clear():
+    LIB.ctd_tuning_clear()
+
+
+def tuning_load(path=TUNING_PATH):
+    """Register the entries of a tuning table written by tune.py (no-op when
+    the file is absent); returns the number of entries."""
+    if not os.path.exists(path):
+        return 0
+    import json
+    with open(path) as f:
+        table = json.load(f)
+    for e in table.get("entries", []):
+        tuning_set(e["nb"], e["nq"], e["nsplit_g"], e["nsplit_h"])
+    return len(table.get("entries", []))
+
+
+tuning_load()
 
 
 def current_stream():
@@ -265,6 +297,11 @@ class Solver:
         self._check(LIB.ctd_nonlinear_load(self.h, d, ptrs, out.ctypes.data_as(C.POINTER(C.c_double))))
         return out
 
+    def tuning_current(self):
+        """(nsplit_g, nsplit_h) the handle uses for its current M_k (3D)."""
+        g, h = C.c_int32(), C.c_int32()
+        self._check(LIB.ctd_tuning_current(self.h, C.byref(g), C.byref(h)))
+        return g.value, h.value
     def profile(self, on=True, classes=None):
         """Enable (and reset) or disable per-kernel HIP-event timing; classes:
         names from KERNELS to time (default all)."""

@@ -78,6 +78,29 @@ def test_server_and_batch_argument_checks():
     assert ctd.LIB.ctd_server_last_error(None)
 
 
+def test_tuning_table_arguments_and_file():
+    """The split-count table: argument checks, set/clear, and the committed
+    table written by tune.py (one entry per mode-tile count, positive splits)."""
+    import json
+    import os
+    from paper_2410_15519_amd import ctd
+    assert ctd.LIB.ctd_tuning_set(0, 100, 8, 8) == -1
+    assert ctd.LIB.ctd_tuning_set(1, 100, 0, 8) == -1
+    assert ctd.LIB.ctd_tuning_set(1, 100, 8, -1) == -1
+    assert ctd.LIB.ctd_tuning_set(1, 100, 8, 8) == 0
+    assert ctd.LIB.ctd_tuning_current(None, None, None) == -1
+    assert ctd.LIB.ctd_tuning_clear() == 0
+    if os.path.exists(ctd.TUNING_PATH):
+        with open(ctd.TUNING_PATH) as f:
+            table = json.load(f)
+        nbs = [e["nb"] for e in table["entries"]]
+        assert nbs == sorted(set(nbs))
+        assert all(e["nsplit_g"] >= 1 and e["nsplit_h"] >= 1 and e["nq"] >= 1 for e in table["entries"])
+        assert ctd.tuning_load() == len(nbs)
+        ctd.tuning_clear()
+        ctd.tuning_load()
+
+
 @pytest.mark.parametrize("n,s", [(7, 2), (37, 1), (64, 2), (129, 3)])
 def test_axis_fast_diag_against_scipy(n, s):
     """The library's host eigen-decomposition for the fast-diagonalisation
