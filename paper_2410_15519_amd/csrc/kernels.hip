@@ -1329,9 +1329,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
       const T ybv = yr[SS + es] * vs[qq];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        // mode 4 w + r of the A segment
-        const T aval = yr[TM ? (r << 2) + w : w * 4 + r] * ybv;
-        acc[r] = mfma16(aval, bval, acc[r]);
+        // A-segment mode of chain r: FP32 w + 4 r (slot 4 w + r: the wave's
+        // four values are one 16-byte word), FP64 4 w + r
+        const T aval = yr[w * 4 + r];
+        acc[r] = mfma16(aval * ybv, bval, acc[r]);
       }
     }
   };
@@ -1353,7 +1354,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
   T* out = (T*)I.gpart + ((size_t)split * I.ntri + t) * TS;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
-    const int al = w * 4 + r;
+    const int al = sizeof(T) == 4 ? w + 4 * r : w * 4 + r;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
       const int i = mfma_row<T>(l, k), j = l & 15;
