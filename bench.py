@@ -29,6 +29,8 @@ Legs (rank 0, one GPU):
      generator (request count and step counts scaled down, sizes and rate as
      generated) through ctd_server_*; p50/p99 latency from arrival to
      completion and aggregate steps/s.
+  7. (p, s) sweep: set-up time and step cost of the 256^3 workload at the
+     CFE parameters (1, 1), (1, 2), (2, 2), (3, 3) (band half-widths 3, 5, 7).
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -190,6 +192,40 @@ def batched_leg(ctd, count=24, steps=2, workers=8):
     return out
 
 
+def ps_sweep_leg(ctd, workload="ac3d_n256", warmup=1, steps=1):
+    """Cost of the CTD step across the CFE parameters (p, s) of the paper's
+    Sec. 4 study, on one 3D workload: set-up time (host CFE tables, banded
+    matrices, eigenvectors of the fast diagonalisation), ms per step and per
+    directional solve after one warm-up step (mixed precision, adaptive)."""
+    import torch
+    from workloads import make_instance
+    out = {"workload": workload, "warmup": warmup, "steps": steps, "cases": []}
+    for p, s in ((1, 1), (1, 2), (2, 2), (3, 3)):
+        inst = make_instance(workload, patch_s=s, poly_p=p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv = ctd.Solver(inst, precision="mixed")
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+        sv.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = sv.step(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sv.close()
+        sweeps = sum(i["sweeps"] for i in infos)
+        case = {"p": p, "s": s, "band": 2 * s + 1, "init_ms": 1e3 * t_init,
+                "ms_per_step": 1e3 * el / steps, "sweeps_per_step": sweeps / steps,
+                "modes": int(infos[-1]["modes"]),
+                "us_per_directional_solve": 1e6 * el / max(1, sweeps * inst.dim)}
+        out["cases"].append(case)
+        log(f"  [ps] (p,s)=({p},{s}): init {case['init_ms']:.0f} ms, "
+            f"{case['ms_per_step']:.0f} ms/step, {sweeps} sweeps, "
+            f"{case['us_per_directional_solve']:.1f} us per directional solve")
+    return out
+
+
 def served_leg(ctd, count=32, step_scale=20, workers=8):
     """Poisson arrivals into the server; latency from arrival to completion."""
     import numpy as np
@@ -236,6 +272,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
+    ap.add_argument("--no-ps", action="store_true", help="skip the (p, s) sweep")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
@@ -384,6 +421,7 @@ def main():
     if not args.no_serve:
         batched = batched_leg(ctd)
         served = served_leg(ctd)
+    ps_sweep = None if args.no_ps else ps_sweep_leg(ctd)
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",
@@ -400,6 +438,7 @@ def main():
         "fp64": fp64,
         "served": served,
         "batched": batched,
+        "ps_sweep": ps_sweep,
         "detail": extra,
     }
     print(json.dumps(out))
