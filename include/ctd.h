@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define CTD_ABI_VERSION 1
+#define CTD_ABI_VERSION 2
 
 enum {
   CTD_OK = 0,
@@ -76,6 +76,17 @@ enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
  *   <= enrich_tol, or at max_modes (the cap of the adaptive variant).
  * Zero values of dilation_a, gauss_points, fp_tol, fp_max_iter select the
  * defaults 12, 5, 1e-2, 20 (ctd_problem_default fills everything).
+ * actd (2D only, Sec. 3.3 adaptive algorithm): nonzero makes max_modes the
+ *   critical mode count M_c of the hybrid CTD/CFE scheme: a step whose
+ *   enrichment reaches max_modes with the last mode still above enrich_tol
+ *   drops its modes and is computed by the full tensor-product CFE solve of
+ *   the same scheme from u^k (exact, by the generalised eigenbases of
+ *   (K_d, M_d)).  Its result u^{k+1} is held as nodes[1] modes (column j of
+ *   the nodal field times the nodal unit vector j of axis 1, amplitude 1),
+ *   which is the field itself, so the next step's CTD sees the same u^k.
+ *   Needs nodes[d] <= 2048; the set-up computes both axes' eigenbases on the
+ *   host (O(n^3)) and the device footprint holds nodes[1] modes of u^k.
+ *   3D: CTD_EUNSUPPORTED.
  */
 typedef struct ctd_problem {
   int32_t abi_version;      /* CTD_ABI_VERSION */
@@ -96,6 +107,7 @@ typedef struct ctd_problem {
   int32_t init_mode;        /* CTD_INIT_HASH | CTD_INIT_WARM */
   int32_t energy_each_step; /* nonzero: ctd_step fills info.energy */
   int32_t solve_method;     /* CTD_SOLVE_AUTO | CTD_SOLVE_BCR | CTD_SOLVE_FD */
+  int32_t actd;             /* nonzero: full CFE solve past max_modes (2D) */
   uint64_t seed;            /* keys the counter-based mode initialisation */
 } ctd_problem;
 
@@ -107,6 +119,7 @@ typedef struct ctd_step_info {
   int32_t fp_unconverged;   /* modes that hit fp_max_iter */
   int32_t zero_mode;        /* 1 if a zero-amplitude mode ended the step */
   int32_t energy_increase;  /* 1 if energy rose by more than 1e-12 relative */
+  int32_t full_solve;       /* 1 if the step was the full CFE solve (actd) */
   double energy;            /* E(u^{k+1}) if energy_each_step, else NaN */
   double last_term_max;     /* nodal max of the last appended mode */
   double ms;                /* wall time of the step on the host clock */
@@ -150,7 +163,8 @@ int ctd_get_step_index(ctd_solver* s, int64_t* k);
 int ctd_set_step_index(ctd_solver* s, int64_t k);
 
 /* Decision log of the last ctd_step call: per step, the number of modes
- * followed by the sweep count of each mode, concatenated.  *len = ints
+ * followed by the sweep count of each mode, or the single entry -1 for a
+ * step computed by the full CFE solve (actd), concatenated.  *len = ints
  * written (or needed, if cap is too small -> CTD_EINVAL). */
 int ctd_get_decisions(ctd_solver* s, int32_t* buf, int64_t cap, int64_t* len);
 
@@ -304,6 +318,8 @@ enum {
   CTD_K_FINALIZE,      /* normalisation + fixed-point test after a fast-
                           diagonalisation solve (fused into the cyclic
                           reduction kernel otherwise)                     */
+  CTD_K_FULL_SOLVE,    /* full CFE step of actd: dense products in the
+                          eigenbases (2D, FP64 MFMA)                      */
   CTD_K_COUNT
 };
 int ctd_profile_enable(ctd_solver* s, int32_t on);

@@ -165,6 +165,36 @@ hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st);
 bool bcr_fits(int n, int B);                       // block data fit in LDS
 __host__ __device__ size_t bcr_lds_bytes(int n, int B);   // block data bytes of one system
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st);
+// Dense FP64 product C = op(A diag(ks) B) on MFMA (actd.hip): A(i, k) =
+// A[i a_i + k a_k], B(k, j) = B[k b_k + j b_j], C(i, j) = C[i c_i + j c_j];
+// i < m, j < n, k < K.  Epilogues: store; alpha acc - D(i, j) (D FP64 or
+// FP32); acc / (c + lam (mu0_i + mu1_j)); or no store and one partial sum
+// per workgroup of w0_i w1_j acc^4 into part (gemm64_blocks(m, n) values).
+enum { kEpiStore = 0, kEpiAxpby = 1, kEpiFdDiv = 2, kEpiU4 = 3 };
+struct GemmArgs {
+  int m = 0, n = 0, K = 0, epi = kEpiStore;
+  const double* A = nullptr;
+  int64_t a_i = 0, a_k = 0;
+  const double* B = nullptr;
+  int64_t b_k = 0, b_j = 0;
+  const double* ks = nullptr;
+  double* C = nullptr;
+  int64_t c_i = 0, c_j = 0;
+  double alpha = 1.0;
+  const void* D = nullptr;
+  int d_f32 = 0;
+  int64_t d_i = 0, d_j = 0;
+  const double* mu0 = nullptr;
+  const double* mu1 = nullptr;
+  double c = 0.0, lam = 0.0;
+  const double* w0 = nullptr;
+  const double* w1 = nullptr;
+  double* part = nullptr;
+};
+hipError_t launch_gemm64(const GemmArgs& g, hipStream_t st);
+int gemm64_blocks(int m, int n);
+hipError_t launch_unit_columns(double* X, int n, int ncols, hipStream_t st);   // X[:, m] = e_m
+hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();
 int num_cus();

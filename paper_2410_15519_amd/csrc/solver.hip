@@ -123,6 +123,10 @@ struct ctd_solver {
   DevScalars* sc_host = nullptr;   // pinned
   double* KXk[kMaxDim] = {};       // K X^k (energy of u^k)
   int Mk = 0, Mcap = 0, Mkp_max = 0, ntri_max = 0;
+  int Mcap_ctd = 0;                // modes of a CTD state (max_modes, initial count)
+  bool actd = false;               // full CFE solve past the mode cap (2D)
+  double* fsQ = nullptr;           // n0 x n1 temporaries of the full solve
+  double* fsT = nullptr;
   int nsplit_g_cap = 0;
   int64_t step_index = 0;
   std::vector<int32_t> decisions_last, decisions_next;
@@ -246,6 +250,10 @@ int validate(const ctd_problem* p, std::string& err) {
     if (!(p->eps > 0) || !std::isfinite(p->eps)) { err = "eps must be positive"; return CTD_EINVAL; }
     if (!(p->S >= 0) || !std::isfinite(p->S)) { err = "S must be >= 0"; return CTD_EINVAL; }
   }
+  if (p->actd) {
+    if (p->dim != 2) { err = "actd (full CFE solve past the mode cap) is 2D only"; return CTD_EUNSUPPORTED; }
+    if (p->nodes[0] > 2048 || p->nodes[1] > 2048) { err = "actd needs nodes <= 2048 per axis"; return CTD_EUNSUPPORTED; }
+  }
   if (p->patch_s < 1 || p->patch_s > 3) { err = "patch_s must be 1, 2 or 3"; return CTD_EINVAL; }
   if (p->poly_p < 0 || p->poly_p > p->patch_s) { err = "need 0 <= poly_p <= patch_s"; return CTD_EINVAL; }
   for (int d = 0; d < p->dim; ++d) {
@@ -343,7 +351,10 @@ int alloc_instance(ctd_solver* s, int m0) {
   DeviceArena& A = s->arena;
   DevInst& I = s->I;
   const bool mixed = s->P.precision == CTD_PREC_MIXED;
-  s->Mcap = std::max(s->P.max_modes, m0);
+  s->actd = s->P.actd != 0 && s->dim == 2;
+  s->Mcap_ctd = std::max(s->P.max_modes, m0);
+  // a field state from the full solve holds one mode per node of axis 1
+  s->Mcap = s->actd ? std::max(s->Mcap_ctd, s->ax[1].n) : s->Mcap_ctd;
   s->Mkp_max = std::max(kTile, round_up(s->Mcap, kTile));
   const int nbmax = s->Mkp_max / kTile;
   s->ntri_max = tri_count(nbmax);
@@ -426,10 +437,19 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(I.T1, sizeof(double) * n0 * nq1);
     AL(I.Mxy, Tsz * n0 * n1);
     AL(I.MxyT, Tsz * n0 * n1);
+    if (s->actd) {
+      AL(s->fsQ, sizeof(double) * n0 * n1);
+      AL(s->fsT, sizeof(double) * n0 * n1);
+    }
   }
-  const int nbmx = nbmax;
+  // energy partials: the pair route serves states of at most Mcap_ctd modes,
+  // the direct 2D route one value per 64 x 64 Gauss-point tile
+  const int nbmx = std::max(kTile, round_up(s->Mcap_ctd, kTile)) / kTile;
   const int npt = nbmx * (nbmx + 1) / 2;
   s->energy_partial_cap = std::max<size_t>((size_t)npt * (npt + 1) / 2 * 16, 2 * (size_t)s->Mcap) + 16;
+  if (s->dim == 2)
+    s->energy_partial_cap = std::max<size_t>(s->energy_partial_cap,
+                                             (size_t)gemm64_blocks(s->ax[0].nq, s->ax[1].nq) + 16);
   AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
   {
     // directional solve per axis: fast diagonalisation (eigenvectors shared
@@ -439,17 +459,21 @@ int alloc_instance(ctd_solver* s, int m0) {
     const int method = s->P.solve_method;
     for (int d = 0; d < s->dim; ++d)
       s->use_fd[d] = method == CTD_SOLVE_FD || (method == CTD_SOLVE_AUTO && s->dim == 3 && all_small);
+    // the eigenbases also serve the full solve of actd
+    auto eig = [&](int d) { return s->use_fd[d] || s->actd; };
     for (int d = 0; d < s->dim; ++d) {
-      if (!s->use_fd[d]) continue;
+      if (!eig(d)) continue;
       const AxisTables& T = s->ax[d];
       const size_t n = T.n;
       DevAxis& X = I.ax[d];
-      AL(X.fdz, sizeof(double) * kFdSplit * n);
-      AL(X.fdu, sizeof(double) * kFdKb * n);
+      if (s->use_fd[d]) {
+        AL(X.fdz, sizeof(double) * kFdSplit * n);
+        AL(X.fdu, sizeof(double) * kFdKb * n);
+      }
       int same = -1;
       for (int e = 0; e < d; ++e) {
         const AxisTables& U = s->ax[e];
-        if (s->use_fd[e] && U.n == T.n && U.lo == T.lo && U.hi == T.hi && U.s == T.s &&
+        if (eig(e) && U.n == T.n && U.lo == T.lo && U.hi == T.hi && U.s == T.s &&
             U.p == T.p && U.a == T.a && U.ng == T.ng)
           same = e;
       }
@@ -537,8 +561,26 @@ int energy_of_uk(ctd_solver* s, double* E) {
   double u2 = 0, gr = 0;
   for (int a = 0; a < M; ++a) { u2 += g2[2 * a]; gr += g2[2 * a + 1]; }
   int np = 0;
-  {
-    const double P = (double)M * (M + 1) / 2.0;
+  const double P = (double)M * (M + 1) / 2.0;
+  bool direct = false;
+  if (s->dim == 2) {
+    // int u^4 straight from the Gauss-point field u = Xh_0 Xh_1^T when that
+    // is cheaper than the pair Grams (and always for field states)
+    const double q0 = s->I.ax[0].nq, q1 = s->I.ax[1].nq;
+    direct = M > s->Mcap_ctd || q0 * q1 * M < (q0 + q1) * P * P;
+  }
+  if (direct) {
+    const DevInst& I = s->I;
+    GemmArgs g;
+    g.m = I.ax[0].nq; g.n = I.ax[1].nq; g.K = M; g.epi = kEpiU4;
+    g.A = I.ax[0].Xh; g.a_i = I.Mkp; g.a_k = 1;
+    g.B = I.ax[1].Xh; g.b_k = 1; g.b_j = I.Mkp;
+    g.w0 = I.ax[0].w; g.w1 = I.ax[1].w;
+    g.part = s->energy_partial;
+    np = gemm64_blocks(g.m, g.n);
+    LAUNCH(s, CTD_K_ENERGY, 2.0 * g.m * g.n * (double)M, 8.0 * (g.m + g.n) * (double)M,
+           launch_gemm64(g, s->stream));
+  } else {
     double fl = 0.0, by = 0.0;
     for (int d = 0; d < s->dim; ++d) { fl += 2.0 * s->I.ax[d].nq * P * P; by += 8.0 * s->I.ax[d].nq * M; }
     LAUNCH(s, CTD_K_ENERGY, fl, by, launch_energy(V, s->energy_partial, &np, s->stream));
@@ -569,18 +611,92 @@ int finish_step(ctd_solver* s, int M) {
   return precompute(s);
 }
 
+// Full CFE step of the adaptive algorithm (2D): u^{k+1} of the tensor-product
+// system from u^k, exactly, in the eigenbases of (K_d, M_d):
+//   Q = c M_0 U^k M_1 - M_xy,   U' = V_0 [(V_0^T Q V_1) / (c + lam (mu_0i + mu_1j))] V_1^T,
+// written as the new modes: X_0 = U' (column j = mode j), X_1 = identity,
+// amplitudes 1.  u^k (X^k, M X^k, sigma^k, M_xy) is read, not modified.
+int full_step_2d(ctd_solver* s) {
+  DevInst& I = s->I;
+  const int n0 = I.ax[0].n, n1 = I.ax[1].n, M = s->Mk;
+  double* Q = s->fsQ;
+  double* T = s->fsT;
+  const double bytes_nn = 8.0 * n0 * n1;
+  auto run = [&](const GemmArgs& g) -> int {
+    LAUNCH(s, CTD_K_FULL_SOLVE, 2.0 * g.m * g.n * (double)g.K,
+           8.0 * ((double)g.m * g.K + (double)g.K * g.n) + bytes_nn, launch_gemm64(g, s->stream));
+    return CTD_OK;
+  };
+  int rc;
+  {
+    // Q = c (M_0 X^k_0) diag(sigma^k) (M_1 X^k_1)^T - M_xy   (row-major n0 x n1)
+    GemmArgs g;
+    g.m = n0; g.n = n1; g.K = M; g.epi = kEpiAxpby;
+    g.A = I.ax[0].MXk; g.a_i = 1; g.a_k = n0;
+    g.B = I.ax[1].MXk; g.b_k = n1; g.b_j = 1;
+    g.ks = I.sk;
+    g.C = Q; g.c_i = n1; g.c_j = 1;
+    g.alpha = s->c; g.D = I.Mxy; g.d_f32 = I.mixed; g.d_i = n1; g.d_j = 1;
+    if ((rc = run(g))) return rc;
+  }
+  {
+    // T = V_0^T Q
+    GemmArgs g;
+    g.m = n0; g.n = n1; g.K = n0;
+    g.A = I.ax[0].fdV; g.a_i = 1; g.a_k = n0;
+    g.B = Q; g.b_k = n1; g.b_j = 1;
+    g.C = T; g.c_i = n1; g.c_j = 1;
+    if ((rc = run(g))) return rc;
+  }
+  {
+    // Q = (T V_1) / (c + lam (mu_0i + mu_1j))
+    GemmArgs g;
+    g.m = n0; g.n = n1; g.K = n1; g.epi = kEpiFdDiv;
+    g.A = T; g.a_i = n1; g.a_k = 1;
+    g.B = I.ax[1].fdV; g.b_k = n1; g.b_j = 1;
+    g.C = Q; g.c_i = n1; g.c_j = 1;
+    g.mu0 = I.ax[0].fdmu; g.mu1 = I.ax[1].fdmu; g.c = s->c; g.lam = s->lam;
+    if ((rc = run(g))) return rc;
+  }
+  {
+    // T = V_0 Q
+    GemmArgs g;
+    g.m = n0; g.n = n1; g.K = n0;
+    g.A = I.ax[0].fdV; g.a_i = n0; g.a_k = 1;
+    g.B = Q; g.b_k = n1; g.b_j = 1;
+    g.C = T; g.c_i = n1; g.c_j = 1;
+    if ((rc = run(g))) return rc;
+  }
+  {
+    // X_0 = T V_1^T, column-major n0 x n1: column j is mode j
+    GemmArgs g;
+    g.m = n0; g.n = n1; g.K = n1;
+    g.A = T; g.a_i = n1; g.a_k = 1;
+    g.B = I.ax[1].fdV; g.b_k = 1; g.b_j = n1;
+    g.C = I.ax[0].X; g.c_i = 1; g.c_j = n0;
+    if ((rc = run(g))) return rc;
+  }
+  HIPCHK(s, launch_unit_columns(I.ax[1].X, n1, n1, s->stream));
+  HIPCHK(s, launch_fill(I.sn, n1, 1.0, s->stream));
+  for (int d = 0; d < 2; ++d) {
+    HIPCHK(s, launch_band_mv(I.ax[d], I.ax[d].Mb, I.ax[d].X, I.ax[d].MX, n1, s->stream));
+    HIPCHK(s, launch_band_mv(I.ax[d], I.ax[d].Kb, I.ax[d].X, I.ax[d].KX, n1, s->stream));
+  }
+  return CTD_OK;
+}
+
 int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info* info,
-             std::vector<int32_t>& log) {
+             std::vector<int32_t>& log, bool full_replay = false) {
   auto t0 = std::chrono::steady_clock::now();
   const int D = s->dim;
-  const bool adaptive = replay == nullptr;
+  const bool adaptive = replay == nullptr && !full_replay;
   const int max_modes = adaptive ? s->P.max_modes : replay_len;
   if (!adaptive && replay_len > s->Mcap) return s->fail(CTD_EINVAL, "replay needs more modes than allocated");
   const int warm = s->P.init_mode == CTD_INIT_WARM;
   int M = 0, sweeps = 0, unconv = 0, zero = 0, capped = 0;
   double last_term = 0.0;
   std::vector<int32_t> iters;
-  for (int mode = 0; mode < max_modes; ++mode) {
+  for (int mode = 0; mode < (full_replay ? 0 : max_modes); ++mode) {
     HIPCHK(s, launch_reset_scalars(s->I, s->stream));
     HIPCHK(s, launch_init_mode(s->I, s->step_index, mode, warm, s->stream));
     for (int d = 0; d < D; ++d) HIPCHK(s, launch_finalize(s->I, d, 0, 1, s->stream));
@@ -659,18 +775,30 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
       if (M >= s->P.max_modes) { capped = 1; break; }
     }
   }
-  if (!adaptive) {
+  if (!adaptive && !full_replay) {
     int rc = read_scalars(s);
     if (rc) return rc;
     if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
     last_term = s->sc_host->term_max;
   }
+  // adaptive algorithm: a step that needs more than M_c modes is the full solve
+  const bool full = full_replay || (s->actd && capped);
+  if (full) {
+    int rc = full_step_2d(s);
+    if (rc) return rc;
+    M = s->ax[1].n;
+  }
   int rc = finish_step(s, M);   // M == 0: the zero field
   if (rc) return rc;
   ++s->step_index;
-  log.push_back(M);
-  for (int v : iters) log.push_back(v);
+  if (full) {
+    log.push_back(-1);
+  } else {
+    log.push_back(M);
+    for (int v : iters) log.push_back(v);
+  }
   if (info) {
+    info->full_solve = full ? 1 : 0;
     info->modes = M;
     info->sweeps = sweeps;
     info->capped = capped;
@@ -794,14 +922,22 @@ int ctd_step(ctd_solver* s, int32_t nsteps, ctd_step_info* info) {
   for (int k = 0; k < nsteps; ++k) {
     const int32_t* rp = nullptr;
     int rl = 0;
+    bool full = false;
     if (replay) {
       if (pos >= s->decisions_next.size()) return s->fail(CTD_ESTATE, "replay log exhausted");
       rl = s->decisions_next[pos];
-      if (rl < 1 || pos + 1 + rl > s->decisions_next.size()) return s->fail(CTD_EINVAL, "malformed replay log");
-      rp = s->decisions_next.data() + pos + 1;
-      pos += 1 + rl;
+      if (rl == -1) {
+        if (!s->actd) return s->fail(CTD_EINVAL, "replayed full solve needs actd");
+        full = true;
+        rl = 0;
+        pos += 1;
+      } else {
+        if (rl < 1 || pos + 1 + rl > s->decisions_next.size()) return s->fail(CTD_EINVAL, "malformed replay log");
+        rp = s->decisions_next.data() + pos + 1;
+        pos += 1 + rl;
+      }
     }
-    int rc = one_step(s, rp, rl, info ? info + k : nullptr, log);
+    int rc = one_step(s, rp, rl, info ? info + k : nullptr, log, full);
     if (rc) return rc;
   }
   if (replay) s->decisions_next.erase(s->decisions_next.begin(), s->decisions_next.begin() + pos);

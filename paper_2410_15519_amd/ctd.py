@@ -25,7 +25,7 @@ INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
 SOLVE = {"auto": 0, "bcr": 1, "fd": 2}
 KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
-           "mxy_build", "energy", "quad_eval", "other", "finalize"]
+           "mxy_build", "energy", "quad_eval", "other", "finalize", "full_solve"]
 
 
 class CtdError(RuntimeError):
@@ -47,7 +47,7 @@ class Problem(C.Structure):
         ("max_modes", C.c_int32), ("precision", C.c_int32),
         ("schedule", C.c_int32), ("init_mode", C.c_int32),
         ("energy_each_step", C.c_int32), ("solve_method", C.c_int32),
-        ("seed", C.c_uint64),
+        ("actd", C.c_int32), ("seed", C.c_uint64),
     ]
 
 
@@ -55,7 +55,7 @@ class StepInfo(C.Structure):
     _fields_ = [
         ("modes", C.c_int32), ("sweeps", C.c_int32), ("capped", C.c_int32),
         ("fp_unconverged", C.c_int32), ("zero_mode", C.c_int32),
-        ("energy_increase", C.c_int32), ("energy", C.c_double),
+        ("energy_increase", C.c_int32), ("full_solve", C.c_int32), ("energy", C.c_double),
         ("last_term_max", C.c_double), ("ms", C.c_double),
     ]
 
@@ -191,7 +191,7 @@ def current_stream():
 
 
 def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash",
-                 energy=False, solve="auto", **over) -> Problem:
+                 energy=False, solve="auto", actd=False, **over) -> Problem:
     """ctd_problem from a workloads.Instance (epsilon form) plus overrides."""
     p = Problem()
     rc = LIB.ctd_problem_default(C.byref(p))
@@ -215,6 +215,7 @@ def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash
     p.init_mode = INIT[init]
     p.energy_each_step = 1 if energy else 0
     p.solve_method = SOLVE[solve]
+    p.actd = 1 if actd else 0
     for k, v in over.items():
         if k in ("nodes", "lo", "hi"):
             for d, x in enumerate(v):
@@ -335,13 +336,23 @@ class Solver:
         steps, i = [], 0
         while i < len(flat):
             m = flat[i]
+            if m == -1:
+                steps.append("full")
+                i += 1
+                continue
             steps.append(flat[i + 1: i + 1 + m])
             i += 1 + m
         return steps
 
     def set_decisions(self, steps):
+        """Per step a list of sweep counts, or "full" for the full CFE solve."""
         flat = []
         for it in steps:
+            if isinstance(it, str):
+                if it != "full":
+                    raise ValueError("a step's decisions are sweep counts or 'full'")
+                flat.append(-1)
+                continue
             flat.append(len(it))
             flat.extend(int(x) for x in it)
         buf = (C.c_int32 * max(len(flat), 1))(*flat)

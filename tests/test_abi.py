@@ -35,8 +35,9 @@ def test_binding_struct_layout_and_validation():
     """ctd_problem_default and ctd_init's validation run without touching a GPU."""
     from paper_2410_15519_amd import ctd
     p = ctd.make_problem()
-    assert p.abi_version == 1 and p.dim == 2 and p.max_modes == 64
-    assert ctypes.sizeof(ctd.Problem) == 208
+    assert p.abi_version == 2 and p.dim == 2 and p.max_modes == 64 and p.actd == 0
+    assert ctypes.sizeof(ctd.Problem) == 216
+    assert ctypes.sizeof(ctd.StepInfo) == 56
     # invalid problems fail before any allocation or device call
     bad = ctd.make_problem(dim=4)
     h = ctypes.c_void_p()
@@ -47,6 +48,12 @@ def test_binding_struct_layout_and_validation():
     bad = ctd.make_problem(patch_s=1, poly_p=2)
     rc = ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h))
     assert rc == -1
+    # the full-solve fallback of the adaptive algorithm is 2D only
+    bad = ctd.make_problem(dim=3, actd=True)
+    rc = ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h))
+    assert rc == -6 and not h.value and b"2D" in ctd.LIB.ctd_last_error(None)
+    bad = ctd.make_problem(actd=True, nodes=(4096, 64, 64))
+    assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
 
 
 def test_footprint_query_without_device():
@@ -62,6 +69,8 @@ def test_footprint_query_without_device():
     assert f(three, precision="mixed") < f(three, precision="fp64")
     # every buffer is rounded to 256 bytes
     assert f(small) % 256 == 0
+    # actd keeps one mode per node of axis 1 for field states
+    assert f(small, actd=True) > f(small)
     bad = ctd.make_problem(dim=4)
     b = ctypes.c_uint64()
     assert ctd.LIB.ctd_footprint_bytes(ctypes.byref(bad), 1, ctypes.byref(b)) == -1

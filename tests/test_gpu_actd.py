@@ -1,0 +1,112 @@
+"""GPU parity of the adaptive algorithm's full-solve fallback (Sec. 3.3, 2D):
+the full tensor-product CFE step in the eigenbases (FP64 MFMA products), the
+switch past the mode cap, CTD steps from the resulting field state, and the
+energy of field states.  Oracle: `oracle.actd` (dense full solve on tiny
+grids) and the full-system residual at sizes the dense solve cannot reach.
+Tolerances: 1e-10 FP64, 1e-6 mixed (relative nodal l2), as for CTD steps.
+"""
+import numpy as np
+import pytest
+
+from oracle.actd import actd_run, decisions
+from oracle.ctd import full_field, state_from_instance
+from oracle.energy import energy_fullgrid
+from oracle.fullgrid import nonlinear_load
+from oracle.scheme import problem_from_instance
+from workloads import small_instance
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ctd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_15519_amd import ctd as mod
+    return mod
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _inst(n=(13, 10), cap=6, kmax=4):
+    return small_instance(dim=2, n=n, m0=3, kmax=kmax, eps=0.05, dt=1e-3, max_modes=cap)
+
+
+@pytest.mark.parametrize("n", [(13, 10), (70, 45)])
+@pytest.mark.parametrize("solve", ["auto", "fd"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_actd_replay_parity(ctd, n, solve, prec):
+    """Schedule full / CTD from the field state / full / CTD: every step's
+    field against the oracle's."""
+    inst = _inst(n=n)
+    pr = problem_from_instance(inst)
+    sched = ["full", [3, 2, 2, 3], "full", [2, 2]]
+    _, logs, fields = actd_run(pr, state_from_instance(inst), len(sched), replay=sched)
+    print(f"actd replay n={n} solve={solve} prec={prec}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", solve=solve, actd=True) as s:
+        s.set_decisions(sched)
+        dec = []
+        for k, sc in enumerate(sched):
+            info = s.step(1)[0]
+            dec += s.decisions()   # the log of the last ctd_step call
+            assert info["full_solve"] == (1 if sc == "full" else 0)
+            assert info["modes"] == (n[1] if sc == "full" else len(sc))
+            err = rel(s.reconstruct(), fields[k])
+            print(f"  step {k} ({'full' if sc == 'full' else 'ctd'}): rel l2 = {err:.3e}", flush=True)
+            assert err < TOL[prec]
+        assert dec == sched
+
+
+@pytest.mark.parametrize("cap", [6, 7])
+def test_actd_adaptive_decisions(ctd, cap):
+    """Adaptive run: the switch happens exactly where the oracle's does."""
+    inst = _inst(n=(17, 12), cap=cap)
+    pr = problem_from_instance(inst)
+    _, logs, fields = actd_run(pr, state_from_instance(inst), 3)
+    with ctd.Solver(inst, precision="fp64", actd=True) as s:
+        infos = s.step(3)
+        assert s.decisions() == decisions(logs)
+        assert [i["full_solve"] for i in infos] == [int(lg.stop == "full") for lg in logs]
+        assert rel(s.reconstruct(), fields[-1]) < 1e-10
+
+
+def test_actd_energy_of_field_states(ctd):
+    """Energy of a field state (one mode per node: the direct Gauss-grid
+    route) against the full-grid energy of the oracle's field."""
+    inst = _inst(n=(21, 16), cap=6)
+    pr = problem_from_instance(inst)
+    _, logs, fields = actd_run(pr, state_from_instance(inst), 2)
+    with ctd.Solver(inst, precision="fp64", actd=True, energy=True) as s:
+        infos = s.step(2)
+        for k in range(2):
+            assert infos[k]["full_solve"] == 1
+            ref = energy_fullgrid(pr, fields[k])
+            assert infos[k]["energy"] == pytest.approx(ref, rel=1e-12)
+        assert infos[1]["energy"] <= infos[0]["energy"]
+
+
+def test_actd_full_solve_residual_large(ctd):
+    """Full step at 512 x 300 nodes (several MFMA tiles, ragged tails), where
+    the dense oracle solve is out of reach: the nodal field must satisfy the
+    tensor system (c M0 (x) M1 + lam (K0 (x) M1 + M0 (x) K1)) U = c M0 U^k M1 - F
+    with F the oracle's full-grid nonlinear load of u^k."""
+    inst = _inst(n=(512, 300), cap=2, kmax=6)
+    pr = problem_from_instance(inst)
+    Uk = full_field(state_from_instance(inst))
+    with ctd.Solver(inst, precision="fp64", schedule="replay", actd=True) as s:
+        s.set_decisions(["full"])
+        s.step(1)
+        U = s.reconstruct()
+    ax = pr.axes
+    M0, M1, K0, K1 = ax[0].M, ax[1].M, ax[0].K, ax[1].K
+    lhs = pr.c * (M0 @ (M1 @ U.T).T) + pr.lam * (K0 @ (M1 @ U.T).T + M0 @ (K1 @ U.T).T)
+    F = nonlinear_load(pr, Uk)
+    Q = pr.c * (M0 @ (M1 @ Uk.T).T) - F
+    err = rel(lhs, Q)
+    print(f"  residual {err:.2e}", flush=True)
+    assert err < 1e-12
