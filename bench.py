@@ -31,6 +31,9 @@ Legs (rank 0, one GPU):
      completion and aggregate steps/s.
   7. (p, s) sweep: set-up time and step cost of the 256^3 workload at the
      CFE parameters (1, 1), (1, 2), (2, 2), (3, 3) (band half-widths 3, 5, 7).
+  8. adaptive full-solve fallback (2D): full CFE steps of a 1024^2 instance
+     (the second from a field state), step time and the FP64 MFMA rate of the
+     dense eigenbasis products.
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -226,6 +229,44 @@ def ps_sweep_leg(ctd, workload="ac3d_n256", warmup=1, steps=1):
     return out
 
 
+def actd_leg(ctd, n=1024, steps=2):
+    """Full-solve fallback of the adaptive algorithm (2D, Sec. 3.3): a 2D
+    instance on n x n nodes replaying full CFE steps; the second one starts
+    from a field state (one mode per node).  Reports the step time and the
+    per-class kernel times, with the FP64 MFMA rate of the full solve's dense
+    products (5 products of 2 n^3 flops per step)."""
+    import torch
+    from workloads import make_instance
+    inst = make_instance("ac2d_n128", nodes=n)
+    t0 = time.perf_counter()
+    sv = ctd.Solver(inst, precision="fp64", schedule="replay", actd=True)
+    t_init = time.perf_counter() - t0
+    sv.set_decisions(["full"] * steps)
+    ms = []
+    prof = {}
+    for k in range(steps):
+        if k == steps - 1:
+            sv.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.step(1)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - t0))
+    prof = sv.profile_read()
+    sv.profile(False)
+    sv.close()
+    fs = prof.get("full_solve", {})
+    out = {"nodes": [n, n], "init_ms": 1e3 * t_init, "ms_per_full_step": ms,
+           "classes_ms_last_step": {k: v["ms"] for k, v in prof.items()}}
+    if fs:
+        out["full_solve_tflops"] = fs["flops"] / (fs["ms"] * 1e-3) / 1e12
+        out["full_solve_frac_fp64_mfma"] = out["full_solve_tflops"] * 1e12 / PEAK["fp64_mfma"]
+    log(f"  [actd] {n}^2 full steps: {', '.join(f'{x:.1f}' for x in ms)} ms; "
+        f"full solve {fs.get('ms', 0):.2f} ms ({out.get('full_solve_tflops', 0):.1f} TFLOP/s); "
+        f"classes {({k: round(v, 2) for k, v in out['classes_ms_last_step'].items()})}")
+    return out
+
+
 def served_leg(ctd, count=32, step_scale=20, workers=8):
     """Poisson arrivals into the server; latency from arrival to completion."""
     import numpy as np
@@ -273,6 +314,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
     ap.add_argument("--no-ps", action="store_true", help="skip the (p, s) sweep")
+    ap.add_argument("--no-actd", action="store_true", help="skip the full-solve fallback leg")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
@@ -422,6 +464,7 @@ def main():
         batched = batched_leg(ctd)
         served = served_leg(ctd)
     ps_sweep = None if args.no_ps else ps_sweep_leg(ctd)
+    actd = None if args.no_actd else actd_leg(ctd)
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",
@@ -439,6 +482,7 @@ def main():
         "served": served,
         "batched": batched,
         "ps_sweep": ps_sweep,
+        "actd": actd,
         "detail": extra,
     }
     print(json.dumps(out))

@@ -1,5 +1,6 @@
 // Dense FP64 products of the 2D full CFE step (the adaptive algorithm's
-// fallback past the mode cap, Sec. 3.3) and of the 2D energy's quartic term.
+// fallback past the mode cap, Sec. 3.3), of the 2D M_xy integrand and of the
+// 2D energy's quartic term.
 //
 // Full step: the tensor-product CFE system of eq. AC-discrete-semi-stable-K,
 //   (c M_0 (x) M_1 + lam (K_0 (x) M_1 + M_0 (x) K_1)) vec U' = vec Q,
@@ -110,6 +111,8 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
           r = g.alpha * v - dv;
         } else if (g.epi == kEpiFdDiv) {
           r = v / (g.c + g.lam * (g.mu0[i] + g.mu1[j]));
+        } else if (g.epi == kEpiCubic) {
+          r = g.alpha * g.w0[i] * g.w1[j] * (v * v * v - v);
         }
         g.C[(int64_t)i * g.c_i + (int64_t)j * g.c_j] = r;
       }

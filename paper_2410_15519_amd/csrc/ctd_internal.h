@@ -117,6 +117,8 @@ struct DevInst {
   int nsplit_g, nsplit_h;
   // 2D route
   double* T1;        // n0 x nq1
+  double* Gq;        // Gauss-grid strip of omega (u^3 - u) W_0 W_1: gq_rows x nq1
+  int gq_rows;       // rows of the strip (whole elements of axis 0)
   void* Mxy;         // n0 x n1 (T), row-major
   void* MxyT;        // n1 x n0 (T)
 };
@@ -169,8 +171,9 @@ hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream
 // A[i a_i + k a_k], B(k, j) = B[k b_k + j b_j], C(i, j) = C[i c_i + j c_j];
 // i < m, j < n, k < K.  Epilogues: store; alpha acc - D(i, j) (D FP64 or
 // FP32); acc / (c + lam (mu0_i + mu1_j)); or no store and one partial sum
-// per workgroup of w0_i w1_j acc^4 into part (gemm64_blocks(m, n) values).
-enum { kEpiStore = 0, kEpiAxpby = 1, kEpiFdDiv = 2, kEpiU4 = 3 };
+// per workgroup of w0_i w1_j acc^4 into part (gemm64_blocks(m, n) values);
+// or alpha w0_i w1_j (acc^3 - acc).
+enum { kEpiStore = 0, kEpiAxpby = 1, kEpiFdDiv = 2, kEpiU4 = 3, kEpiCubic = 4 };
 struct GemmArgs {
   int m = 0, n = 0, K = 0, epi = kEpiStore;
   const double* A = nullptr;

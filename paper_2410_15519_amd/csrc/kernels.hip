@@ -1727,25 +1727,25 @@ hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
 
 // ------------------------------------------------------------ M_xy (2D)
 // Full integration of M_xy = int N~_x^T N~_y L w(u^k) (eq. KxxMxx) on the
-// tensor Gauss grid: U = Xh_0 Xh_1^T, G = omega (U^3 - U) W_0 W_1,
-// T1 = Phi_0^T G (gathered per node), M_xy = T1 Phi_1.
-template <class T>
-__global__ void k_mxy_t1(DevInst I) {
+// tensor Gauss grid: U = Xh_0 Xh_1^T and G = omega (U^3 - U) W_0 W_1 by the
+// FP64 MFMA product (a strip of whole elements of axis 0 at a time, so the
+// Gauss-grid buffer stays bounded), T1 = Phi_0^T G accumulated per strip
+// (gathered per node, elements in increasing order), M_xy = T1 Phi_1.
+__global__ void k_mxy_t1_strip(DevInst I, int r0, int r1, int i_lo, int i_hi) {
   const DevAxis& X = I.ax[0];
-  const DevAxis& Yx = I.ax[1];
+  const int nqy = I.ax[1].nq;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int nqy = Yx.nq;
-  if (idx >= (size_t)X.n * nqy) return;
-  const int i = (int)(idx / nqy), qy = (int)(idx % nqy);
-  const int ldh = I.Mkp;
-  const T* Xh = (const T*)(sizeof(T) == 4 ? (const void*)X.Xhf : (const void*)X.Xh);
-  const T* Yh = (const T*)(sizeof(T) == 4 ? (const void*)Yx.Xhf : (const void*)Yx.Xh);
-  const T* yrow = Yh + (size_t)qy * ldh;
+  if (idx >= (size_t)(i_hi - i_lo) * nqy) return;
+  const int i = i_lo + (int)(idx / nqy), qy = (int)(idx % nqy);
   const int n = X.n, ne = n - 1;
   int e0 = i - X.SW;
   e0 = e0 < 0 ? 0 : e0;
   int e1 = i + X.SW;
   e1 = e1 > ne - 1 ? ne - 1 : e1;
+  // elements of this strip: rows [r0, r1) are whole elements
+  const int ea = r0 / X.ng, eb = r1 / X.ng;
+  e0 = e0 < ea ? ea : e0;
+  e1 = e1 > eb - 1 ? eb - 1 : e1;
   double acc = 0.0;
   for (int e = e0; e <= e1; ++e) {
     const int st = elem_start(e, X.s, n, X.SW);
@@ -1753,14 +1753,10 @@ __global__ void k_mxy_t1(DevInst I) {
     if (jj < 0 || jj >= X.SW) continue;
     for (int g = 0; g < X.ng; ++g) {
       const int qx = e * X.ng + g;
-      const T* xrow = Xh + (size_t)qx * ldh;
-      T u = 0;
-      for (int a = 0; a < I.Mk; ++a) u += xrow[a] * yrow[a];
-      const double ud = (double)u;
-      acc += X.phi[(size_t)qx * X.SW + jj] * X.w[qx] * (ud * ud * ud - ud);
+      acc += X.phi[(size_t)qx * X.SW + jj] * I.Gq[(size_t)(qx - r0) * nqy + qy];
     }
   }
-  I.T1[idx] = acc * I.omega * Yx.w[qy];
+  I.T1[(size_t)i * nqy + qy] += acc;
 }
 
 template <class T>
@@ -1792,15 +1788,32 @@ __global__ void k_mxy_t2(DevInst I) {
 }
 
 hipError_t launch_mxy_build(const DevInst& I, hipStream_t st) {
-  const size_t t1 = (size_t)I.ax[0].n * I.ax[1].nq;
-  const size_t t2 = (size_t)I.ax[0].n * I.ax[1].n;
-  if (I.mixed) {
-    k_mxy_t1<float><<<(int)((t1 + 255) / 256), 256, 0, st>>>(I);
-    k_mxy_t2<float><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
-  } else {
-    k_mxy_t1<double><<<(int)((t1 + 255) / 256), 256, 0, st>>>(I);
-    k_mxy_t2<double><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
+  const DevAxis& X = I.ax[0];
+  const int nq0 = X.nq, nq1 = I.ax[1].nq;
+  hipError_t e = launch_fill(I.T1, X.n * nq1, 0.0, st);
+  if (e != hipSuccess) return e;
+  for (int r0 = 0; r0 < nq0; r0 += I.gq_rows) {
+    const int r1 = r0 + I.gq_rows < nq0 ? r0 + I.gq_rows : nq0;
+    GemmArgs g;
+    g.m = r1 - r0; g.n = nq1; g.K = I.Mk; g.epi = kEpiCubic;
+    g.A = X.Xh + (size_t)r0 * I.Mkp; g.a_i = I.Mkp; g.a_k = 1;
+    g.B = I.ax[1].Xh; g.b_k = 1; g.b_j = I.Mkp;
+    g.C = I.Gq; g.c_i = nq1; g.c_j = 1;
+    g.alpha = I.omega; g.w0 = X.w + r0; g.w1 = I.ax[1].w;
+    e = launch_gemm64(g, st);
+    if (e != hipSuccess) return e;
+    // nodes whose support meets elements [r0 / ng, r1 / ng)
+    int i_lo = r0 / X.ng - X.SW, i_hi = r1 / X.ng + X.SW;
+    i_lo = i_lo < 0 ? 0 : i_lo;
+    i_hi = i_hi > X.n ? X.n : i_hi;
+    const size_t t1 = (size_t)(i_hi - i_lo) * nq1;
+    k_mxy_t1_strip<<<(int)((t1 + 255) / 256), 256, 0, st>>>(I, r0, r1, i_lo, i_hi);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
+  const size_t t2 = (size_t)X.n * I.ax[1].n;
+  if (I.mixed) k_mxy_t2<float><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
+  else k_mxy_t2<double><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
   return hipGetLastError();
 }
 

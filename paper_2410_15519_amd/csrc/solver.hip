@@ -435,6 +435,14 @@ int alloc_instance(ctd_solver* s, int m0) {
   } else {
     const size_t n0 = s->ax[0].n, n1 = s->ax[1].n, nq1 = s->ax[1].nq;
     AL(I.T1, sizeof(double) * n0 * nq1);
+    {
+      // Gauss-grid strip of the M_xy integrand: whole elements of axis 0,
+      // about 32 MB
+      const size_t ng = s->ax[0].ng;
+      const size_t rows = std::max<size_t>(1, (32u << 20) / (sizeof(double) * nq1 * ng)) * ng;
+      I.gq_rows = (int)std::min<size_t>(rows, (size_t)s->ax[0].nq);
+      AL(I.Gq, sizeof(double) * (size_t)I.gq_rows * nq1);
+    }
     AL(I.Mxy, Tsz * n0 * n1);
     AL(I.MxyT, Tsz * n0 * n1);
     if (s->actd) {
