@@ -42,8 +42,8 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
   // load maps: along the contiguous index of each operand
   const bool a_rows = g.a_i == 1;
   const bool b_cols = g.b_j == 1;
-  for (int k0 = 0; k0 < g.K; k0 += kBK) {
-    double av[4], bv[4];
+  double av[4], bv[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int r = a_rows ? (t & 63) : (t >> 4) + 16 * u;
@@ -63,6 +63,9 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
       const int gj = j0 + c, gk = k0 + k;
       bv[u] = (gj < g.n && gk < g.K) ? g.B[(int64_t)gk * g.b_k + (int64_t)gj * g.b_j] : 0.0;
     }
+  };
+  if (g.K > 0) fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += kBK) {
     __syncthreads();   // the previous chunk's LDS reads are done
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -74,6 +77,8 @@ __global__ __launch_bounds__(256) void k_gemm64(GemmArgs g) {
       Bs[kb * kPad + c] = bv[u];
     }
     __syncthreads();
+    // the next chunk's global loads are in flight during this chunk's MFMAs
+    if (k0 + kBK < g.K) fetch(k0 + kBK);
 #pragma unroll
     for (int ks = 0; ks < kBK; ks += 4) {
       const int k = ks + (l >> 4);
