@@ -110,3 +110,21 @@ def test_actd_full_solve_residual_large(ctd):
     err = rel(lhs, Q)
     print(f"  residual {err:.2e}", flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_mxy_strips_nonlinear_load(ctd, prec):
+    """2D nonlinear load with the Gauss-grid integrand built in several
+    strips (1100 x 900 nodes: 5495 x 4495 Gauss points, a ragged last
+    strip) against the oracle's full-grid integral."""
+    from oracle.ctd import FullGridNonlinear
+    inst = small_instance(dim=2, n=(1100, 900), m0=5, kmax=6)
+    pr = problem_from_instance(inst)
+    rng = np.random.default_rng(11)
+    u = [rng.uniform(-1, 1, n) for n in (1100, 900)]
+    F = FullGridNonlinear(pr, state_from_instance(inst))
+    with ctd.Solver(inst, precision=prec) as s:
+        for d in range(2):
+            err = rel(s.nonlinear_load(d, u), F(d, u))
+            print(f"  strips load d={d}: {err:.2e}", flush=True)
+            assert err < (1e-12 if prec == "fp64" else 2e-6)
