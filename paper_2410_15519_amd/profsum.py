@@ -30,7 +30,7 @@ def kernel_source_sha() -> str:
 
 
 def short_name(name: str) -> str:
-    name = name.replace("ctd::", "")
+    name = name.replace("ctd::", "").replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*$", "", name)
     return name.replace("void ", "").strip()
 
