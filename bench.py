@@ -315,9 +315,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
     ap.add_argument("--no-ps", action="store_true", help="skip the (p, s) sweep")
     ap.add_argument("--no-actd", action="store_true", help="skip the full-solve fallback leg")
-    ap.add_argument("--actd-only", action="store_true",
-                    help="run only the full-solve fallback leg and print its JSON (profiling aid; "
-                         "not the benchmark line)")
+    ap.add_argument("--only", choices=["actd", "batched", "served", "ps"],
+                    help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
@@ -342,8 +341,9 @@ def main():
         assert torch.equal(dst, src)
         del src, dst
         torch.cuda.empty_cache()
-    if args.actd_only:
-        print(json.dumps({"actd": actd_leg(ctd)}))
+    if args.only:
+        legs = {"actd": actd_leg, "batched": batched_leg, "served": served_leg, "ps": ps_sweep_leg}
+        print(json.dumps({args.only: legs[args.only](ctd)}))
         return
     inst = make_instance(args.workload)
     log(f"workload {args.workload}: dim={inst.dim} nodes={inst.nodes} eps={inst.eps} dt={inst.dt} "
