@@ -8,6 +8,7 @@
 #include "ctd_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <mutex>
 
@@ -682,9 +683,44 @@ __host__ __device__ inline int bcr_threads(int n, int B) {
   return 64 * w;
 }
 
-template <int B>
+// Block storage of the cyclic reduction.  MODE 0: every block in LDS (sa);
+// 1: every block in global memory (sa); 2: odd blocks in LDS (sa), even
+// blocks in global memory (sb).  Levels s >= 2 and the back substitution
+// above s = 1 touch odd blocks only, so in mode 2 only the first level and
+// the last back-substitution level reach global memory.  Each access takes
+// the branch of its block's parity, so LDS blocks keep LDS instructions.
+template <int B, int MODE>
+struct BcrMem {
+  static constexpr int S = Bcr<B>::STRIDE;
+  double* sa;
+  double* sb;
+  // P: parity of block I known at the call site (1 odd, 2 even) or 0
+  template <int P = 0>
+  __device__ __forceinline__ double ld(int e, int I) const {
+    if (MODE == 2) {
+      if (P == 1 || (P == 0 && (I & 1))) return sa[(size_t)(I >> 1) * S + e];
+      return sb[(size_t)(I >> 1) * S + e];
+    }
+    return sa[(size_t)I * S + e];
+  }
+  template <int P = 0>
+  __device__ __forceinline__ void st(int e, int I, double v) const {
+    if (MODE == 2) {
+      if (P == 1 || (P == 0 && (I & 1))) sa[(size_t)(I >> 1) * S + e] = v;
+      else sb[(size_t)(I >> 1) * S + e] = v;
+      return;
+    }
+    sa[(size_t)I * S + e] = v;
+  }
+  // odd blocks only in mode 2 (the kept blocks of every level)
+  __device__ __forceinline__ double* odd_ptr(int e, int I) const {
+    return MODE == 2 ? sa + (size_t)(I >> 1) * S + e : sa + (size_t)I * S + e;
+  }
+};
+
+template <int B, int MODE>
 __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const double* Kb, double al, double be,
-                              const double* rpart, int nchunk, double* out, double* sm) {
+                              const double* rpart, int nchunk, double* out, BcrMem<B, MODE> mem) {
   typedef Bcr<B> T;
   static_assert(B <= 8, "a group of B lanes per block");
   constexpr int NP = T::NP;
@@ -696,7 +732,14 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
   const int c = lane_ok ? ln - gi * B : 0;     // column owned by this lane
   const int gbase = lane_ok ? gi * B : 0;      // first lane of the group in its wave
   const int grp = (tid >> 6) * GPW + (lane_ok ? gi : 0), ngrp = (nt >> 6) * GPW;
-#define BCR(e, I) sm[(size_t)(I) * T::STRIDE + (e)]
+#define BLD(e, I) mem.ld((e), (I))
+#define BST(e, I, v) mem.st((e), (I), (v))
+  // kept blocks (odd in every level) and their neighbours (even in the
+  // first level, odd above it): parity known at compile time per level kind
+#define BLDO(e, I) mem.template ld<1>((e), (I))
+#define BSTO(e, I, v) mem.template st<1>((e), (I), (v))
+#define BLDN(e, I) mem.template ld<NP_>((e), (I))
+#define BSTN(e, I, v) mem.template st<NP_>((e), (I), (v))
   // D, L and b of every block: clear D and L (padding rows of the last block
   // get a unit diagonal), scatter the band entries with coalesced loads
   // issued four at a time, and sum the RHS partials
@@ -708,14 +751,14 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
       while (T::pk(r + 1, 0) <= e) ++r;
       if (I * B + r >= n && e == T::pk(r, r)) v = 1.0;
     }
-    BCR(e, I) = v;
+    BST(e, I, v);
   }
   for (int i = tid; i < N * B; i += nt) {
     const int I = i / B, r = i - I * B;
     double v = 0.0;
     if (i < n)
       for (int y = 0; y <= nchunk; ++y) v += rpart[(size_t)y * n + i];
-    BCR(T::OB + r, I) = v;
+    BST(T::OB + r, I, v);
   }
   __syncthreads();
   {
@@ -735,18 +778,19 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
         if (idx < total && i < n) {
           const double v = al * mv[u] + be * kv[u];
           const int I = i / B, r = i - I * B, J = j / B, cc = j - J * B;
-          if (I == J) BCR(T::pk(r, cc), I) = v;
-          else BCR(T::OL + r * B + cc, I) = v;
+          if (I == J) BST(T::pk(r, cc), I, v);
+          else BST(T::OL + r * B + cc, I, v);
         }
       }
     }
   }
   __syncthreads();
-  int top = 1;
-  for (int s = 1;; s <<= 1) {
+  // one reduction level; FIRST: the first level (s = 1), whose neighbour
+  // blocks J1, J2 are even
+  auto level = [&](auto first_tag, const int s) {
+    constexpr int NP_ = decltype(first_tag)::value ? 2 : 1;
     const int first = s - 1;
     const int count = (N - first + s - 1) / s;
-    if (count <= 1) { top = s; break; }
     const int nkept = count / 2;
     for (int g0 = 0; g0 < nkept; g0 += ngrp) {
       const int g = g0 + grp;
@@ -761,7 +805,7 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
       // of the group through the idle slots of the kept block I (its L copy
       // and factor slots are first written when I is eliminated); a group
       // lives in one wave, whose LDS accesses complete in order.
-      double* vx = &BCR(T::OLN, I);               // V1 (B x B, column-major by lane)
+      double* vx = mem.odd_ptr(T::OLN, I);        // V1 (B x B, column-major by lane)
       double w1[B], y1[B], v2[B], y2[B];
       double bc = 0.0;
       {
@@ -770,15 +814,15 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
         double G[NP], v1[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-          v1[q] = BCR(T::OL + c * B + q, I);      // row c of L_I
-          w1[q] = BCR(T::OL + q * B + c, J1);     // column c of L_J1
-          y1[q] = BCR(T::OB + q, J1);
+          v1[q] = BLDO(T::OL + c * B + q, I);      // row c of L_I
+          w1[q] = BLDN(T::OL + q * B + c, J1);     // column c of L_J1
+          y1[q] = BLDN(T::OB + q, J1);
         }
         if (act)
 #pragma unroll
-          for (int q = 0; q < B; ++q) BCR(T::OLN + c * B + q, J1) = v1[q];
+          for (int q = 0; q < B; ++q) BSTN(T::OLN + c * B + q, J1, v1[q]);
 #pragma unroll
-        for (int e = 0; e < NP; ++e) G[e] = BCR(e, J1);
+        for (int e = 0; e < NP; ++e) G[e] = BLDN(e, J1);
         T::chol(G);
         T::fwd(G, v1);
         T::fwd(G, w1);
@@ -786,7 +830,7 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
         if (act) {
 #pragma unroll
           for (int e = 0; e < NP; ++e)
-            if (e % B == c) BCR(T::OG + e, J1) = G[e];
+            if (e % B == c) BSTN(T::OG + e, J1, G[e]);
         }
 #pragma unroll
         for (int q = 0; q < B; ++q) bc += v1[q] * y1[q];
@@ -800,11 +844,11 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
         // the last active block, which no other kept block has as J1
         double G[NP];
 #pragma unroll
-        for (int e = 0; e < NP; ++e) G[e] = BCR(e, J2);
+        for (int e = 0; e < NP; ++e) G[e] = BLDN(e, J2);
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-          v2[q] = BCR(T::OL + q * B + c, J2);     // column c of L_J2
-          y2[q] = BCR(T::OB + q, J2);
+          v2[q] = BLDN(T::OL + q * B + c, J2);     // column c of L_J2
+          y2[q] = BLDN(T::OB + q, J2);
         }
         T::chol(G);
         T::fwd(G, v2);
@@ -812,7 +856,7 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
         if (act && has2 && k + 1 == count - 1) {
 #pragma unroll
           for (int e = 0; e < NP; ++e)
-            if (e % B == c) BCR(T::OG + e, J2) = G[e];
+            if (e % B == c) BSTN(T::OG + e, J2, G[e]);
         }
         if (!has2) {
 #pragma unroll
@@ -836,10 +880,10 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
             d += a1 * v1c[q] + a2 * v2[q];
             lsum += a1 * w1[q];
           }
-          if (r >= c) BCR(T::pk(r, c), I) -= d;
-          BCR(T::OL + r * B + c, I) = -lsum;
+          if (r >= c) BSTO(T::pk(r, c), I, BLDO(T::pk(r, c), I) - d);
+          BSTO(T::OL + r * B + c, I, -lsum);
         }
-        BCR(T::OB + c, I) -= bc;
+        BSTO(T::OB + c, I, BLDO(T::OB + c, I) - bc);
       } else {
 #pragma unroll
         for (int r = 0; r < B; ++r)
@@ -848,25 +892,35 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
       }
     }
     __syncthreads();
+  };
+  int top = 1;
+  for (int s = 1;; s <<= 1) {
+    const int first = s - 1;
+    const int count = (N - first + s - 1) / s;
+    if (count <= 1) { top = s; break; }
+    if (MODE == 2 && s == 1) level(std::true_type{}, s);
+    else level(std::false_type{}, s);
   }
   // last active block: x = D^-1 b
   if (tid < B) {
     const int J = top - 1;
     double G[NP], v[B];
 #pragma unroll
-    for (int e = 0; e < NP; ++e) G[e] = BCR(e, J);
+    for (int e = 0; e < NP; ++e) G[e] = BLD(e, J);
 #pragma unroll
-    for (int q = 0; q < B; ++q) v[q] = BCR(T::OB + q, J);
+    for (int q = 0; q < B; ++q) v[q] = BLD(T::OB + q, J);
     T::chol(G);
     T::fwd(G, v);
     T::bwd(G, v);
     if (tid == 0)
 #pragma unroll
-      for (int q = 0; q < B; ++q) BCR(T::OB + q, J) = v[q];
+      for (int q = 0; q < B; ++q) BST(T::OB + q, J, v[q]);
   }
   __syncthreads();
-  // back substitution, top level down
-  for (int s = top >> 1; s >= 1; s >>= 1) {
+  // back substitution, top level down; in the last level (s = 1) the
+  // solved blocks J are even, their neighbours odd
+  auto back = [&](auto last_tag, const int s) {
+    constexpr int NP_ = decltype(last_tag)::value ? 2 : 1;
     const int first = s - 1;
     const int count = (N - first + s - 1) / s;
     const int nelim = (count + 1) / 2;
@@ -875,35 +929,44 @@ __device__ __forceinline__ void bcr_solve_par(int n, const double* Mb, const dou
       const bool act = lane_ok && g < nelim;
       const int J = first + 2 * (act ? g : 0) * s;
       const bool lo = J - s >= 0, hi = J + s < N;
-      double t = BCR(T::OB + c, J);
+      double t = BLDN(T::OB + c, J);
       if (lo) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) t -= BCR(T::OL + c * B + q, J) * BCR(T::OB + q, J - s);
+        for (int q = 0; q < B; ++q) t -= BLDN(T::OL + c * B + q, J) * BLDO(T::OB + q, J - s);
       }
       if (hi) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) t -= BCR(T::OLN + q * B + c, J) * BCR(T::OB + q, J + s);
+        for (int q = 0; q < B; ++q) t -= BLDN(T::OLN + q * B + c, J) * BLDO(T::OB + q, J + s);
       }
       double v[B], G[NP];
 #pragma unroll
       for (int q = 0; q < B; ++q) v[q] = __shfl(t, gbase + q, 64);
 #pragma unroll
-      for (int e = 0; e < NP; ++e) G[e] = BCR(T::OG + e, J);
+      for (int e = 0; e < NP; ++e) G[e] = BLDN(T::OG + e, J);
       T::fwd(G, v);
       T::bwd(G, v);
       double xc = v[0];
 #pragma unroll
       for (int q = 1; q < B; ++q) xc = q == c ? v[q] : xc;
-      if (act) BCR(T::OB + c, J) = xc;
+      if (act) BSTN(T::OB + c, J, xc);
     }
     __syncthreads();
+  };
+  for (int s = top >> 1; s >= 1; s >>= 1) {
+    if (MODE == 2 && s == 1) back(std::true_type{}, s);
+    else back(std::false_type{}, s);
   }
   for (int i = tid; i < n; i += nt) {
     const int I = i / B, r = i - I * B;
-    out[i] = BCR(T::OB + r, I);
+    out[i] = BLD(T::OB + r, I);
   }
   __syncthreads();
-#undef BCR
+#undef BLD
+#undef BST
+#undef BLDO
+#undef BSTO
+#undef BLDN
+#undef BSTN
 }
 
 __host__ __device__ size_t bcr_lds_bytes(int n, int B) {
@@ -913,6 +976,17 @@ __host__ __device__ size_t bcr_lds_bytes(int n, int B) {
 }
 
 bool bcr_fits(int n, int B) { return bcr_lds_bytes(n, B) + 1024 <= (size_t)max_lds_bytes(); }
+
+// LDS of the split storage (odd blocks in LDS; also the 3n-double scratch of
+// the normalisation that follows the solve)
+size_t bcr_split_lds_bytes(int n, int B) {
+  const int N = (n + B - 1) / B;
+  const int stride = (B * (B + 1) + 2 * B * B + B) | 1;
+  const size_t odd = sizeof(double) * (size_t)(N / 2) * stride;
+  const size_t fin = sizeof(double) * 3 * (size_t)n;
+  return odd > fin ? odd : fin;
+}
+bool bcr_split_fits(int n, int B) { return bcr_split_lds_bytes(n, B) + 1024 <= (size_t)max_lds_bytes(); }
 
 // alpha_d, beta_d of K_d = alpha_d M_d + beta_d K_d (eq. KxQx, 3D analogue)
 // from the fixed factors' m_e = u_e.M.u_e, k_e = u_e.K.u_e.
@@ -933,12 +1007,14 @@ __device__ __forceinline__ void directional_coeffs(const DevInst& I, int d, doub
 
 // Directional solve by block cyclic reduction: alpha_d, beta_d from the
 // fixed factors, solve, then normalisation and the fixed-point test.
-// GWS: block data in the global workspace (a separate instantiation, so that
-// the LDS one keeps LDS addressing)
-template <int B, bool GWS>
+// MODE (BcrMem): 0 block data in LDS, 1 in the global workspace, 2 odd
+// blocks in LDS and even blocks in the workspace (separate instantiations,
+// so that LDS data keep LDS addressing)
+template <int B, int MODE>
 __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk, double* gws) {
   extern __shared__ double lds[];
-  double* sm = GWS ? gws : lds;
+  BcrMem<B, MODE> mem{MODE == 1 ? gws : lds, MODE == 2 ? gws : nullptr};
+  double* sm = MODE == 1 ? gws : lds;
   __shared__ double red[96];
   __shared__ double ab[2];
   DevAxis& A = I.ax[d];
@@ -948,21 +1024,23 @@ __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr(DevInst I, 
     I.sc->beta[d] = ab[1];
   }
   __syncthreads();
-  bcr_solve_par<B>(A.n, A.Mb, A.Kb, ab[0], ab[1], A.rpart, nchunk, A.u, sm);
+  bcr_solve_par<B, MODE>(A.n, A.Mb, A.Kb, ab[0], ab[1], A.rpart, nchunk, A.u, mem);
   finalize_body<B>(I, d, sweep, 0, red, sm);
 }
 
 hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream_t st) {
   const DevAxis& A = I.ax[d];
   const bool fits = bcr_fits(A.n, A.B);
+  const bool split = !fits && bcr_split_fits(A.n, A.B);
   if (!fits && !I.bcr_ws) return hipErrorInvalidValue;
-  const size_t shm = fits ? bcr_lds_bytes(A.n, A.B) : 0;
+  const size_t shm = fits ? bcr_lds_bytes(A.n, A.B) : (split ? bcr_split_lds_bytes(A.n, A.B) : 0);
   double* gws = fits ? nullptr : I.bcr_ws;
   const int nchunk = rhs_chunks(I, M, 0);
   const int nt = bcr_threads(A.n, A.B);
-#define SOLVE_BCR(BW)                                                              \
-  (fits ? k_solve_bcr<BW, false><<<1, nt, shm, st>>>(I, d, sweep, nchunk, nullptr)      \
-        : k_solve_bcr<BW, true><<<1, nt, 0, st>>>(I, d, sweep, nchunk, gws))
+#define SOLVE_BCR(BW)                                                                   \
+  (fits ? k_solve_bcr<BW, 0><<<1, nt, shm, st>>>(I, d, sweep, nchunk, nullptr)          \
+        : split ? k_solve_bcr<BW, 2><<<1, nt, shm, st>>>(I, d, sweep, nchunk, gws)      \
+                : k_solve_bcr<BW, 1><<<1, nt, 0, st>>>(I, d, sweep, nchunk, gws))
   switch (A.B) {
     case 3: SOLVE_BCR(3); break;
     case 5: SOLVE_BCR(5); break;
@@ -973,14 +1051,15 @@ hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream
   return hipGetLastError();
 }
 
-template <int B, bool GWS>
+template <int B, int MODE>
 __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_band_solve_bcr(int n, const double* Mb, const double* Kb,
                                                         const double* alpha, const double* beta,
                                                         const double* b, double* x, double* gws) {
   extern __shared__ double lds[];
   const int k = blockIdx.x;
-  double* sm = GWS ? gws + (size_t)k * (bcr_lds_bytes(n, B) / sizeof(double)) : lds;
-  bcr_solve_par<B>(n, Mb, Kb, alpha[k], beta[k], b + (size_t)k * n, 0, x + (size_t)k * n, sm);
+  double* g = MODE == 0 ? nullptr : gws + (size_t)k * (bcr_lds_bytes(n, B) / sizeof(double));
+  BcrMem<B, MODE> mem{MODE == 1 ? g : lds, MODE == 2 ? g : nullptr};
+  bcr_solve_par<B, MODE>(n, Mb, Kb, alpha[k], beta[k], b + (size_t)k * n, 0, x + (size_t)k * n, mem);
 }
 
 hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
@@ -988,17 +1067,19 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st) {
   const bool fits = bcr_fits(n, bw);
+  const bool split = !fits && bcr_split_fits(n, bw);
   const size_t bytes = bcr_lds_bytes(n, bw);
   double* gws = nullptr;
   if (!fits) {
     hipError_t e = hipMallocAsync((void**)&gws, bytes * (size_t)count, st);
     if (e != hipSuccess) return e;
   }
-  const size_t shm = fits ? bytes : 0;
+  const size_t shm = fits ? bytes : (split ? bcr_split_lds_bytes(n, bw) : 0);
   const int nt = bcr_threads(n, bw);
-#define BAND_BCR(BW)                                                                     \
-  (fits ? k_band_solve_bcr<BW, false><<<count, nt, shm, st>>>(n, Mb, Kb, alpha, beta, b, x, nullptr) \
-        : k_band_solve_bcr<BW, true><<<count, nt, 0, st>>>(n, Mb, Kb, alpha, beta, b, x, gws))
+#define BAND_BCR(BW)                                                                               \
+  (fits ? k_band_solve_bcr<BW, 0><<<count, nt, shm, st>>>(n, Mb, Kb, alpha, beta, b, x, nullptr)    \
+        : split ? k_band_solve_bcr<BW, 2><<<count, nt, shm, st>>>(n, Mb, Kb, alpha, beta, b, x, gws) \
+                : k_band_solve_bcr<BW, 1><<<count, nt, 0, st>>>(n, Mb, Kb, alpha, beta, b, x, gws))
   switch (bw) {
     case 3: BAND_BCR(3); break;
     case 5: BAND_BCR(5); break;
@@ -2215,9 +2296,12 @@ hipError_t configure_kernels() {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
     g_num_cus = ncu;
   // Raising the limit is best effort: launches check their own LDS needs.
-  const void* ks[] = {(const void*)k_solve_bcr<3, false>, (const void*)k_solve_bcr<5, false>,
-                      (const void*)k_solve_bcr<7, false>, (const void*)k_band_solve_bcr<3, false>,
-                      (const void*)k_band_solve_bcr<5, false>, (const void*)k_band_solve_bcr<7, false>,
+  const void* ks[] = {(const void*)k_solve_bcr<3, 0>, (const void*)k_solve_bcr<5, 0>,
+                      (const void*)k_solve_bcr<7, 0>, (const void*)k_band_solve_bcr<3, 0>,
+                      (const void*)k_band_solve_bcr<5, 0>, (const void*)k_band_solve_bcr<7, 0>,
+                      (const void*)k_solve_bcr<3, 2>, (const void*)k_solve_bcr<5, 2>,
+                      (const void*)k_solve_bcr<7, 2>, (const void*)k_band_solve_bcr<3, 2>,
+                      (const void*)k_band_solve_bcr<5, 2>, (const void*)k_band_solve_bcr<7, 2>,
                       (const void*)k_cubic_h<double>,
                       (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
                       (const void*)k_reconstruct_tile<double>, (const void*)k_reconstruct_mfma<float>,

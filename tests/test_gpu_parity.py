@@ -47,8 +47,10 @@ def test_band_solve_kernel(ctd):
     import torch
     import scipy.linalg as sla
     from oracle.cfe1d import Axis
-    # the last two exceed the LDS and run on a device workspace
-    for s, n in ((1, 37), (2, 100), (2, 1031), (3, 515), (2, 2048), (3, 1300)):
+    # block data in LDS up to (3, 515); (2, 2048) and (3, 1300): odd blocks in
+    # LDS, even blocks in a device workspace; the last two: all blocks in the
+    # workspace
+    for s, n in ((1, 37), (2, 100), (2, 1031), (3, 515), (2, 2048), (3, 1300), (2, 2600), (3, 2000)):
         ax = Axis(n, 0.0, 1.0, s=s, p=min(s, 2), a=12.0, ng=5)
         bw = 2 * s + 1
         Mb, Kb = ax.banded(ax.M), ax.banded(ax.K)
