@@ -159,7 +159,7 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
-constexpr int kFdSplit = 8;   // row splits of the projection V^T b
+constexpr int kFdSplit = 32;   // row splits of the projection V^T b
 constexpr int kFdKb = 8;      // eigenvector splits of the back-projection V z
 // x = V diag(1 / (alpha + beta mu)) V^T b into ax[d].u, alpha/beta from the
 // fixed factors (two launches; the normalisation follows separately)
