@@ -128,3 +128,22 @@ def test_mxy_strips_nonlinear_load(ctd, prec):
             err = rel(s.nonlinear_load(d, u), F(d, u))
             print(f"  strips load d={d}: {err:.2e}", flush=True)
             assert err < (1e-12 if prec == "fp64" else 2e-6)
+
+
+def test_actd_in_batch_equals_standalone(ctd):
+    """Instances that switch to the full solve, stepped concurrently on
+    worker streams, end bitwise where each alone does."""
+    insts = [_inst(n=(17 + 6 * k, 12 + 3 * k), cap=6 if k % 2 == 0 else 7) for k in range(4)]
+    b = ctd.Batch(insts, precision="fp64", actd=True)
+    try:
+        b.set_workers(4)
+        b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        with ctd.Solver(inst, precision="fp64", actd=True) as s:
+            s.step(2)
+            amp, fac = s.modes()
+        assert np.array_equal(got[i][0], amp), f"instance {i}"
+        assert all(np.array_equal(x, y) for x, y in zip(got[i][1], fac)), f"instance {i}"
