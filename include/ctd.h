@@ -310,7 +310,8 @@ enum {
   CTD_K_RHS,           /* right-hand side assembly + nonlinear projection */
   CTD_K_SOLVE,         /* banded solve (block cyclic reduction) + normalisation */
   CTD_K_SIGNATURE,     /* Grams of a fresh factor, Gauss-point values     */
-  CTD_K_GEMV,          /* M_xy products (2D)                              */
+  CTD_K_GEMV,          /* (no launches: the 2D M_xy product runs inside
+                          the RHS launch, booked under CTD_K_RHS)         */
   CTD_K_MXY,           /* M_xy build (2D, once per step)                  */
   CTD_K_ENERGY,        /* separated energy                                */
   CTD_K_QUAD,          /* Gauss-point tables of u^k (once per step)       */

@@ -58,7 +58,6 @@ struct DevAxis {
   double* Ku;       // n
   double* rhs;      // n
   double* rpart;    // (chunks + 1) x n partial right-hand sides
-  double* F;        // n, nonlinear load (2D route)
   double* v;        // nq, W * (Phi u)
   float* vf;
   double* gm;       // Mcap: u . MX[:, m]
@@ -135,7 +134,10 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
-int rhs_chunks(const DevInst& I, int M, int load_only);
+// index of the last RHS partial chunk of direction d (consumers add chunks
+// 0 ..= this one); load chunks: 2D ceil(n_other / 64), 3D one
+int rhs_chunks(const DevInst& I, int d, int M, int load_only);
+int rhs_load_chunks(const DevInst& I, int d);
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st);
 // g_d as split-K partials, then their reduction into g_d and S = w g_d g_other
 hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st);
@@ -146,7 +148,6 @@ int cubic_h_rows(const DevInst& I);     // Gauss points per workgroup of the h k
 int cubic_h_blocks_per_cu(const DevInst& I);   // resident h workgroups per CU
 hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_mxy_build(const DevInst& I, hipStream_t st);
-hipError_t launch_gemv(const DevInst& I, int d, hipStream_t st);
 hipError_t launch_reset_scalars(const DevInst& I, hipStream_t st);
 hipError_t launch_energy(const DevInst& I, double* partial, int* npartial,
                          hipStream_t st);

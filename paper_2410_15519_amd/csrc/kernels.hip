@@ -455,13 +455,17 @@ hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st) {
 // ck = c with the 2D M_xy load (which contains the full w), ck = c + omega
 // with the 3D cubic load F_d = omega Phi^T W h.
 // Grid: row blocks of 64 x (column chunks of 64 over [MXk | MX | KX], plus
-// one chunk for -F_d).  Each block writes its partial sums to
-// rpart[chunk][row]; the solve kernel adds the chunks in fixed order.
+// the load chunks: 3D one chunk for -F_d; 2D the columns of the M_xy
+// product F_d = M_xy u_e (d = 0) or M_xy^T u_e (d = 1), 64 per chunk, each
+// column stored contiguously over the rows of d (a row of M_xy^T or M_xy)).
+// Each block writes its partial sums to rpart[chunk][row]; the solve kernel
+// adds the chunks in fixed order.
 __device__ __forceinline__ int rhs_columns(const DevInst& I, int M, int load_only) {
   return load_only ? (I.dim == 3 ? I.Mk : 0) : I.Mk + 2 * M;
 }
 
 __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
+  // nchunk: the linear column chunks; the load chunks follow
   extern __shared__ double hl[];
   __shared__ double coef[64];
   __shared__ double part[256];
@@ -516,12 +520,42 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
     if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
     return;
   }
+  if (I.dim == 2) {
+    // load chunk of the 2D M_xy product: 16 columns per wave, loaded before
+    // the coefficients -u_e[j] (+u_e[j] for the load alone)
+    const int o = 1 - d, nco = I.ax[o].n;
+    const int j0 = (y - nchunk) * 64;
+    const void* base = d == 0 ? I.MxyT : I.Mxy;
+    double cv[16];
+#pragma unroll
+    for (int cc = 0; cc < 16; ++cc) {
+      const int j = j0 + w * 16 + cc;
+      const size_t at = (size_t)j * n + i;
+      double v = 0.0;
+      if (j < nco && i < n) v = I.mixed ? (double)((const float*)base)[at] : ((const double*)base)[at];
+      cv[cc] = v;
+    }
+    if (tid < 64) {
+      const int j = j0 + tid;
+      coef[tid] = j < nco ? (load_only ? I.ax[o].u[j] : -I.ax[o].u[j]) : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (i < n) {
+#pragma unroll
+      for (int cc = 0; cc < 16; ++cc) acc += coef[w * 16 + cc] * cv[cc];
+    }
+    part[tid] = acc;
+    __syncthreads();
+    if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
+    return;
+  }
   // chunk nchunk: the projected nonlinear load F_i = omega sum_q Phi[q, i] W_q h_q
   // over the elements around the 64 rows; h and the Phi rows of those
   // elements are staged in LDS, and the elements of a row are split over the
   // four waves (summed in wave order).
   double F = 0.0;
-  if (I.dim == 3) {
+  {
     const int ne = n - 1;
     const int SW = A.SW;
     const int e_lo = r0 - SW > 0 ? r0 - SW : 0;
@@ -562,21 +596,27 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
     part[tid] = Fw;
     __syncthreads();
     if (w == 0) F = I.omega * (part[l] + part[64 + l] + part[128 + l] + part[192 + l]);
-  } else if (i < n) {
-    F = A.F[i];
   }
   if (w == 0 && i < n) A.rpart[(size_t)nchunk * n + i] = load_only ? F : -F;
 }
 
-int rhs_chunks(const DevInst& I, int M, int load_only) {
+static int rhs_linear_chunks(const DevInst& I, int M, int load_only) {
   const int ctot = load_only ? (I.dim == 3 ? I.Mk : 0) : I.Mk + 2 * M;
   return (ctot + 63) / 64;
 }
 
+int rhs_load_chunks(const DevInst& I, int d) {
+  return I.dim == 2 ? (I.ax[1 - d].n + 63) / 64 : 1;
+}
+
+int rhs_chunks(const DevInst& I, int d, int M, int load_only) {
+  return rhs_linear_chunks(I, M, load_only) + rhs_load_chunks(I, d) - 1;
+}
+
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only) {
   const DevAxis& A = I.ax[d];
-  const int nchunk = rhs_chunks(I, M, load_only);
-  dim3 grid((A.n + 63) / 64, nchunk + 1);
+  const int nchunk = rhs_linear_chunks(I, M, load_only);
+  dim3 grid((A.n + 63) / 64, nchunk + rhs_load_chunks(I, d));
   // h (qcount) and the Phi rows (qcount x SW) of the elements around a row block
   const size_t shm = sizeof(double) * (size_t)(64 + 2 * A.SW + 2) * A.ng * (1 + A.SW);
   k_rhs<<<grid, 256, shm, st>>>(I, d, M, load_only, nchunk);
@@ -597,7 +637,7 @@ __global__ void k_rhs_sum(DevInst I, int d, int nchunk) {
 }
 
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st) {
-  k_rhs_sum<<<(I.ax[d].n + 255) / 256, 256, 0, st>>>(I, d, rhs_chunks(I, M, load_only));
+  k_rhs_sum<<<(I.ax[d].n + 255) / 256, 256, 0, st>>>(I, d, rhs_chunks(I, d, M, load_only));
   return hipGetLastError();
 }
 
@@ -1035,7 +1075,7 @@ hipError_t launch_solve_bcr(const DevInst& I, int d, int sweep, int M, hipStream
   if (!fits && !I.bcr_ws) return hipErrorInvalidValue;
   const size_t shm = fits ? bcr_lds_bytes(A.n, A.B) : (split ? bcr_split_lds_bytes(A.n, A.B) : 0);
   double* gws = fits ? nullptr : I.bcr_ws;
-  const int nchunk = rhs_chunks(I, M, 0);
+  const int nchunk = rhs_chunks(I, d, M, 0);
   const int nt = bcr_threads(A.n, A.B);
 #define SOLVE_BCR(BW)                                                                   \
   (fits ? k_solve_bcr<BW, 0><<<1, nt, shm, st>>>(I, d, sweep, nchunk, nullptr)          \
@@ -1236,7 +1276,7 @@ hipError_t launch_solve_fd(const DevInst& I, int d, int M, hipStream_t st) {
   if (!A.fdV || !A.fdmu || !A.fdz) return hipErrorInvalidValue;
   const int n = A.n;
   const size_t per = (size_t)(n + kFdSplit - 1) / kFdSplit;
-  k_fd_project<<<dim3((n + 63) / 64, kFdSplit), 256, sizeof(double) * per, st>>>(I, d, rhs_chunks(I, M, 0));
+  k_fd_project<<<dim3((n + 63) / 64, kFdSplit), 256, sizeof(double) * per, st>>>(I, d, rhs_chunks(I, d, M, 0));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t K = (size_t)(n + kFdKb - 1) / kFdKb;
@@ -1895,28 +1935,6 @@ hipError_t launch_mxy_build(const DevInst& I, hipStream_t st) {
   const size_t t2 = (size_t)X.n * I.ax[1].n;
   if (I.mixed) k_mxy_t2<float><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
   else k_mxy_t2<double><<<(int)((t2 + 255) / 256), 256, 0, st>>>(I);
-  return hipGetLastError();
-}
-
-// F_0 = M_xy u_1 (d = 0) or F_1 = M_xy^T u_0 (d = 1): one wave per row.
-template <class T>
-__global__ void k_gemv(DevInst I, int d) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + w;
-  const int nrows = I.ax[d].n, ncols = I.ax[1 - d].n;
-  if (row >= nrows) return;
-  const T* Mat = (const T*)(d == 0 ? I.Mxy : I.MxyT) + (size_t)row * ncols;
-  const double* x = I.ax[1 - d].u;
-  double s = 0.0;
-  for (int j = l; j < ncols; j += 64) s += (double)Mat[j] * x[j];
-  s = wave_sum(s);
-  if (l == 0) I.ax[d].F[row] = s;
-}
-
-hipError_t launch_gemv(const DevInst& I, int d, hipStream_t st) {
-  const int blocks = (I.ax[d].n + 3) / 4;
-  if (I.mixed) k_gemv<float><<<blocks, 256, 0, st>>>(I, d);
-  else k_gemv<double><<<blocks, 256, 0, st>>>(I, d);
   return hipGetLastError();
 }
 

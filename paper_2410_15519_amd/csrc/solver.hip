@@ -406,8 +406,10 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.Mu, sizeof(double) * n);
     AL(X.Ku, sizeof(double) * n);
     AL(X.rhs, sizeof(double) * n);
-    AL(X.rpart, sizeof(double) * n * (size_t)((3 * s->Mcap + 63) / 64 + 1));
-    AL(X.F, sizeof(double) * n);
+    // RHS partials: linear column chunks, then the load chunks (2D: the
+    // columns of the M_xy product, 64 per chunk)
+    const size_t nload = s->dim == 2 ? (size_t)(s->ax[1 - d].n + 63) / 64 : 1;
+    AL(X.rpart, sizeof(double) * n * ((size_t)(3 * s->Mcap + 63) / 64 + nload));
     AL(X.v, sizeof(double) * nqp);
     if (mixed) AL(X.vf, sizeof(float) * nqp);
     AL(X.gm, sizeof(double) * M);
@@ -727,12 +729,15 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
         if (D == 3) {
           Work w = w_cubic(s, d);
           LAUNCH(s, CTD_K_CUBIC_H, w.flops, w.bytes, launch_cubic_h(s->I, d, s->stream));
-        } else {
-          Work w = w_gemv(s, d);
-          LAUNCH(s, CTD_K_GEMV, w.flops, w.bytes, launch_gemv(s->I, d, s->stream));
         }
         {
+          // 2D: the M_xy product is part of the RHS launch
           Work w = w_rhs(s, d, M);
+          if (D == 2) {
+            const Work wg = w_gemv(s, d);
+            w.flops += wg.flops;
+            w.bytes += wg.bytes;
+          }
           LAUNCH(s, CTD_K_RHS, w.flops, w.bytes, launch_rhs(s->I, d, M, s->stream));
           Work ws = w_solve(s, d);
           if (s->use_fd[d]) {
@@ -1120,8 +1125,6 @@ extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const*
     rc = cubic_after(s, e2, d);
     if (rc) return rc;
     HIPCHK(s, launch_cubic_h(s->I, d, s->stream));
-  } else {
-    HIPCHK(s, launch_gemv(s->I, d, s->stream));
   }
   HIPCHK(s, launch_rhs(s->I, d, 0, s->stream, 1));
   HIPCHK(s, launch_rhs_sum(s->I, d, 0, 1, s->stream));
