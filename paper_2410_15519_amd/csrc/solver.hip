@@ -216,7 +216,7 @@ Work w_sig(const ctd_solver* s, int d, int M) {
   const double v = s->dim == 3 ? nq : 0.0;
   return {2.0 * n * c + 2.0 * v * s->I.ax[d].SW, 8.0 * n * (c + 1) + 8.0 * v};
 }
-Work w_gemv(const ctd_solver* s, int d) {
+Work w_load2d(const ctd_solver* s, int d) {
   const double a = s->I.ax[d].n, b = s->I.ax[1 - d].n;
   return {2.0 * a * b, tsz(s) * a * b};
 }
@@ -734,7 +734,7 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
           // 2D: the M_xy product is part of the RHS launch
           Work w = w_rhs(s, d, M);
           if (D == 2) {
-            const Work wg = w_gemv(s, d);
+            const Work wg = w_load2d(s, d);
             w.flops += wg.flops;
             w.bytes += wg.bytes;
           }
