@@ -2,6 +2,7 @@
 
     python -m paper_2410_15519_amd.profsum trace DB TITLE CMD > summary.md
     python -m paper_2410_15519_amd.profsum pmc FETCH_CSV WRITE_CSV COPY_MIB TITLE CMD > summary.md
+    python -m paper_2410_15519_amd.profsum mfma COUNTER_CSV CUS TITLE CMD > summary.md
 
 `trace` groups the kernel records of a rocpd database by kernel name and
 grid.  `pmc` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
@@ -9,6 +10,8 @@ over two counter runs of the same command, scales each by what the counter
 reads for the plain copy kernel k_copy16 of COPY_MIB MiB, and prints the
 HBM traffic per launch of every kernel with the sha256 of the kernel source
 it was taken on (a reader of the summary can tell when the kernels changed).
+`mfma` reports the MFMA busy fraction and the executed MFMA flops per kernel
+from one counter run (see `mfma`).
 """
 from __future__ import annotations
 
@@ -122,11 +125,44 @@ def traffic_from_summary(path: str, kernel: str):
     return float(m.group(1)) if m else None
 
 
+def mfma(csv_path: str, cus: int, title: str, cmd: str, xcds: int = 8, simds: int = 4) -> str:
+    """MFMA activity per kernel and grid from one counter run holding
+    SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE, SQ_INSTS_VALU_MFMA_MOPS_F32 and
+    SQ_INSTS_VALU_MFMA_MOPS_F64 (per-dispatch means).  GRBM_GUI_ACTIVE reads
+    the sum over the XCDs; the MFMA busy cycles are summed over all SIMDs (32
+    per executed 16x16x4 FP32 MFMA).  Busy fraction = busy cycles /
+    (GRBM_GUI_ACTIVE / xcds x cus x simds); executed flops = MOPS count x 512."""
+    busy = _per_kernel(csv_path, "SQ_VALU_MFMA_BUSY_CYCLES")
+    act = _per_kernel(csv_path, "GRBM_GUI_ACTIVE")
+    m32 = _per_kernel(csv_path, "SQ_INSTS_VALU_MFMA_MOPS_F32")
+    m64 = _per_kernel(csv_path, "SQ_INSTS_VALU_MFMA_MOPS_F64")
+    names = sorted((k for k in busy if k in act and (m32.get(k, (0, 0))[1] + m64.get(k, (0, 0))[1]) > 0),
+                   key=lambda k: -busy[k][0] * busy[k][1])
+    out = [f"# {title}", "", "Commands (run from the repository root on one MI355X):", "", "```", cmd, "```", "",
+           f"Per-dispatch means per kernel name and grid size.  GRBM_GUI_ACTIVE is the sum over the {xcds} "
+           f"XCDs and the MFMA busy cycles the sum over the {cus * simds} SIMDs (32 per executed 16x16x4 "
+           f"FP32 MFMA), so MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / {xcds} x "
+           f"{cus * simds}); executed flops = SQ_INSTS_VALU_MFMA_MOPS_* x 512.", "",
+           f"kernel source sha256 (first 16 hex): {kernel_source_sha()}", "",
+           "| kernel [grid work-items] | dispatches | GRBM_GUI_ACTIVE | MFMA busy cycles | MFMA busy | executed FP32 MFMA GFLOP | executed FP64 MFMA GFLOP |",
+           "|---|---|---|---|---|---|---|"]
+    for k in names[:16]:
+        n, b = busy[k]
+        a = act[k][1]
+        f32 = m32.get(k, (0, 0.0))[1] * 512 / 1e9
+        f64 = m64.get(k, (0, 0.0))[1] * 512 / 1e9
+        frac = b / (a / xcds * cus * simds) if a > 0 else 0.0
+        out.append(f"| {k} | {n} | {a:.0f} | {b:.0f} | {100 * frac:.1f} % | {f32:.3f} | {f64:.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "trace":
         sys.stdout.write(trace(argv[1], argv[2], argv[3]))
     elif len(argv) >= 6 and argv[0] == "pmc":
         sys.stdout.write(pmc(argv[1], argv[2], float(argv[3]), argv[4], argv[5]))
+    elif len(argv) >= 5 and argv[0] == "mfma":
+        sys.stdout.write(mfma(argv[1], int(argv[2]), argv[3], argv[4]))
     else:
         raise SystemExit(__doc__)
 
