@@ -34,7 +34,9 @@ Legs (rank 0, one GPU):
   8. adaptive full-solve fallback (2D): full CFE steps of a 1024^2 instance
      (the second from a field state), step time and the FP64 MFMA rate of the
      dense eigenbasis products.
-Prints ONE JSON line on stdout; progress goes to stderr.
+Prints ONE JSON line on stdout; progress goes to stderr.  `--only LEG`
+(actd, batched, served, ps) runs a single leg and prints its JSON instead,
+for profiling that leg alone; it is not the benchmark line.
 """
 from __future__ import annotations
 
