@@ -4,7 +4,11 @@
 One "step" is one time step of the stabilized semi-implicit scheme solved in
 separated form by the HIP library (greedy enrichment, alternating fixed-point
 sweeps, banded 1D solves, cubic contractions, energy on the separated
-quadrature), on seeded synthetic cosine initial data held on the GPU.
+quadrature), on seeded synthetic cosine initial data held on the GPU.  The
+fixed-point iteration of mode m starts from mode m of u^k (`--init warm`,
+the default; the paper leaves the initial guess open) or from the
+counter-based random vector (`--init hash`); every leg uses the same choice,
+and leg 9 reports the other one.
 
 Legs (rank 0, one GPU):
   1. mixed precision (FP32 MFMA contractions, FP64 solves/decisions), adaptive:
@@ -34,6 +38,10 @@ Legs (rank 0, one GPU):
   8. adaptive full-solve fallback (2D): full CFE steps of a 1024^2 instance
      (the second from a field state), step time and the FP64 MFMA rate of the
      dense eigenbasis products.
+  9. the other initial guess: the headline workload and protocol with the
+     counter-based initial vector of a mode (the headline uses mode m of u^k,
+     `--init`), steps/s, sweeps, and one mixed step against FP64 with the
+     same decisions.
 Prints ONE JSON line on stdout; progress goes to stderr.  `--only LEG`
 (actd, batched, served, ps) runs a single leg and prints its JSON instead,
 for profiling that leg alone; it is not the benchmark line.
@@ -61,13 +69,13 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True):
+def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True, init="hash"):
     """W warmup steps (the last one timed per kernel class, all classes), then
     K timed steps with HIP events around the launches of the dominant class
     only (events on every launch would slow the launch cadence)."""
     import torch
     sched = "replay" if decisions is not None else "adaptive"
-    s = ctd.Solver(inst, precision=precision, schedule=sched, energy=True)
+    s = ctd.Solver(inst, precision=precision, schedule=sched, energy=True, init=init)
     if decisions is not None:
         s.set_decisions(decisions)
     dec = []
@@ -269,6 +277,49 @@ def actd_leg(ctd, n=1024, steps=2):
     return out
 
 
+def init_leg(ctd, inst, warmup, steps, init):
+    """The same workload and protocol as the headline with another initial
+    guess of a mode ("hash": the counter-based random vector; "warm": mode m
+    of u^k; the paper leaves the initial guess open): steps/s and sweeps, and
+    one mixed step against the FP64 step with the same decisions from the same
+    FP64 state (relative nodal l2)."""
+    import numpy as np
+    import torch
+    from workloads import Instance
+    s, infos, el, _, dec = run_leg(ctd, inst, "mixed", warmup, steps, profile=False, init=init)
+    s.close()
+    out = {"init": init, "steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+           "sweeps_per_step": float(np.mean([i["sweeps"] for i in infos])),
+           "modes_per_step": float(np.mean([i["modes"] for i in infos]))}
+    # FP64 reference state after warmup + steps - 1 steps (replaying the mixed
+    # decisions), then one FP64 and one mixed step from it
+    k_prev = warmup + steps - 1
+    ref = ctd.Solver(inst, precision="fp64", schedule="replay", init=init)
+    ref.set_decisions(dec[:k_prev])
+    ref.step(k_prev)
+    amp, fac = ref.modes()
+    ref.set_decisions(dec[k_prev:])
+    ref.step(1)
+    n = int(np.prod(inst.nodes))
+    U64 = torch.empty(n, dtype=torch.float64, device="cuda")
+    ref.reconstruct("f64", out=U64)
+    ref.close()
+    st = Instance(**{**inst.__dict__, "amp": amp, "factors": fac})
+    one = ctd.Solver(st, precision="mixed", schedule="replay", init=init)
+    one.step_index = k_prev
+    one.set_decisions(dec[k_prev:])
+    one.step(1)
+    U1 = torch.empty(n, dtype=torch.float64, device="cuda")
+    one.reconstruct("f64", out=U1)
+    one.close()
+    out["rel_l2_step_mixed_vs_fp64"] = float(torch.linalg.norm(U1 - U64) / torch.linalg.norm(U64))
+    del U1, U64
+    torch.cuda.empty_cache()
+    log(f"  [init {init}] {out['steps_per_s']:.3f} steps/s, {out['sweeps_per_step']:.0f} sweeps/step, "
+        f"mixed vs FP64 step {out['rel_l2_step_mixed_vs_fp64']:.2e}")
+    return out
+
+
 def served_leg(ctd, count=32, step_scale=20, workers=8):
     """Poisson arrivals into the server; latency from arrival to completion."""
     import numpy as np
@@ -317,6 +368,9 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
     ap.add_argument("--no-ps", action="store_true", help="skip the (p, s) sweep")
     ap.add_argument("--no-actd", action="store_true", help="skip the full-solve fallback leg")
+    ap.add_argument("--init", choices=["warm", "hash"], default="warm",
+                    help="initial guess of a mode: mode m of u^k (warm) or the counter-based vector")
+    ap.add_argument("--no-alt-init", action="store_true", help="skip the leg with the other initial guess")
     ap.add_argument("--only", choices=["actd", "batched", "served", "ps"],
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
@@ -352,7 +406,8 @@ def main():
         f"max_modes={inst.max_modes}")
 
     # leg 1: mixed, adaptive (the headline)
-    s_mix, infos, elapsed, prof, dec_all = run_leg(ctd, inst, "mixed", args.warmup, args.steps)
+    s_mix, infos, elapsed, prof, dec_all = run_leg(ctd, inst, "mixed", args.warmup, args.steps,
+                                                   init=args.init)
     value = args.steps / elapsed
     dom, roof = roofline_of(prof["timed"], "mixed", args.workload)
     sweeps_per_step = float(np.mean([i["sweeps"] for i in infos]))
@@ -396,13 +451,14 @@ def main():
         s_mix.close()
         del s_mix
         # leg 2: FP64 adaptive (timed for context); keep u^k before its last step
-        s64 = ctd.Solver(inst, precision="fp64", energy=True)
+        s64 = ctd.Solver(inst, precision="fp64", energy=True, init=args.init)
         for k in range(args.warmup + args.steps - 1):
             s64.step(1)
         amp_prev, fac_prev = s64.modes()
         k_prev = s64.step_index
         s64.close()
-        s64, infos64, el64, prof64, dec64 = run_leg(ctd, inst, "fp64", args.warmup, args.steps)
+        s64, infos64, el64, prof64, dec64 = run_leg(ctd, inst, "fp64", args.warmup, args.steps,
+                                                    init=args.init)
         fp64 = {"steps_per_s": args.steps / el64,
                 "dominant": roofline_of(prof64["timed"], "fp64", args.workload)[1]}
         U64 = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -413,7 +469,7 @@ def main():
         st = Instance(dim=inst.dim, nodes=inst.nodes, eps=inst.eps, S=inst.S, dt=inst.dt,
                       steps=1, amp=amp_prev, factors=fac_prev, max_modes=inst.max_modes,
                       seed=inst.seed, enrich_tol=inst.enrich_tol)
-        one = ctd.Solver(st, precision="mixed", schedule="replay")
+        one = ctd.Solver(st, precision="mixed", schedule="replay", init=args.init)
         one.step_index = k_prev
         one.set_decisions(dec64[-1:])
         one.step(1)
@@ -424,7 +480,7 @@ def main():
         del U1
         # leg 3d: the same single step in FP64 from u^k with amplitudes perturbed by 1e-14
         stp = Instance(**{**st.__dict__, "amp": amp_prev * (1.0 + 1e-14)})
-        onep = ctd.Solver(stp, precision="fp64", schedule="replay")
+        onep = ctd.Solver(stp, precision="fp64", schedule="replay", init=args.init)
         onep.step_index = k_prev
         onep.set_decisions(dec64[-1:])
         onep.step(1)
@@ -435,7 +491,7 @@ def main():
         del U1
         # leg 3b: accumulated difference of the mixed run against FP64 replaying its decisions
         sref, _, _, _, _ = run_leg(ctd, inst, "fp64", 0, args.warmup + args.steps,
-                                   decisions=dec_all, profile=False)
+                                   decisions=dec_all, profile=False, init=args.init)
         Uref = torch.empty(n, dtype=torch.float64, device="cuda")
         sref.reconstruct("f64", out=Uref)
         sref.close()
@@ -445,7 +501,7 @@ def main():
         # of the same decisions from u0 with amplitudes perturbed by 1e-14
         pert = Instance(**{**inst.__dict__, "amp": inst.amp * (1.0 + 1e-14)})
         sp, _, _, _, _ = run_leg(ctd, pert, "fp64", 0, args.warmup + args.steps,
-                                 decisions=dec_all, profile=False)
+                                 decisions=dec_all, profile=False, init=args.init)
         Up = torch.empty(n, dtype=torch.float64, device="cuda")
         sp.reconstruct("f64", out=Up)
         sp.close()
@@ -472,6 +528,8 @@ def main():
         batched = batched_leg(ctd)
         served = served_leg(ctd)
     ps_sweep = None if args.no_ps else ps_sweep_leg(ctd)
+    other = "hash" if args.init == "warm" else "warm"
+    alt_init = None if args.no_alt_init else init_leg(ctd, inst, args.warmup, args.steps, other)
     actd = None if args.no_actd else actd_leg(ctd)
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
     out = {
@@ -483,13 +541,14 @@ def main():
         "config": {"workload": args.workload, "dim": inst.dim, "nodes": list(inst.nodes),
                    "eps": inst.eps, "S": inst.S, "dt": inst.dt, "max_modes": inst.max_modes,
                    "precision": "mixed", "init_modes": int(len(inst.amp)), "s": inst.patch_s,
-                   "p": inst.poly_p, "a": inst.dilation_a},
+                   "p": inst.poly_p, "a": inst.dilation_a, "init": args.init},
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64": fp64,
         "served": served,
         "batched": batched,
         "ps_sweep": ps_sweep,
+        "alt_init": alt_init,
         "actd": actd,
         "detail": extra,
     }
