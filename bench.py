@@ -184,7 +184,7 @@ def cpu_baseline(inst, sweeps_per_step, budget_s=20.0):
                        f"{sweeps_per_step:.0f} sweeps x {inst.dim} directions per step measured on the GPU")}
 
 
-def batched_leg(ctd, count=24, steps=2, workers=8):
+def batched_leg(ctd, count=24, steps=2, workers=8, init="warm"):
     """Instance-steps/s of a concurrent batch (and of the same batch on one worker)."""
     import torch
     from workloads import make_batch
@@ -192,7 +192,7 @@ def batched_leg(ctd, count=24, steps=2, workers=8):
     out = {"instances": count, "steps": steps,
            "nodes": sorted(int(i.nodes[0]) for i in insts)}
     for w in (1, workers):
-        b = ctd.Batch(insts, precision="mixed")
+        b = ctd.Batch(insts, precision="mixed", init=init)
         b.set_workers(w)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -205,7 +205,7 @@ def batched_leg(ctd, count=24, steps=2, workers=8):
     return out
 
 
-def ps_sweep_leg(ctd, workload="ac3d_n256", warmup=1, steps=1):
+def ps_sweep_leg(ctd, workload="ac3d_n256", warmup=1, steps=1, init="warm"):
     """Cost of the CTD step across the CFE parameters (p, s) of the paper's
     Sec. 4 study, on one 3D workload: set-up time (host CFE tables, banded
     matrices, eigenvectors of the fast diagonalisation), ms per step and per
@@ -217,7 +217,7 @@ def ps_sweep_leg(ctd, workload="ac3d_n256", warmup=1, steps=1):
         inst = make_instance(workload, patch_s=s, poly_p=p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        sv = ctd.Solver(inst, precision="mixed")
+        sv = ctd.Solver(inst, precision="mixed", init=init)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
         sv.step(warmup)
@@ -320,7 +320,7 @@ def init_leg(ctd, inst, warmup, steps, init):
     return out
 
 
-def served_leg(ctd, count=32, step_scale=20, workers=8):
+def served_leg(ctd, count=32, step_scale=20, workers=8, init="warm"):
     """Poisson arrivals into the server; latency from arrival to completion."""
     import numpy as np
     from workloads import make_requests, CONFIGS
@@ -334,7 +334,7 @@ def served_leg(ctd, count=32, step_scale=20, workers=8):
         dt = t_arr - (time.perf_counter() - t0)
         if dt > 0:
             time.sleep(dt)
-        tickets.append((srv.submit(inst, precision="mixed"), inst))
+        tickets.append((srv.submit(inst, precision="mixed", init=init), inst))
     for t, _ in tickets:
         srv.wait(t)
     st = [srv.status(t) for t, _ in tickets]
@@ -398,7 +398,9 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     if args.only:
-        legs = {"actd": actd_leg, "batched": batched_leg, "served": served_leg, "ps": ps_sweep_leg}
+        legs = {"actd": lambda c: actd_leg(c), "batched": lambda c: batched_leg(c, init=args.init),
+                "served": lambda c: served_leg(c, init=args.init),
+                "ps": lambda c: ps_sweep_leg(c, init=args.init)}
         print(json.dumps({args.only: legs[args.only](ctd)}))
         return
     inst = make_instance(args.workload)
@@ -525,9 +527,9 @@ def main():
         del loads, inst128
     batched = served = None
     if not args.no_serve:
-        batched = batched_leg(ctd)
-        served = served_leg(ctd)
-    ps_sweep = None if args.no_ps else ps_sweep_leg(ctd)
+        batched = batched_leg(ctd, init=args.init)
+        served = served_leg(ctd, init=args.init)
+    ps_sweep = None if args.no_ps else ps_sweep_leg(ctd, init=args.init)
     other = "hash" if args.init == "warm" else "warm"
     alt_init = None if args.no_alt_init else init_leg(ctd, inst, args.warmup, args.steps, other)
     actd = None if args.no_actd else actd_leg(ctd)

@@ -41,10 +41,11 @@ def uneven_2d(count, seed=11):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_batch_concurrent_equals_standalone(ctd, prec):
+@pytest.mark.parametrize("init", ["hash", "warm"])
+def test_batch_concurrent_equals_standalone(ctd, prec, init):
     insts = uneven_2d(6)
-    print(f"batch sizes {[i.nodes[0] for i in insts]} prec={prec}", flush=True)
-    b = ctd.Batch(insts, precision=prec)
+    print(f"batch sizes {[i.nodes[0] for i in insts]} prec={prec} init={init}", flush=True)
+    b = ctd.Batch(insts, precision=prec, init=init)
     try:
         b.set_workers(4)
         b.step(2)
@@ -52,7 +53,7 @@ def test_batch_concurrent_equals_standalone(ctd, prec):
     finally:
         b.close()
     for i, inst in enumerate(insts):
-        assert same_modes(got[i], standalone(ctd, inst, 2, precision=prec)), f"instance {i}"
+        assert same_modes(got[i], standalone(ctd, inst, 2, precision=prec, init=init)), f"instance {i}"
 
 
 def test_served_alone_equals_mix(ctd):
