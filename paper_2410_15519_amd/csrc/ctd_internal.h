@@ -131,7 +131,11 @@ hipError_t launch_init_mode(const DevInst& I, int64_t step, int mode, int warm,
                             hipStream_t st);
 hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
                            hipStream_t st, int nparts = 0);
+// normalisation of the initial guesses of every direction in one launch
+// (one workgroup per direction; all axes share the band width)
+hipError_t launch_finalize_init(const DevInst& I, hipStream_t st);
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
+hipError_t launch_signature_all(const DevInst& I, int M, hipStream_t st);   // every direction, one launch
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);
 // index of the last RHS partial chunk of direction d (consumers add chunks

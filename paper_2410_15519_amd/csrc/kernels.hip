@@ -386,7 +386,25 @@ template <int B>
 __global__ __launch_bounds__(1024) void k_finalize(DevInst I, int d, int sweep, int from_init, int nparts) {
   __shared__ double red[96];
   extern __shared__ double ul[];
-  finalize_body<B>(I, d, sweep, from_init, red, ul, nparts);
+  // d < 0: every direction at once, one workgroup each (the initial guesses)
+  finalize_body<B>(I, d < 0 ? (int)blockIdx.x : d, sweep, from_init, red, ul, nparts);
+}
+
+hipError_t launch_finalize_init(const DevInst& I, hipStream_t st) {
+  int n = 0;
+  for (int e = 0; e < I.dim; ++e) {
+    if (I.ax[e].B != I.ax[0].B) return hipErrorInvalidValue;
+    n = n > I.ax[e].n ? n : I.ax[e].n;
+  }
+  const size_t shm = sizeof(double) * 3 * (size_t)n;
+  const int nt = n >= 1024 ? 1024 : (n + 63) / 64 * 64;
+  switch (I.ax[0].B) {
+    case 3: k_finalize<3><<<I.dim, nt, shm, st>>>(I, -1, 0, 1, 0); break;
+    case 5: k_finalize<5><<<I.dim, nt, shm, st>>>(I, -1, 0, 1, 0); break;
+    case 7: k_finalize<7><<<I.dim, nt, shm, st>>>(I, -1, 0, 1, 0); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
@@ -408,7 +426,8 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
 // (gm = X^T M u, gk = X^T K u over the M modes of u^{k+1}, gmk = X^kT M u)
 // and v = W * (Phi u) at the Gauss points (3D cubic route).
 __global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v) {
-  DevAxis& A = I.ax[d];
+  // d < 0: every direction at once, direction blockIdx.y (the initial guesses)
+  DevAxis& A = I.ax[d < 0 ? (int)blockIdx.y : d];
   const int n = A.n;
   if ((int)blockIdx.x < ndot_blocks) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -446,6 +465,17 @@ hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st) {
   const int nv = want_v ? (I.ax[d].nq + 255) / 256 : 0;
   if (ndot + nv == 0) return hipSuccess;
   k_signature<<<ndot + nv, 256, 0, st>>>(I, d, M, ndot, want_v);
+  return hipGetLastError();
+}
+
+hipError_t launch_signature_all(const DevInst& I, int M, hipStream_t st) {
+  const int total = 2 * M + I.Mk;
+  const int ndot = (total + 3) / 4;
+  const int want_v = I.dim == 3;
+  int nv = 0;
+  for (int e = 0; want_v && e < I.dim; ++e) nv = nv > (I.ax[e].nq + 255) / 256 ? nv : (I.ax[e].nq + 255) / 256;
+  if (ndot + nv == 0) return hipSuccess;
+  k_signature<<<dim3(ndot + nv, I.dim), 256, 0, st>>>(I, -1, M, ndot, want_v);
   return hipGetLastError();
 }
 

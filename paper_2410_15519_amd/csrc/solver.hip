@@ -709,10 +709,16 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
   for (int mode = 0; mode < (full_replay ? 0 : max_modes); ++mode) {
     HIPCHK(s, launch_reset_scalars(s->I, s->stream));
     HIPCHK(s, launch_init_mode(s->I, s->step_index, mode, warm, s->stream));
-    for (int d = 0; d < D; ++d) HIPCHK(s, launch_finalize(s->I, d, 0, 1, s->stream));
-    for (int d = 0; d < D; ++d) {
-      Work w = w_sig(s, d, M);
-      LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
+    HIPCHK(s, launch_finalize_init(s->I, s->stream));
+    {
+      // the initial guesses' Grams and Gauss-point values, every direction in one launch
+      Work w{0.0, 0.0};
+      for (int d = 0; d < D; ++d) {
+        const Work wd = w_sig(s, d, M);
+        w.flops += wd.flops;
+        w.bytes += wd.bytes;
+      }
+      LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature_all(s->I, M, s->stream));
     }
     if (D == 3) {
       int rc = cubic_after(s, 1, -1);
