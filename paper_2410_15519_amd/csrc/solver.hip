@@ -764,8 +764,11 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
       if (adaptive) {
         int rc = read_scalars(s);
         if (rc) return rc;
-        if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
+        // a zero amplitude ends the mode (Sec. 3.3 stopping) before the
+        // non-finite test: the directions solved after it in the same sweep
+        // see zero fixed factors and produce NaN for a mode that is dropped
         if (s->sc_host->zero) { zero = 1; break; }
+        if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
         conv = s->sc_host->converged != 0 && it >= 2;
         if (conv) last = true;
       }

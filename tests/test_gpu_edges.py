@@ -1,0 +1,95 @@
+"""Degenerate and boundary cases of the step on the GPU against the oracle:
+the zero field (the first mode has zero amplitude and ends the step, Sec.
+3.3 stopping), the smallest mesh the CFE space allows (2s + 2 nodes per
+axis), a single initial mode, and a constant field (every mode of u^{k+1}
+is again constant)."""
+import numpy as np
+import pytest
+
+from oracle.ctd import ctd_step, full_field, state_from_instance
+from oracle.scheme import problem_from_instance
+from workloads import Instance, small_instance
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_15519_amd import ctd as mod
+    return mod
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("dim,n", [(2, 20), (3, 12)])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_zero_field_stays_zero(ctd, dim, n, prec):
+    base = small_instance(dim=dim, n=n, m0=2, kmax=3)
+    inst = Instance(**{**base.__dict__, "amp": np.zeros_like(base.amp)})
+    pr = problem_from_instance(inst)
+    st, lg = ctd_step(pr, state_from_instance(inst), 0)
+    assert lg.stop == "zero" and st.modes == 0
+    with ctd.Solver(inst, precision=prec) as s:
+        info = s.step(1)[0]
+        assert info["modes"] == 0 and info["zero_mode"] == 1
+        assert not np.any(s.reconstruct())
+        assert s.decisions() == [[]]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("s_patch", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smallest_mesh(ctd, dim, s_patch, prec):
+    n = 2 * s_patch + 2
+    inst = small_instance(dim=dim, n=n, m0=2, kmax=2, max_modes=8, patch_s=s_patch,
+                          poly_p=min(2, s_patch))
+    pr = problem_from_instance(inst)
+    st, lg = ctd_step(pr, state_from_instance(inst), 0)
+    ref = full_field(st)
+    print(f"smallest mesh dim={dim} n={n} modes={len(lg.iters)} prec={prec}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay") as s:
+        s.set_decisions([lg.iters])
+        s.step(1)
+        err = rel(s.reconstruct(), ref)
+    assert err < (1e-10 if prec == "fp64" else 1e-6), err
+
+
+@pytest.mark.parametrize("dim,n", [(2, 33), (3, 17)])
+def test_single_initial_mode(ctd, dim, n):
+    inst = small_instance(dim=dim, n=n, m0=1, kmax=3, max_modes=16)
+    pr = problem_from_instance(inst)
+    st = state_from_instance(inst)
+    logs, fields = [], []
+    for k in range(2):
+        st, lg = ctd_step(pr, st, k)
+        logs.append(lg)
+        fields.append(full_field(st))
+    with ctd.Solver(inst, precision="fp64") as s:
+        s.step(2)
+        assert s.decisions() == [lg.iters for lg in logs]
+        assert rel(s.reconstruct(), fields[-1]) < 1e-10
+
+
+@pytest.mark.parametrize("dim,n", [(2, 25), (3, 13)])
+def test_constant_field(ctd, dim, n):
+    """u^k = 0.5 everywhere: u^{k+1} is constant again (the nonlinear and
+    linear loads are multiples of the same constant).  One mode (the cap):
+    the second mode of this step has an amplitude at the enrichment
+    tolerance and no well-defined direction."""
+    base = small_instance(dim=dim, n=n, m0=1, kmax=1, max_modes=1)
+    inst = Instance(**{**base.__dict__, "amp": np.array([0.5]),
+                       "factors": [np.ones((m, 1)) for m in base.nodes]})
+    pr = problem_from_instance(inst)
+    st, lg = ctd_step(pr, state_from_instance(inst), 0)
+    ref = full_field(st)
+    with ctd.Solver(inst, precision="fp64", schedule="replay") as s:
+        s.set_decisions([lg.iters])
+        s.step(1)
+        U = s.reconstruct()
+    assert rel(U, ref) < 1e-10
+    assert np.ptp(U) < 1e-10 * np.abs(U).max()
