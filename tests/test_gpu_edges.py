@@ -29,16 +29,24 @@ def rel(a, b):
 @pytest.mark.parametrize("dim,n", [(2, 20), (3, 12)])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_zero_field_stays_zero(ctd, dim, n, prec):
+    """A zero field: the first mode has zero amplitude, u^{k+1} = 0, and the
+    energy is that of the zero state."""
     base = small_instance(dim=dim, n=n, m0=2, kmax=3)
     inst = Instance(**{**base.__dict__, "amp": np.zeros_like(base.amp)})
     pr = problem_from_instance(inst)
     st, lg = ctd_step(pr, state_from_instance(inst), 0)
     assert lg.stop == "zero" and st.modes == 0
-    with ctd.Solver(inst, precision=prec) as s:
+    with ctd.Solver(inst, precision=prec, energy=True) as s:
         info = s.step(1)[0]
         assert info["modes"] == 0 and info["zero_mode"] == 1
         assert not np.any(s.reconstruct())
         assert s.decisions() == [[]]
+        # E(0) = a0 |Omega| (Sec. 2.1 energy; a0 = 1/4, unit box)
+        assert info["energy"] == pytest.approx(0.25, rel=1e-13)
+        assert s.energy() == pytest.approx(0.25, rel=1e-13)
+        # and the next step from the zero field is again the zero field
+        info = s.step(1)[0]
+        assert info["modes"] == 0 and not np.any(s.reconstruct())
 
 
 @pytest.mark.parametrize("dim", [2, 3])
