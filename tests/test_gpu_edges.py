@@ -101,3 +101,33 @@ def test_constant_field(ctd, dim, n):
         U = s.reconstruct()
     assert rel(U, ref) < 1e-10
     assert np.ptp(U) < 1e-10 * np.abs(U).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 21), (3, 11)])
+def test_single_sweep_per_mode(ctd, dim, n):
+    """fp_max_iter = 1: every mode takes exactly one sweep (no fixed-point
+    test is possible before the second), decisions as the oracle's."""
+    inst = small_instance(dim=dim, n=n, m0=2, kmax=3, max_modes=10, fp_max_iter=1)
+    pr = problem_from_instance(inst)
+    st, lg = ctd_step(pr, state_from_instance(inst), 0)
+    assert set(lg.iters) == {1}
+    with ctd.Solver(inst, precision="fp64") as s:
+        s.step(1)
+        assert s.decisions() == [lg.iters]
+        assert rel(s.reconstruct(), full_field(st)) < 1e-10
+
+
+def test_actd_full_solve_of_zero_field(ctd):
+    """The full solve of a zero field is the zero field, and the CTD step
+    from that field state drops its first mode."""
+    base = small_instance(dim=2, n=(13, 10), m0=2, kmax=3, max_modes=4)
+    inst = Instance(**{**base.__dict__, "amp": np.zeros_like(base.amp)})
+    with ctd.Solver(inst, precision="fp64", schedule="replay", actd=True, energy=True) as s:
+        s.set_decisions(["full"])
+        info = s.step(1)[0]
+        assert info["full_solve"] == 1 and info["modes"] == 10
+        assert not np.any(s.reconstruct())
+        assert info["energy"] == pytest.approx(0.25, rel=1e-13)
+    with ctd.Solver(inst, precision="fp64", actd=True) as s:
+        info = s.step(1)[0]
+        assert info["modes"] == 0 and info["zero_mode"] == 1
