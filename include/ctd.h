@@ -257,7 +257,8 @@ int ctd_server_submit(ctd_server* srv, const ctd_problem* p, int32_t m0,
                       int32_t nsteps, int64_t* ticket);
 int ctd_server_status(ctd_server* srv, int64_t ticket, ctd_request_status* st);
 /* Block until the request is DONE or FAILED, or timeout_ms passes
- * (< 0: no limit); CTD_EAGAIN on timeout. */
+ * (< 0: no limit); CTD_EAGAIN on timeout; a FAILED request returns its own
+ * error code (its message through ctd_server_last_error). */
 int ctd_server_wait(ctd_server* srv, int64_t ticket, double timeout_ms);
 /* Modes of a DONE request (host buffers as in ctd_get_modes, cap >= modes);
  * release != 0 frees its device memory and forgets the ticket. */

@@ -9,7 +9,7 @@ standalone solver is the reference.
 import numpy as np
 import pytest
 
-from workloads import small_instance, make_batch, make_requests
+from workloads import Instance, small_instance, make_batch, make_requests
 
 pytestmark = pytest.mark.gpu
 
@@ -111,3 +111,32 @@ def test_server_admits_by_footprint(ctd):
     with ctd.Server(budget_bytes=fa // 2, workers=1) as srv:
         with pytest.raises(ctd.CtdError):
             srv.submit(a, nsteps=1)
+
+
+def test_nonfinite_input_fails_alone(ctd):
+    """A request whose initial factors hold a NaN ends with ENONFINITE (the
+    kernels run normally on it); the requests served beside it complete and
+    equal their standalone runs."""
+    good = small_instance(dim=2, n=40, m0=3, kmax=4, seed=5, max_modes=12)
+    bad_f = [f.copy() for f in good.factors]
+    bad_f[1][7, 0] = float("nan")
+    bad = Instance(**{**good.__dict__, "factors": bad_f})
+    with ctd.Solver(bad, precision="fp64") as s:
+        with pytest.raises(ctd.CtdError) as ei:
+            s.step(1)
+        assert "NONFINITE" in str(ei.value)
+    ref = standalone(ctd, good, 2, precision="fp64")
+    with ctd.Server(workers=2) as srv:
+        tb = srv.submit(bad, nsteps=2, precision="fp64")
+        tg = srv.submit(good, nsteps=2, precision="fp64")
+        # waiting on a failed request returns its error
+        with pytest.raises(ctd.CtdError) as ei:
+            srv.wait(tb, 60000)
+        assert "NONFINITE" in str(ei.value)
+        assert srv.wait(tg, 60000)
+        assert srv.status(tb)["state"] == "failed"
+        assert srv.status(tg)["state"] == "done"
+        got = srv.fetch(tg)
+        stats = srv.stats()
+        assert stats["failed"] == 1 and stats["completed"] == 1
+    assert same_modes(got, ref)
