@@ -101,6 +101,10 @@ def test_constant_field(ctd, dim, n):
         U = s.reconstruct()
     assert rel(U, ref) < 1e-10
     assert np.ptp(U) < 1e-10 * np.abs(U).max()
+    # the scheme's scalar recurrence for a constant state (Sec. 2.5 with
+    # w = u^3 - u): u' = u - w(u) / (1/dt + alpha L)
+    u0 = 0.5
+    assert np.allclose(U, u0 - (u0 ** 3 - u0) / pr.c, rtol=1e-12, atol=0)
 
 
 @pytest.mark.parametrize("dim,n", [(2, 21), (3, 11)])
