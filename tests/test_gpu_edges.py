@@ -135,3 +135,30 @@ def test_actd_full_solve_of_zero_field(ctd):
     with ctd.Solver(inst, precision="fp64", actd=True) as s:
         info = s.step(1)[0]
         assert info["modes"] == 0 and info["zero_mode"] == 1
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_linear_case_eigen_product(ctd, dim):
+    """a0 = 0 (no nonlinear term, paper-form coefficients): u^k = prod_d v_d
+    with K v = mu M v is damped in one mode by c / (c + lam sum mu) (the
+    scheme of Sec. 2.5 diagonalised by the generalised eigenvectors)."""
+    import scipy.linalg as sla
+    n = 11
+    base = small_instance(dim=dim, n=n, m0=1, kmax=1, max_modes=4)
+    pr = problem_from_instance(base)
+    ax = pr.axes[0]
+    mu, V = sla.eigh(ax.K, ax.M)
+    idx = [2, 5, 3][:dim]
+    inst = Instance(**{**base.__dict__, "amp": np.array([0.6]),
+                       "factors": [V[:, [i]].copy() for i in idx]})
+    L, kappa, alpha, dt = 1.0, 0.04, 2.0, base.dt
+    c, lam = 1.0 / dt + alpha * L, L * kappa
+    factor = c / (c + lam * sum(mu[i] for i in idx))
+    U0 = 0.6
+    for v in [V[:, i] for i in idx]:
+        U0 = np.multiply.outer(U0, v) if np.ndim(U0) else U0 * v
+    with ctd.Solver(inst, precision="fp64", L=L, kappa=kappa, a0=0.0, alpha=alpha) as s:
+        info = s.step(1)[0]
+        U = s.reconstruct()
+    print(f"  linear dim={dim}: modes {info['modes']}, factor {factor:.12f}", flush=True)
+    assert np.abs(U - factor * U0).max() < 1e-10 * np.abs(U0).max()
