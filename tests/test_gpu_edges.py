@@ -162,3 +162,22 @@ def test_linear_case_eigen_product(ctd, dim):
         U = s.reconstruct()
     print(f"  linear dim={dim}: modes {info['modes']}, factor {factor:.12f}", flush=True)
     assert np.abs(U - factor * U0).max() < 1e-10 * np.abs(U0).max()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 19), (3, 13)])
+def test_data_constant_along_other_axes(ctd, dim, n):
+    """u^k constant along y (and z): u^{k+1} stays constant along them (the
+    step reduces to a 1D CFE problem), and equals the oracle's."""
+    base = small_instance(dim=dim, n=n, m0=2, kmax=3, max_modes=6)
+    fac = [base.factors[0]] + [np.ones((m, 2)) for m in base.nodes[1:]]
+    inst = Instance(**{**base.__dict__, "factors": fac})
+    pr = problem_from_instance(inst)
+    st, lg = ctd_step(pr, state_from_instance(inst), 0)
+    ref = full_field(st)
+    with ctd.Solver(inst, precision="fp64", schedule="replay") as s:
+        s.set_decisions([lg.iters])
+        s.step(1)
+        U = s.reconstruct()
+    assert rel(U, ref) < 1e-10
+    spread = np.ptp(U.reshape(U.shape[0], -1), axis=1).max()
+    assert spread < 1e-10 * np.abs(U).max()
