@@ -181,3 +181,26 @@ def test_data_constant_along_other_axes(ctd, dim, n):
     assert rel(U, ref) < 1e-10
     spread = np.ptp(U.reshape(U.shape[0], -1), axis=1).max()
     assert spread < 1e-10 * np.abs(U).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("solve", ["fd", "bcr"])
+def test_strongly_anisotropic_3d(ctd, prec, solve):
+    """9 x 70 x 131 nodes: the split counts follow the shortest axis while
+    every axis pads its own tables; replayed step against the oracle."""
+    inst = small_instance(dim=3, n=(9, 70, 131), m0=3, kmax=4, eps=0.05, dt=1e-3, max_modes=20)
+    key = ("aniso",)
+    if key not in _aniso:
+        pr = problem_from_instance(inst)
+        st, lg = ctd_step(pr, state_from_instance(inst), 0)
+        _aniso[key] = (full_field(st), lg.iters)
+    ref, iters = _aniso[key]
+    with ctd.Solver(inst, precision=prec, schedule="replay", solve=solve) as s:
+        s.set_decisions([iters])
+        s.step(1)
+        err = rel(s.reconstruct(), ref)
+    print(f"  anisotropic {prec} {solve}: {err:.2e}", flush=True)
+    assert err < (1e-10 if prec == "fp64" else 1e-6)
+
+
+_aniso = {}
