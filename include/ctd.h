@@ -15,8 +15,10 @@
  *   - Every function returns an int status: CTD_OK (0) or a negative code.
  *     Nothing aborts or throws; ctd_last_error() gives a message.
  *   - Host arrays passed in are copied during the call; the caller keeps
- *     ownership.  Device memory is owned by the library (hipMalloc) and
- *     released by ctd_destroy / ctd_batch_destroy.
+ *     ownership.  Device memory of an instance comes from the caller's
+ *     allocator when ctd_problem.dev_alloc / dev_free are set (e.g. a
+ *     framework's caching allocator), else from hipMallocAsync on the
+ *     instance's stream; it is held until ctd_destroy / ctd_batch_destroy.
  *   - All device work of a handle is ordered on the HIP stream given at
  *     creation (NULL = the null stream).  One host thread at a time per handle.
  *   - Factor matrices are column-major: column m (one mode) is contiguous,
@@ -34,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CTD_ABI_VERSION 2
+#define CTD_ABI_VERSION 3
 
 enum {
   CTD_OK = 0,
@@ -87,7 +89,20 @@ enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
  *   Needs nodes[d] <= 2048; the set-up computes both axes' eigenbases on the
  *   host (O(n^3)) and the device footprint holds nodes[1] modes of u^k.
  *   3D: CTD_EUNSUPPORTED.
+ * dev_alloc / dev_free / alloc_ctx: optional device allocator (both set or
+ *   both NULL).  dev_alloc(bytes, hip_stream, ctx) returns device memory
+ *   usable in stream order on hip_stream (NULL = out of memory ->
+ *   CTD_ENOMEM); dev_free(ptr, bytes, hip_stream, ctx) returns it, called
+ *   only after the instance's stream has been synchronised.  The callbacks
+ *   may run on the library's worker threads (batch, server) and must be
+ *   thread-safe.  Stability: the scheme is energy stable for
+ *   alpha >= max(w')/2 = 4 a0 on |u| <= 1 (Sec. 2.5,
+ *   eq. AC-discrete-semi-stable-step); a smaller alpha is accepted and
+ *   reported by ctd_step_info.stability_warning.
  */
+typedef void* (*ctd_dev_alloc_fn)(uint64_t bytes, void* hip_stream, void* ctx);
+typedef void (*ctd_dev_free_fn)(void* ptr, uint64_t bytes, void* hip_stream, void* ctx);
+
 typedef struct ctd_problem {
   int32_t abi_version;      /* CTD_ABI_VERSION */
   int32_t dim;              /* 2 or 3 */
@@ -109,6 +124,9 @@ typedef struct ctd_problem {
   int32_t solve_method;     /* CTD_SOLVE_AUTO | CTD_SOLVE_BCR | CTD_SOLVE_FD */
   int32_t actd;             /* nonzero: full CFE solve past max_modes (2D) */
   uint64_t seed;            /* keys the counter-based mode initialisation */
+  ctd_dev_alloc_fn dev_alloc;   /* optional device allocator (see above)  */
+  ctd_dev_free_fn dev_free;
+  void* alloc_ctx;
 } ctd_problem;
 
 /* Per-step report of ctd_step. */
@@ -120,6 +138,8 @@ typedef struct ctd_step_info {
   int32_t zero_mode;        /* 1 if a zero-amplitude mode ended the step */
   int32_t energy_increase;  /* 1 if energy rose by more than 1e-12 relative */
   int32_t full_solve;       /* 1 if the step was the full CFE solve (actd) */
+  int32_t stability_warning;/* 1 if alpha < max(w')/2 = 4 a0: the energy law of
+                               App. A is not guaranteed (Sec. 2.5)          */
   double energy;            /* E(u^{k+1}) if energy_each_step, else NaN */
   double last_term_max;     /* nodal max of the last appended mode */
   double ms;                /* wall time of the step on the host clock */
@@ -129,7 +149,9 @@ typedef struct ctd_solver ctd_solver;
 
 /* Fill *p with defaults: dim 2, 64 nodes on [0,1], eps 0.02, S 2, dt 1e-3,
  * s = 2, p = 2, a = 12, 5 Gauss points, fp_tol 1e-2, 20 sweeps,
- * enrich_tol 1e-8, 64 modes, FP64, adaptive, hash init. */
+ * enrich_tol 1e-8, 64 modes, FP64, adaptive, warm initial guess of a mode
+ * (mode m of u^k, the counter-based vector past the modes of u^k), library
+ * allocation. */
 int ctd_problem_default(ctd_problem* p);
 
 /* Validate the problem, build the 1D CFE tables (App. B/C, eq. KxxMxx) on the
@@ -148,13 +170,26 @@ int ctd_step(ctd_solver* s, int32_t nsteps, ctd_step_info* info);
  * on the separated tensor Gauss rule, FP64. */
 int ctd_energy(ctd_solver* s, double* E);
 
-/* Dense nodal field into a caller buffer (C order, axis 0 slowest), dtype
- * CTD_DTYPE_F64 or CTD_DTYPE_F32; on_device != 0: out is device memory,
- * else host memory of prod(nodes) elements. */
-int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device);
+/* Dense nodal field of u^k, u[i0, i1(, i2)] = sum_m sigma_m prod_d X_d[i_d, m]
+ * (eq. CTD); nodal values equal the nodal coefficients by the Kronecker-delta
+ * property of the CFE shape functions (Sec. 3.2), so this is the field at the
+ * mesh nodes.  out: caller-owned buffer of dtype CTD_DTYPE_F64 or
+ * CTD_DTYPE_F32, device memory if on_device != 0, else host memory.
+ * strides: dim element strides (axis d of node index i_d at
+ * out[sum_d i_d strides[d]]), all > 0 and such that distinct nodes map to
+ * distinct elements (not checked beyond positivity); NULL = C order, axis 0
+ * slowest.  Non-contiguous layouts pass through a contiguous device
+ * temporary.  Synchronises the stream before returning. */
+int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device,
+                    const int64_t* strides);
 
-/* Current separated field: *m modes; amp (cap values) and out[d]
- * (nodes[d] x cap, column-major), host buffers; any may be NULL to query *m. */
+/* Current separated field u^k = sum_m amp[m] prod_d out[d][:, m] (eq. CTD;
+ * nodal coefficients = nodal values, Sec. 3.2): *m modes; amp (cap values)
+ * and out[d] (nodes[d] x cap, column-major), caller-owned host buffers; any
+ * may be NULL to query *m only.  cap < *m with a buffer given: CTD_EINVAL.
+ * Factors are unit in the M_d norm except along axis 0, which carries the
+ * sign; amp >= 0.  Together with ctd_get_step_index this is a checkpoint:
+ * ctd_init(p, m, out, amp, ...) and ctd_set_step_index resume the run. */
 int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out,
                   int32_t cap);
 
@@ -163,7 +198,8 @@ int ctd_get_step_index(ctd_solver* s, int64_t* k);
 int ctd_set_step_index(ctd_solver* s, int64_t k);
 
 /* Decision log of the last ctd_step call: per step, the number of modes
- * followed by the sweep count of each mode, or the single entry -1 for a
+ * followed by the sweep count of each mode (0 modes: the step's first mode
+ * had zero amplitude and u^{k+1} = 0), or the single entry -1 for a
  * step computed by the full CFE solve (actd), concatenated.  *len = ints
  * written (or needed, if cap is too small -> CTD_EINVAL). */
 int ctd_get_decisions(ctd_solver* s, int32_t* buf, int64_t cap, int64_t* len);
@@ -210,7 +246,7 @@ int ctd_batch_step(ctd_batch* b, int32_t nsteps, ctd_step_info* info);
 int ctd_batch_get_modes(ctd_batch* b, int32_t i, int32_t* m, double* amp,
                         double* const* out, int32_t cap);
 int ctd_batch_reconstruct(ctd_batch* b, int32_t i, void* out, int32_t dtype,
-                          int32_t on_device);
+                          int32_t on_device, const int64_t* strides);
 const char* ctd_batch_last_error(const ctd_batch* b);
 void ctd_batch_destroy(ctd_batch* b);
 
@@ -261,7 +297,11 @@ int ctd_server_status(ctd_server* srv, int64_t ticket, ctd_request_status* st);
  * error code (its message through ctd_server_last_error). */
 int ctd_server_wait(ctd_server* srv, int64_t ticket, double timeout_ms);
 /* Modes of a DONE request (host buffers as in ctd_get_modes, cap >= modes);
- * release != 0 frees its device memory and forgets the ticket. */
+ * release != 0 frees its device memory and forgets the ticket.  A FAILED
+ * request returns its error code; with release != 0 its ticket is forgotten
+ * too.  Tickets are claimed under the server's lock, so concurrent fetches of
+ * one ticket are safe: the first release wins, later calls get CTD_EINVAL
+ * (unknown ticket) or, while a release is in progress, CTD_EAGAIN. */
 int ctd_server_fetch(ctd_server* srv, int64_t ticket, int32_t* m, double* amp,
                      double* const* out, int32_t cap, int32_t release);
 int ctd_server_get_stats(ctd_server* srv, ctd_server_stats* st);

@@ -36,7 +36,7 @@ class Problem:
     enrich_tol: float = 1e-8
     max_modes: int = 64
     seed: int = 0
-    init: str = "hash"          # "hash" or "warm" (mode m of u^k when m < M_k)
+    init: str = "warm"          # "warm" (mode m of u^k when m < M_k) or "hash"
 
     @property
     def c(self):

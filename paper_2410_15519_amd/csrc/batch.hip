@@ -130,9 +130,10 @@ int ctd_batch_get_modes(ctd_batch* b, int32_t i, int32_t* m, double* amp,
   return ctd_get_modes(b->inst[i], m, amp, out, cap);
 }
 
-int ctd_batch_reconstruct(ctd_batch* b, int32_t i, void* out, int32_t dtype, int32_t on_device) {
+int ctd_batch_reconstruct(ctd_batch* b, int32_t i, void* out, int32_t dtype, int32_t on_device,
+                          const int64_t* strides) {
   if (!b || i < 0 || i >= (int)b->inst.size()) return CTD_EINVAL;
-  return ctd_reconstruct(b->inst[i], out, dtype, on_device);
+  return ctd_reconstruct(b->inst[i], out, dtype, on_device, strides);
 }
 
 const char* ctd_batch_last_error(const ctd_batch* b) {

@@ -157,12 +157,21 @@ hipError_t launch_energy(const DevInst& I, double* partial, int* npartial,
                          hipStream_t st);
 hipError_t launch_energy_grams(const DevInst& I, int M, double* partial,
                                hipStream_t st);
+// dst[sum_d i_d strides[d]] = src[C-order index of i], elements of esz bytes
+hipError_t launch_scatter_strided(const void* src, void* dst, int esz, int dim, const int64_t* n,
+                                  const int64_t* strides, hipStream_t st);
 hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
                               hipStream_t st);
 hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
                                    const double* Kb, const double* alpha,
                                    const double* beta, const double* b,
                                    double* x, int count, hipStream_t st);
+// device workspace the batched banded solve needs (0 when the block data of
+// a system fit in LDS), and the launch on a caller-provided workspace
+size_t band_solve_workspace_bytes(int n, int bw, int count);
+hipError_t launch_band_solve_batch_ws(int n, int bw, const double* Mb, const double* Kb,
+                                      const double* alpha, const double* beta, const double* b,
+                                      double* x, int count, double* gws, hipStream_t st);
 hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t st);
 constexpr int kFdSplit = 32;   // row splits of the projection V^T b
 constexpr int kFdKb = 8;      // eigenvector splits of the back-projection V z

@@ -1132,18 +1132,17 @@ __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_band_solve_bcr(int n,
   bcr_solve_par<B, MODE>(n, Mb, Kb, alpha[k], beta[k], b + (size_t)k * n, 0, x + (size_t)k * n, mem);
 }
 
-hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
-                                   const double* Kb, const double* alpha,
-                                   const double* beta, const double* b,
-                                   double* x, int count, hipStream_t st) {
+size_t band_solve_workspace_bytes(int n, int bw, int count) {
+  return bcr_fits(n, bw) ? 0 : bcr_lds_bytes(n, bw) * (size_t)count;
+}
+
+hipError_t launch_band_solve_batch_ws(int n, int bw, const double* Mb, const double* Kb,
+                                      const double* alpha, const double* beta, const double* b,
+                                      double* x, int count, double* gws, hipStream_t st) {
   const bool fits = bcr_fits(n, bw);
   const bool split = !fits && bcr_split_fits(n, bw);
+  if (!fits && !gws) return hipErrorInvalidValue;
   const size_t bytes = bcr_lds_bytes(n, bw);
-  double* gws = nullptr;
-  if (!fits) {
-    hipError_t e = hipMallocAsync((void**)&gws, bytes * (size_t)count, st);
-    if (e != hipSuccess) return e;
-  }
   const size_t shm = fits ? bytes : (split ? bcr_split_lds_bytes(n, bw) : 0);
   const int nt = bcr_threads(n, bw);
 #define BAND_BCR(BW)                                                                               \
@@ -1154,10 +1153,23 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
     case 3: BAND_BCR(3); break;
     case 5: BAND_BCR(5); break;
     case 7: BAND_BCR(7); break;
-    default: break;
+    default: return hipErrorInvalidValue;
   }
 #undef BAND_BCR
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
+                                   const double* Kb, const double* alpha,
+                                   const double* beta, const double* b,
+                                   double* x, int count, hipStream_t st) {
+  const size_t ws = band_solve_workspace_bytes(n, bw, count);
+  double* gws = nullptr;
+  if (ws) {
+    hipError_t e = hipMallocAsync((void**)&gws, ws, st);
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_band_solve_batch_ws(n, bw, Mb, Kb, alpha, beta, b, x, count, gws, st);
   if (gws) {
     hipError_t f = hipFreeAsync(gws, st);
     if (e == hipSuccess) e = f;
@@ -2319,6 +2331,34 @@ hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
   const int blocks = (int)((total + 255) / 256);
   if (dtype == CTD_DTYPE_F32) k_reconstruct<float><<<blocks, 256, 0, st>>>(I, M, (float*)out);
   else k_reconstruct<double><<<blocks, 256, 0, st>>>(I, M, (double*)out);
+  return hipGetLastError();
+}
+
+// Strided placement of a C-ordered nodal grid (caller layouts of
+// ctd_reconstruct): one element per lane, reads coalesced.
+template <class T>
+__global__ void k_scatter_strided(const T* __restrict__ src, T* __restrict__ dst, int64_t total,
+                                  int64_t n1, int64_t n2, int64_t s0, int64_t s1, int64_t s2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  const int64_t i2 = k % n2, r = k / n2, i1 = r % n1, i0 = r / n1;
+  dst[i0 * s0 + i1 * s1 + i2 * s2] = src[k];
+}
+
+hipError_t launch_scatter_strided(const void* src, void* dst, int esz, int dim, const int64_t* n,
+                                  const int64_t* strides, hipStream_t st) {
+  // view as three axes (leading unit axes for 2D)
+  int64_t nn[3] = {1, 1, 1}, ss[3] = {0, 0, 0};
+  for (int d = 0; d < dim; ++d) { nn[3 - dim + d] = n[d]; ss[3 - dim + d] = strides[d]; }
+  const int64_t total = nn[0] * nn[1] * nn[2];
+  if (total == 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (esz == 4)
+    k_scatter_strided<float><<<blocks, 256, 0, st>>>((const float*)src, (float*)dst, total, nn[1], nn[2],
+                                                     ss[0], ss[1], ss[2]);
+  else
+    k_scatter_strided<double><<<blocks, 256, 0, st>>>((const double*)src, (double*)dst, total, nn[1],
+                                                      nn[2], ss[0], ss[1], ss[2]);
   return hipGetLastError();
 }
 

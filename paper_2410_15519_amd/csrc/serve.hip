@@ -36,6 +36,7 @@ struct Request {
   int32_t state = CTD_REQ_QUEUED, error = 0, steps_done = 0, modes = 0;
   double t_submit = 0, t_start = 0, t_done = 0;
   ctd_solver* solver = nullptr;
+  bool busy = false;   // a fetch holds the request (claimed under the lock)
   std::string err;
 };
 
@@ -237,26 +238,37 @@ int ctd_server_fetch(ctd_server* S, int64_t ticket, int32_t* m, double* amp, dou
     std::lock_guard<std::mutex> lk(S->mu);
     r = find(S, ticket);
     if (!r) { S->err = "unknown ticket"; return CTD_EINVAL; }
+    if (r->state == CTD_REQ_FAILED) {
+      // its device memory went back at failure; release forgets the ticket
+      S->err = r->err;
+      const int code = r->error;
+      if (release && !r->busy) S->reqs.erase(ticket);
+      return code;
+    }
     if (r->state != CTD_REQ_DONE) { S->err = "request not done"; return CTD_EAGAIN; }
+    if (r->busy) { S->err = "request is being fetched by another thread"; return CTD_EAGAIN; }
+    // claimed: no worker touches a DONE request and no other fetch may now
+    r->busy = true;
   }
-  // a DONE request is touched by no worker: its solver is the caller's now
   int rc = ctd_get_modes(r->solver, m, amp, out, cap);
-  if (rc) {
+  if (rc || !release) {
     std::lock_guard<std::mutex> lk(S->mu);
-    S->err = ctd_last_error(r->solver);
+    if (rc) S->err = ctd_last_error(r->solver);
+    r->busy = false;
     return rc;
   }
-  if (release) {
-    // the worker stream may already run another request: free on the null
-    // stream (the worker streams are non-blocking, so this waits for nothing
-    // of theirs; the request's own work finished before it was marked done)
-    ctd::solver_bind_stream(r->solver, nullptr);
-    ctd_destroy(r->solver);
+  // the worker stream may already run another request: free on the null
+  // stream (the worker streams are non-blocking, so this waits for nothing
+  // of theirs; the request's own work finished before it was marked done)
+  ctd::solver_bind_stream(r->solver, nullptr);
+  ctd_destroy(r->solver);
+  r->solver = nullptr;
+  {
     std::lock_guard<std::mutex> lk(S->mu);
     S->in_use -= r->footprint;
     S->reqs.erase(ticket);
-    S->cv_work.notify_all();
   }
+  S->cv_work.notify_all();
   return CTD_OK;
 }
 

@@ -26,13 +26,36 @@ namespace {
 
 thread_local std::string g_init_error = "no error";
 
-// Device memory of one instance.  Buffers are cleared on the instance's
-// stream; in the dry mode only the byte count is kept (footprint queries).
+// Device memory of one instance: from the caller's allocator hooks when the
+// problem has them, else stream-ordered hipMallocAsync.  Buffers are cleared
+// on the instance's stream; in the dry mode only the byte count is kept
+// (footprint queries).
 struct DeviceArena {
-  std::vector<void*> ptrs;
+  std::vector<std::pair<void*, size_t>> ptrs;
   size_t bytes = 0;
   hipStream_t stream = nullptr;
   bool dry = false;
+  ctd_dev_alloc_fn hook_alloc = nullptr;
+  ctd_dev_free_fn hook_free = nullptr;
+  void* hook_ctx = nullptr;
+  hipError_t raw_alloc(void** p, size_t n) {
+    if (hook_alloc) {
+      *p = hook_alloc((uint64_t)n, (void*)stream, hook_ctx);
+      return *p ? hipSuccess : hipErrorOutOfMemory;
+    }
+    // stream-ordered: no device-wide synchronisation when other instances'
+    // work is in flight on other streams
+    return hipMallocAsync(p, n, stream);
+  }
+  // returns memory of raw_alloc; with hooks only after the stream is idle
+  void raw_free(void* p, size_t n) {
+    if (hook_free) {
+      (void)hipStreamSynchronize(stream);
+      hook_free(p, (uint64_t)n, (void*)stream, hook_ctx);
+    } else {
+      (void)hipFreeAsync(p, stream);
+    }
+  }
   hipError_t alloc(void** p, size_t n) {
     if (n == 0) n = 8;
     n = (n + 255) / 256 * 256;
@@ -41,19 +64,19 @@ struct DeviceArena {
       bytes += n;
       return hipSuccess;
     }
-    // stream-ordered: no device-wide synchronisation when other instances'
-    // work is in flight on other streams
-    hipError_t e = hipMallocAsync(p, n, stream);
+    hipError_t e = raw_alloc(p, n);
     if (e == hipSuccess) {
-      ptrs.push_back(*p);
+      ptrs.push_back({*p, n});
       bytes += n;
       e = hipMemsetAsync(*p, 0, n, stream);
     }
     return e;
   }
   void release() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, stream);
-    if (!ptrs.empty()) (void)hipStreamSynchronize(stream);
+    if (ptrs.empty()) return;
+    (void)hipStreamSynchronize(stream);
+    for (auto& pn : ptrs) raw_free(pn.first, pn.second);
+    if (!hook_free) (void)hipStreamSynchronize(stream);
     ptrs.clear();
   }
 };
@@ -145,7 +168,7 @@ struct ctd_solver {
   }
   int hip_fail(hipError_t e, const char* where) {
     err = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
-    return CTD_EDEVICE;
+    return e == hipErrorOutOfMemory ? CTD_ENOMEM : CTD_EDEVICE;
   }
 };
 
@@ -240,6 +263,10 @@ int validate(const ctd_problem* p, std::string& err) {
   if (p->precision != CTD_PREC_FP64 && p->precision != CTD_PREC_MIXED) { err = "bad precision"; return CTD_EINVAL; }
   if (p->schedule != CTD_SCHED_ADAPTIVE && p->schedule != CTD_SCHED_REPLAY) { err = "bad schedule"; return CTD_EINVAL; }
   if (p->init_mode != CTD_INIT_HASH && p->init_mode != CTD_INIT_WARM) { err = "bad init_mode"; return CTD_EINVAL; }
+  if ((p->dev_alloc == nullptr) != (p->dev_free == nullptr)) {
+    err = "dev_alloc and dev_free must both be set or both be NULL";
+    return CTD_EINVAL;
+  }
   const bool paper = std::isfinite(p->L) || std::isfinite(p->kappa) || std::isfinite(p->a0) || std::isfinite(p->alpha);
   if (paper) {
     if (!(p->L > 0) || !(p->kappa >= 0) || !(p->a0 >= 0) || !(p->alpha >= 0)) {
@@ -339,6 +366,9 @@ int setup_host(ctd_solver* s, const ctd_problem* p, void* hip_stream, std::strin
   s->omega = 4.0 * s->a0 * s->L;
   s->stream = (hipStream_t)hip_stream;
   s->arena.stream = s->stream;
+  s->arena.hook_alloc = p->dev_alloc;
+  s->arena.hook_free = p->dev_free;
+  s->arena.hook_ctx = p->alloc_ctx;
   for (int d = 0; d < s->dim; ++d) {
     int rc = build_axis(p->nodes[d], p->lo[d], p->hi[d], p->patch_s, p->poly_p,
                         s->P.dilation_a, s->P.gauss_points, s->ax[d], err);
@@ -801,7 +831,7 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     int rc = read_scalars(s);
     if (rc) return rc;
     if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
-    last_term = s->sc_host->term_max;
+    last_term = M > 0 ? s->sc_host->term_max : 0.0;
   }
   // adaptive algorithm: a step that needs more than M_c modes is the full solve
   const bool full = full_replay || (s->actd && capped);
@@ -829,6 +859,9 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     info->last_term_max = last_term;
     info->energy = std::numeric_limits<double>::quiet_NaN();
     info->energy_increase = 0;
+    // energy stability of the scheme needs alpha >= max(w')/2 = 4 a0 on
+    // |u| <= 1 (Sec. 2.5); below it the step still runs, flagged
+    info->stability_warning = s->alpha < 4.0 * s->a0 ? 1 : 0;
   }
   if (s->P.energy_each_step) {
     double E;
@@ -864,7 +897,7 @@ int ctd_problem_default(ctd_problem* p) {
   p->L = nan; p->kappa = nan; p->a0 = nan; p->alpha = nan;
   p->patch_s = 2; p->poly_p = 2; p->dilation_a = 12.0; p->gauss_points = 5;
   p->fp_max_iter = 20; p->fp_tol = 1e-2; p->enrich_tol = 1e-8; p->max_modes = 64;
-  p->precision = CTD_PREC_FP64; p->schedule = CTD_SCHED_ADAPTIVE; p->init_mode = CTD_INIT_HASH;
+  p->precision = CTD_PREC_FP64; p->schedule = CTD_SCHED_ADAPTIVE; p->init_mode = CTD_INIT_WARM;
   p->energy_each_step = 0; p->seed = 0;
   return CTD_OK;
 }
@@ -954,7 +987,8 @@ int ctd_step(ctd_solver* s, int32_t nsteps, ctd_step_info* info) {
         rl = 0;
         pos += 1;
       } else {
-        if (rl < 1 || pos + 1 + rl > s->decisions_next.size()) return s->fail(CTD_EINVAL, "malformed replay log");
+        // rl == 0: a step whose first mode had zero amplitude (u^{k+1} = 0)
+        if (rl < 0 || pos + 1 + rl > s->decisions_next.size()) return s->fail(CTD_EINVAL, "malformed replay log");
         rp = s->decisions_next.data() + pos + 1;
         pos += 1 + rl;
       }
@@ -972,26 +1006,63 @@ int ctd_energy(ctd_solver* s, double* E) {
   return energy_of_uk(s, E);
 }
 
-int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device) {
+int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device,
+                    const int64_t* strides) {
   if (!s || !out) return CTD_EINVAL;
   if (dtype != CTD_DTYPE_F64 && dtype != CTD_DTYPE_F32) return s->fail(CTD_EINVAL, "bad dtype");
   DevInst V = s->I;
   for (int d = 0; d < s->dim; ++d) V.ax[d].X = s->I.ax[d].Xk;
   V.sn = s->I.sk;
+  int64_t n[3] = {1, 1, 1}, cst[3] = {0, 0, 0};
+  for (int d = 0; d < s->dim; ++d) n[d] = s->ax[d].n;
+  // C-order strides; a caller layout equal to them takes the direct path
+  cst[s->dim - 1] = 1;
+  for (int d = s->dim - 2; d >= 0; --d) cst[d] = cst[d + 1] * n[d + 1];
+  bool contiguous = true;
+  if (strides) {
+    for (int d = 0; d < s->dim; ++d) {
+      if (strides[d] < 1) return s->fail(CTD_EINVAL, "strides must be positive");
+      contiguous = contiguous && strides[d] == cst[d];
+    }
+  }
   size_t total = 1;
-  for (int d = 0; d < s->dim; ++d) total *= (size_t)s->ax[d].n;
-  const size_t bytes = total * (dtype == CTD_DTYPE_F32 ? 4 : 8);
+  for (int d = 0; d < s->dim; ++d) total *= (size_t)n[d];
+  const size_t esz = dtype == CTD_DTYPE_F32 ? 4 : 8;
+  const size_t bytes = total * esz;
   void* dst = out;
   void* tmp = nullptr;
-  if (!on_device) {
-    HIPCHK(s, hipMallocAsync(&tmp, bytes, s->stream));
+  if (!on_device || !contiguous) {
+    HIPCHK(s, s->arena.raw_alloc(&tmp, bytes));
     dst = tmp;
   }
   hipError_t e = launch_reconstruct(V, s->Mk, dst, dtype, s->stream);
-  if (e == hipSuccess && !on_device) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
-  if (tmp) (void)hipFreeAsync(tmp, s->stream);
+  std::vector<unsigned char> host;
+  if (e == hipSuccess && !contiguous && on_device)
+    e = launch_scatter_strided(tmp, out, (int)esz, s->dim, n, strides, s->stream);
+  if (e == hipSuccess && !on_device) {
+    if (contiguous) {
+      e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+    } else {
+      host.resize(bytes);
+      e = hipMemcpyAsync(host.data(), tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+    }
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (tmp) s->arena.raw_free(tmp, bytes);
   if (e != hipSuccess) return s->hip_fail(e, "reconstruct");
+  if (!host.empty()) {
+    // host layout other than C order: place each element (marshalling only)
+    unsigned char* o = (unsigned char*)out;
+    size_t k = 0;
+    for (int64_t i0 = 0; i0 < n[0]; ++i0)
+      for (int64_t i1 = 0; i1 < n[1]; ++i1)
+        for (int64_t i2 = 0; i2 < n[2]; ++i2, ++k) {
+          int64_t off = i0 * strides[0];
+          if (s->dim > 1) off += i1 * strides[1];
+          if (s->dim > 2) off += i2 * strides[2];
+          std::memcpy(o + (size_t)off * esz, host.data() + k * esz, esz);
+        }
+  }
   return CTD_OK;
 }
 

@@ -48,6 +48,7 @@ class Problem(C.Structure):
         ("schedule", C.c_int32), ("init_mode", C.c_int32),
         ("energy_each_step", C.c_int32), ("solve_method", C.c_int32),
         ("actd", C.c_int32), ("seed", C.c_uint64),
+        ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p),
     ]
 
 
@@ -55,7 +56,8 @@ class StepInfo(C.Structure):
     _fields_ = [
         ("modes", C.c_int32), ("sweeps", C.c_int32), ("capped", C.c_int32),
         ("fp_unconverged", C.c_int32), ("zero_mode", C.c_int32),
-        ("energy_increase", C.c_int32), ("full_solve", C.c_int32), ("energy", C.c_double),
+        ("energy_increase", C.c_int32), ("full_solve", C.c_int32),
+        ("stability_warning", C.c_int32), ("energy", C.c_double),
         ("last_term_max", C.c_double), ("ms", C.c_double),
     ]
 
@@ -98,7 +100,7 @@ def _load():
         "ctd_init": (C.c_int, [P(Problem), C.c_int32, P(P(C.c_double)), P(C.c_double), vp, P(vp)]),
         "ctd_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
         "ctd_energy": (C.c_int, [vp, P(C.c_double)]),
-        "ctd_reconstruct": (C.c_int, [vp, vp, C.c_int32, C.c_int32]),
+        "ctd_reconstruct": (C.c_int, [vp, vp, C.c_int32, C.c_int32, P(C.c_int64)]),
         "ctd_get_modes": (C.c_int, [vp, P(C.c_int32), P(C.c_double), P(P(C.c_double)), C.c_int32]),
         "ctd_get_step_index": (C.c_int, [vp, P(C.c_int64)]),
         "ctd_set_step_index": (C.c_int, [vp, C.c_int64]),
@@ -123,7 +125,7 @@ def _load():
         "ctd_server_destroy": (None, [vp]),
         "ctd_batch_get_modes": (C.c_int, [vp, C.c_int32, P(C.c_int32), P(C.c_double),
                                           P(P(C.c_double)), C.c_int32]),
-        "ctd_batch_reconstruct": (C.c_int, [vp, C.c_int32, vp, C.c_int32, C.c_int32]),
+        "ctd_batch_reconstruct": (C.c_int, [vp, C.c_int32, vp, C.c_int32, C.c_int32, P(C.c_int64)]),
         "ctd_batch_last_error": (C.c_char_p, [vp]),
         "ctd_batch_destroy": (None, [vp]),
         "ctd_kernel_band_solve": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
@@ -190,9 +192,47 @@ def current_stream():
     return None
 
 
-def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash",
-                 energy=False, solve="auto", actd=False, **over) -> Problem:
-    """ctd_problem from a workloads.Instance (epsilon form) plus overrides."""
+# Device allocator hooks (ctd_problem.dev_alloc / dev_free): instance memory
+# from torch's caching allocator on the instance's stream.  ctypes callbacks
+# take the GIL, so they are safe on the library's worker threads.
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:          # out of memory: the library reports CTD_ENOMEM
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:          # interpreter shutdown: the process frees it
+        pass
+
+
+TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+TORCH_FREE = _FREE_FN(_torch_free)
+
+
+def _torch_has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="warm",
+                 energy=False, solve="auto", actd=False, allocator="torch", **over) -> Problem:
+    """ctd_problem from a workloads.Instance (epsilon form) plus overrides.
+
+    allocator: "torch" (device memory from torch's caching allocator, when
+    torch has a GPU) or "library" (hipMallocAsync inside the library)."""
     p = Problem()
     rc = LIB.ctd_problem_default(C.byref(p))
     if rc != CTD_OK:
@@ -216,6 +256,11 @@ def make_problem(inst=None, *, precision="fp64", schedule="adaptive", init="hash
     p.energy_each_step = 1 if energy else 0
     p.solve_method = SOLVE[solve]
     p.actd = 1 if actd else 0
+    if allocator == "torch" and _torch_has_gpu():
+        p.dev_alloc = C.cast(TORCH_ALLOC, C.c_void_p).value
+        p.dev_free = C.cast(TORCH_FREE, C.c_void_p).value
+    elif allocator not in ("torch", "library"):
+        raise ValueError("allocator is 'torch' or 'library'")
     for k, v in over.items():
         if k in ("nodes", "lo", "hi"):
             for d, x in enumerate(v):
@@ -266,12 +311,20 @@ class Solver:
         return e.value
 
     def reconstruct(self, dtype="f64", out=None):
-        """Dense nodal field.  out: optional torch device tensor (filled in place)."""
+        """Dense nodal field.  out: optional torch device tensor or numpy array
+        of the grid's shape, any positive strides (filled in place)."""
         if out is not None:
-            self._check(LIB.ctd_reconstruct(self.h, C.c_void_p(out.data_ptr()), DTYPE[dtype], 1))
+            if hasattr(out, "data_ptr"):
+                strides = (C.c_int64 * 3)(*out.stride())
+                self._check(LIB.ctd_reconstruct(self.h, C.c_void_p(out.data_ptr()), DTYPE[dtype], 1,
+                                                strides))
+            else:
+                strides = (C.c_int64 * 3)(*[st // out.itemsize for st in out.strides])
+                self._check(LIB.ctd_reconstruct(self.h, out.ctypes.data_as(C.c_void_p), DTYPE[dtype],
+                                                0, strides))
             return out
         arr = np.empty(self.nodes, dtype=np.float64 if dtype == "f64" else np.float32)
-        self._check(LIB.ctd_reconstruct(self.h, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0))
+        self._check(LIB.ctd_reconstruct(self.h, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0, None))
         return arr
 
     def modes(self):
@@ -441,7 +494,7 @@ class Batch:
     def reconstruct(self, i, dtype="f64"):
         inst = self.insts[i]
         arr = np.empty(tuple(inst.nodes[: inst.dim]), dtype=np.float64 if dtype == "f64" else np.float32)
-        rc = LIB.ctd_batch_reconstruct(self.h, i, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0)
+        rc = LIB.ctd_batch_reconstruct(self.h, i, arr.ctypes.data_as(C.c_void_p), DTYPE[dtype], 0, None)
         if rc != CTD_OK:
             raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
         return arr
@@ -516,8 +569,16 @@ class Server:
         return True
 
     def fetch(self, ticket, release=True):
+        """Modes of a done request; a failed request raises its error (and is
+        forgotten when release is set)."""
         m = C.c_int32()
-        self._check(LIB.ctd_server_fetch(self.h, ticket, C.byref(m), None, None, 0, 0))
+        rc = LIB.ctd_server_fetch(self.h, ticket, C.byref(m), None, None, 0, 0)
+        if rc != CTD_OK:
+            err = CtdError(rc, LIB.ctd_server_last_error(self.h).decode())
+            if release and rc != CTD_EAGAIN and self.status(ticket)["state"] == "failed":
+                LIB.ctd_server_fetch(self.h, ticket, C.byref(m), None, None, 0, 1)
+                self._nodes.pop(ticket, None)
+            raise err
         amp, outs, ptrs = _mode_buffers(self._nodes[ticket], m.value)
         self._check(LIB.ctd_server_fetch(self.h, ticket, C.byref(m),
                                          amp.ctypes.data_as(C.POINTER(C.c_double)), ptrs, m.value,

@@ -35,9 +35,20 @@ def test_binding_struct_layout_and_validation():
     """ctd_problem_default and ctd_init's validation run without touching a GPU."""
     from paper_2410_15519_amd import ctd
     p = ctd.make_problem()
-    assert p.abi_version == 2 and p.dim == 2 and p.max_modes == 64 and p.actd == 0
-    assert ctypes.sizeof(ctd.Problem) == 216
+    assert p.abi_version == 3 and p.dim == 2 and p.max_modes == 64 and p.actd == 0
+    assert p.init_mode == ctd.INIT["warm"]          # library default: warm guess
+    raw = ctd.Problem()
+    assert ctd.LIB.ctd_problem_default(ctypes.byref(raw)) == 0
+    assert raw.init_mode == ctd.INIT["warm"] and not raw.dev_alloc and not raw.dev_free
+    assert ctypes.sizeof(ctd.Problem) == 240
     assert ctypes.sizeof(ctd.StepInfo) == 56
+    # allocator hooks: both or neither
+    half = ctd.make_problem(allocator="library")
+    half.dev_alloc = ctypes.cast(ctd.TORCH_ALLOC, ctypes.c_void_p).value
+    h = ctypes.c_void_p()
+    ptrs0 = (ctypes.POINTER(ctypes.c_double) * 3)()
+    assert ctd.LIB.ctd_init(ctypes.byref(half), 1, ptrs0, None, None, ctypes.byref(h)) == -1
+    assert b"dev_alloc" in ctd.LIB.ctd_last_error(None)
     # invalid problems fail before any allocation or device call
     bad = ctd.make_problem(dim=4)
     h = ctypes.c_void_p()

@@ -74,12 +74,13 @@ def test_band_solve_kernel(ctd):
                                                   (3, 21, 3, 2, "fd"), (2, (1500, 24), 3, 2, "auto"),
                                                   (3, (40, 17, 23), 3, 2, "fd")])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_step_replay_parity(ctd, dim, n, m0, steps, solve, prec):
+@pytest.mark.parametrize("init", ["warm", "hash"])
+def test_step_replay_parity(ctd, dim, n, m0, steps, solve, prec, init):
     inst = small_instance(dim=dim, n=n, m0=m0, kmax=4, eps=0.05, dt=1e-3, max_modes=24)
-    pr, st, fields, logs = oracle_run(inst, steps)
-    print(f"replay dim={dim} n={n} solve={solve} prec={prec} modes={[len(l.iters) for l in logs]}",
-          flush=True)
-    with ctd.Solver(inst, precision=prec, schedule="replay", solve=solve) as s:
+    pr, st, fields, logs = oracle_run(inst, steps, init=init)
+    print(f"replay dim={dim} n={n} solve={solve} prec={prec} init={init} "
+          f"modes={[len(l.iters) for l in logs]}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", solve=solve, init=init) as s:
         s.set_decisions([lg.iters for lg in logs])
         for k in range(steps):
             info = s.step(1)[0]

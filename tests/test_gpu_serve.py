@@ -140,3 +140,63 @@ def test_nonfinite_input_fails_alone(ctd):
         stats = srv.stats()
         assert stats["failed"] == 1 and stats["completed"] == 1
     assert same_modes(got, ref)
+
+
+def _oracle_steps(inst, steps):
+    from oracle.ctd import ctd_step, full_field, state_from_instance
+    from oracle.scheme import problem_from_instance
+    pr = problem_from_instance(inst)
+    st = state_from_instance(inst)
+    logs = []
+    for k in range(steps):
+        st, lg = ctd_step(pr, st, k)
+        logs.append(lg.iters)
+    return full_field(st), logs
+
+
+def _field(amp, factors):
+    sub = "m,im,jm->ij" if len(factors) == 2 else "m,im,jm,km->ijk"
+    return np.einsum(sub, amp, *factors)
+
+
+def test_batched_instances_match_oracle(ctd):
+    """Instances stepped inside a concurrent batch against the CPU oracle
+    (FP64, adaptive on both sides: same decisions, fields to 1e-10)."""
+    insts = uneven_2d(5, seed=21)
+    b = ctd.Batch(insts, precision="fp64")
+    try:
+        b.set_workers(3)
+        b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i in (0, 2, 4):
+        ref, logs = _oracle_steps(insts[i], 2)
+        U = _field(*got[i])
+        err = float(np.linalg.norm(U - ref) / np.linalg.norm(ref))
+        print(f"batched instance {i} n={insts[i].nodes[0]}: rel l2 {err:.2e}", flush=True)
+        assert err < 1e-10
+
+
+def test_served_request_matches_oracle(ctd):
+    """A 2D and a 3D request served in a mix of others against the oracle."""
+    t2 = small_instance(dim=2, n=36, m0=3, kmax=4, seed=15, max_modes=10)
+    t3 = small_instance(dim=3, n=15, m0=3, kmax=4, seed=16, max_modes=8)
+    others = [inst for _, inst in make_requests(seed=4, count=5, nodes2d_range=(24, 80),
+                                                nodes3d_range=(12, 18), steps_range=(1, 3),
+                                                max_modes=10)]
+    with ctd.Server(workers=3) as srv:
+        tk = [srv.submit(o, precision="fp64") for o in others[:2]]
+        a = srv.submit(t2, nsteps=2, precision="fp64")
+        c = srv.submit(t3, nsteps=2, precision="fp64")
+        tk += [srv.submit(o, precision="fp64") for o in others[2:]]
+        for k in tk + [a, c]:
+            assert srv.wait(k, 120000)
+        got2, got3 = srv.fetch(a), srv.fetch(c)
+        for k in tk:
+            srv.fetch(k)
+    for inst, got in ((t2, got2), (t3, got3)):
+        ref, _ = _oracle_steps(inst, 2)
+        err = float(np.linalg.norm(_field(*got) - ref) / np.linalg.norm(ref))
+        print(f"served dim={inst.dim}: rel l2 {err:.2e}", flush=True)
+        assert err < 1e-10

@@ -27,9 +27,12 @@ def test_field_state_is_the_field():
 
 def test_ctd_step_from_field_state_equals_step_from_modes():
     """The CTD integrals of u^k depend on the field only: the same step from
-    the 3-mode state and from its 10-mode field form agree to rounding."""
+    the 3-mode state and from its 10-mode field form agree to rounding.  The
+    counter-based initial guess of a mode is used: it does not depend on the
+    modes of u^k (the warm guess takes mode m of u^k, which differs between
+    the two forms of the same field)."""
     inst = _inst(cap=32)
-    pr = problem_from_instance(inst)
+    pr = problem_from_instance(inst, init="hash")
     st = state_from_instance(inst)
     new_a, log_a = ctd_step(pr, st, 0)
     assert log_a.stop == "tol"
@@ -64,9 +67,10 @@ def test_no_switch_within_the_cap():
 def test_replay_mixes_full_and_ctd_steps():
     """Replayed schedule full / CTD from the field / full from a CTD state:
     each CTD step from a field state equals the CTD step from the same field
-    held as modes (the field after a CTD step), so the run is consistent."""
+    held as modes (the field after a CTD step), so the run is consistent
+    (counter-based initial guess: independent of how u^k is held)."""
     inst = _inst(cap=6)
-    pr = problem_from_instance(inst)
+    pr = problem_from_instance(inst, init="hash")
     sched = ["full", [3, 2, 2, 3], "full", [2, 2]]
     st, logs, fields = actd_run(pr, state_from_instance(inst), 4, replay=sched)
     assert actd.decisions(logs) == sched

@@ -242,22 +242,57 @@ def test_energy_law_full_solve(dim, n):
 
 
 def test_energy_law_can_fail_without_stabilizer():
-    """alpha = 0 with dt far above 2/(L max w') (eq. AC-discrete-semi-step): energy rises."""
+    """alpha = 0 with dt above 2/(L max w') (eq. AC-discrete-semi-step): the
+    explicit w-term overshoots around u = 1 and the energy rises by a finite,
+    measured amount (no overflow); the same data with alpha = max(w')/2 on the
+    range the field visits (eq. AC-discrete-semi-stable-step) decreases."""
     n = 10
     inst = small_instance(dim=2, n=n, m0=3, kmax=2, eps=0.02)
+    U0 = full_field(state_from_instance(inst))
+    U0 = 1.0 + 0.05 * U0 / np.abs(U0).max()          # near the well u = 1
+    for alpha, expect_rise in ((0.0, True), (None, False)):
+        pr = problem_from_instance(inst)
+        pr.dt = 1.5
+        # stabilised case: alpha >= max w'/2 over |u| <= 1.06 (the field stays there)
+        pr.alpha = 0.5 * pr.max_w_prime(1.06) if alpha is None else alpha
+        Kf, Mf = full_matrices(pr)
+        U = U0.copy()
+        E = energy_fullgrid(pr, U)
+        rises = []
+        for _ in range(5):
+            U = full_step(pr, U, Kf, Mf)
+            E1 = energy_fullgrid(pr, U)
+            assert np.isfinite(E1) and np.abs(U).max() < 2.0
+            rises.append(E1 - E)
+            E = E1
+        if expect_rise:
+            assert max(rises) > 1e-3          # a rise of about 10x the initial energy
+        else:
+            assert max(rises) <= 1e-12 * abs(E)
+            assert np.abs(U).max() <= 1.06
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_closed_forms(dim):
+    """Sec. 2.1 energy of fields whose integrals are known exactly (the rule is
+    exact: u^4 of a degree-1 factor is degree 4 per axis, 5 Gauss points):
+      u = x (x) 1 (x) ...:  a0 int (x^2-1)^2 + kappa/2 int 1 = a0 8/15 + kappa/2,
+      u = x (x) y (x) ...:  a0 (5^-D - 2 3^-D + 1) + kappa/2 D 3^-(D-1).
+    Pins the gradient coefficient (kappa/2) and the quartic and quadratic
+    terms of both oracle evaluations independently of each other."""
+    n = 9
+    inst = small_instance(dim=dim, n=n, m0=1, kmax=1, eps=0.3)
     pr = problem_from_instance(inst)
-    pr.alpha = 0.0
-    pr.dt = 50.0
-    U = full_field(state_from_instance(inst))
-    Kf, Mf = full_matrices(pr)
-    rises = 0
-    E = energy_fullgrid(pr, U)
-    for _ in range(6):
-        U = full_step(pr, U, Kf, Mf)
-        E1 = energy_fullgrid(pr, U)
-        rises += E1 > E * (1 + 1e-9)
-        E = E1
-    assert rises >= 1
+    x = np.linspace(0.0, 1.0, n)[:, None]
+    one = np.ones((n, 1))
+    cases = [
+        (State(np.array([1.0]), [x] + [one] * (dim - 1)), pr.a0 * 8.0 / 15.0 + 0.5 * pr.kappa),
+        (State(np.array([1.0]), [x] * dim),
+         pr.a0 * (5.0 ** -dim - 2.0 * 3.0 ** -dim + 1.0) + 0.5 * pr.kappa * dim * 3.0 ** -(dim - 1)),
+    ]
+    for st, ref in cases:
+        assert energy_separated(pr, st) == pytest.approx(ref, rel=1e-13, abs=1e-14)
+        assert energy_fullgrid(pr, full_field(st)) == pytest.approx(ref, rel=1e-13, abs=1e-14)
 
 
 def test_ctd_energy_decreases_and_bounded():
