@@ -69,7 +69,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True, init="hash"):
+def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True, init="warm",
+            warm_infos=None):
     """W warmup steps (the last one timed per kernel class, all classes), then
     K timed steps with HIP events around the launches of the dominant class
     only (events on every launch would slow the launch cadence)."""
@@ -86,6 +87,8 @@ def run_leg(ctd, inst, precision, warmup, steps, decisions=None, profile=True, i
             s.profile(True)
         info = s.step(1)[0]
         dec += s.decisions()
+        if warm_infos is not None:
+            warm_infos.append(info)
         if last:
             prof_all = s.profile_read()
             s.profile(False)
@@ -141,15 +144,13 @@ def roofline_of(prof, precision, workload="ac3d_n1024"):
                   "algorithmic_per_launch": per_launch}
 
 
-def cpu_baseline(inst, sweeps_per_step, budget_s=20.0):
-    """Oracle directional solves at the steady-state shape (M_k = max_modes).
-
-    The cost of a directional solve does not depend on the data values, so the
-    sample uses a seeded random u^k with the workload's mode cap; steps/s =
-    1 / (seconds per directional solve * directional solves per step).
-    """
-    import numpy as np
-    from oracle.ctd import SeparatedNonlinear, State, solve_direction
+def cpu_baseline(inst, gpu_step0_ms, gpu_sweeps0):
+    """The oracle (plain numpy/scipy FP64) on whole time steps of the same
+    workload: step 1 from the seeded initial field, as the GPU's first step.
+    A step from the 8-mode initial field is the cheapest step of the run
+    (M_k = 8 in the cubic contraction); the GPU's time for the same step is
+    reported beside it, so the ratio compares like with like."""
+    from oracle.ctd import ctd_step, state_from_instance
     from oracle.scheme import problem_from_instance
     try:
         from threadpoolctl import threadpool_info
@@ -157,51 +158,169 @@ def cpu_baseline(inst, sweeps_per_step, budget_s=20.0):
     except Exception:
         cores = os.cpu_count()
     pr = problem_from_instance(inst)
-    rng = np.random.default_rng(11)
-    Mk = inst.max_modes
-    st_k = State(rng.uniform(0.01, 0.1, Mk),
-                 [rng.uniform(-1, 1, (n, Mk)) for n in inst.nodes])
-    new = State(rng.uniform(0.01, 0.1, Mk // 2),
-                [rng.uniform(-1, 1, (n, Mk // 2)) for n in inst.nodes])
-    F = SeparatedNonlinear(pr, st_k)
-    u = [rng.uniform(-1, 1, n) for n in inst.nodes]
+    st = state_from_instance(inst)
     t0 = time.perf_counter()
-    done = 0
-    while True:
-        d = done % inst.dim
-        u[d] = solve_direction(pr, d, u, new, st_k, F)
-        u[d] /= np.sqrt(u[d] @ (pr.axes[d].M @ u[d]))
-        done += 1
+    _, lg = ctd_step(pr, st, 0)
+    el = time.perf_counter() - t0
+    log(f"  [cpu oracle] whole step 1: {el:.1f} s, {len(lg.iters)} modes, {sum(lg.iters)} sweeps")
+    return {"value": 1.0 / el, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": (f"one whole oracle time step (step 1 from the seeded {len(inst.amp)}-mode "
+                       f"initial field, M_k = {len(inst.amp)}; {len(lg.iters)} modes, "
+                       f"{sum(lg.iters)} sweeps, {el:.1f} s) of the {inst.nodes[0]}^{inst.dim} "
+                       f"workload; later steps (M_k = {inst.max_modes}) cost more on both sides"),
+            "gpu_same_step_steps_per_s": 1e3 / gpu_step0_ms if gpu_step0_ms else None,
+            "gpu_same_step_sweeps": gpu_sweeps0}
+
+
+def rel_l2(a, b):
+    import numpy as np
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def ac2d_leg(ctd, steps=50, check_steps=3):
+    """The 2D 128^2 workload (eps 0.02, dt 1e-3, 4 cosine modes, cap 64), FP64:
+    steps/s over its 50 steps (adaptive), and the GPU against the CPU oracle
+    (relative nodal l2) after each of the first steps with the oracle's
+    decisions replayed."""
+    import torch
+    from oracle.ctd import ctd_step, full_field, state_from_instance
+    from oracle.scheme import problem_from_instance
+    from workloads import make_instance
+    inst = make_instance("ac2d_n128")
+    s = ctd.Solver(inst, precision="fp64", energy=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = s.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.close()
+    pr = problem_from_instance(inst)
+    st = state_from_instance(inst)
+    refs, logs = [], []
+    for k in range(check_steps):
+        st, lg = ctd_step(pr, st, k)
+        refs.append(full_field(st))
+        logs.append(lg.iters)
+    errs = []
+    with ctd.Solver(inst, precision="fp64", schedule="replay") as r:
+        r.set_decisions(logs)
+        for k in range(check_steps):
+            r.step(1)
+            errs.append(rel_l2(r.reconstruct(), refs[k]))
+    out = {"workload": "ac2d_n128", "precision": "fp64", "steps": steps, "steps_per_s": steps / el,
+           "ms_per_step": 1e3 * el / steps,
+           "modes_per_step": sum(i["modes"] for i in infos) / steps,
+           "sweeps_per_step": sum(i["sweeps"] for i in infos) / steps,
+           "energy_first_last": [infos[0]["energy"], infos[-1]["energy"]],
+           "energy_increases": int(sum(i["energy_increase"] for i in infos)),
+           "rel_l2_vs_oracle_first_steps": errs}
+    log(f"  [ac2d_n128] {out['steps_per_s']:.1f} steps/s FP64, vs oracle {errs}")
+    return out
+
+
+def ac3d_n256_leg(ctd, steps=100):
+    """The 3D 256^3 workload (eps 0.01, dt 5e-4, 8 cosine modes, cap 64):
+    steps/s of its 100 steps in mixed precision and in FP64 (adaptive), the
+    mixed run against an FP64 replay of its decisions after all steps and for
+    its last step alone (from the FP64 state), and the first step of both
+    paths against the CPU oracle replaying the oracle's decisions."""
+    import numpy as np
+    import torch
+    from oracle.ctd import ctd_step, full_field, state_from_instance
+    from oracle.scheme import problem_from_instance
+    from workloads import Instance, make_instance
+    inst = make_instance("ac3d_n256")
+    out = {"workload": "ac3d_n256", "steps": steps}
+    dec = {}
+    for prec in ("mixed", "fp64"):
+        s = ctd.Solver(inst, precision=prec, energy=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = s.step(steps)
+        torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        log(f"  [cpu oracle] directional solve {done}: {el:.1f} s")
-        if el > budget_s or done >= 3 * inst.dim:
-            break
-    per_solve = el / done
-    steps_per_s = 1.0 / (per_solve * sweeps_per_step * inst.dim)
-    return {"value": steps_per_s, "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"{done} oracle directional solves at M_k={Mk}, {Mk // 2} earlier modes, "
-                       f"nodes={inst.nodes[0]}^{inst.dim} ({per_solve:.2f} s each), scaled by "
-                       f"{sweeps_per_step:.0f} sweeps x {inst.dim} directions per step measured on the GPU")}
+        dec[prec] = s.decisions()
+        if prec == "mixed":
+            Umix = s.reconstruct()
+        s.close()
+        out[prec] = {"steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+                     "sweeps_per_step": sum(i["sweeps"] for i in infos) / steps,
+                     "modes_per_step": sum(i["modes"] for i in infos) / steps,
+                     "energy_increases": int(sum(i["energy_increase"] for i in infos))}
+        log(f"  [ac3d_n256] {prec}: {out[prec]['steps_per_s']:.2f} steps/s, "
+            f"{out[prec]['sweeps_per_step']:.0f} sweeps/step")
+    # FP64 replay of the mixed decisions: accumulated and last-step differences
+    r = ctd.Solver(inst, precision="fp64", schedule="replay")
+    r.set_decisions(dec["mixed"][:-1])
+    r.step(steps - 1)
+    amp, fac = r.modes()
+    k_prev = r.step_index
+    r.set_decisions(dec["mixed"][-1:])
+    r.step(1)
+    U64 = r.reconstruct()
+    r.close()
+    out["rel_l2_accum_mixed_vs_fp64"] = rel_l2(Umix, U64)
+    st = Instance(**{**inst.__dict__, "amp": amp, "factors": fac})
+    one = ctd.Solver(st, precision="mixed", schedule="replay")
+    one.step_index = k_prev
+    one.set_decisions(dec["mixed"][-1:])
+    one.step(1)
+    out["rel_l2_last_step_mixed_vs_fp64"] = rel_l2(one.reconstruct(), U64)
+    one.close()
+    # first step against the oracle (its decisions replayed on the GPU)
+    pr = problem_from_instance(inst)
+    t0 = time.perf_counter()
+    st1, lg = ctd_step(pr, state_from_instance(inst), 0)
+    t_or = time.perf_counter() - t0
+    ref = full_field(st1)
+    for prec in ("fp64", "mixed"):
+        with ctd.Solver(inst, precision=prec, schedule="replay") as g:
+            g.set_decisions([lg.iters])
+            g.step(1)
+            out[f"rel_l2_step1_{prec}_vs_oracle"] = rel_l2(g.reconstruct(), ref)
+    out["oracle_step1_s"] = t_or
+    log(f"  [ac3d_n256] mixed vs fp64: accumulated {out['rel_l2_accum_mixed_vs_fp64']:.2e}, "
+        f"last step {out['rel_l2_last_step_mixed_vs_fp64']:.2e}; step 1 vs oracle "
+        f"fp64 {out['rel_l2_step1_fp64_vs_oracle']:.2e} mixed {out['rel_l2_step1_mixed_vs_oracle']:.2e}")
+    return out
 
 
-def batched_leg(ctd, count=24, steps=2, workers=8, init="warm"):
-    """Instance-steps/s of a concurrent batch (and of the same batch on one worker)."""
+def batched_leg(ctd, count=512, steps=2, workers=8, init="warm", sample=(0, 255, 511)):
+    """Instance-steps/s of the uneven 2D batch (the batch2d_512 instances)
+    under both executors: lockstep rounds of multi-instance launches, and
+    the pool of worker streams.  Sampled instances of the lockstep run are
+    compared with the standalone solver bitwise."""
+    import numpy as np
     import torch
     from workloads import make_batch
     insts = make_batch(count=count)
-    out = {"instances": count, "steps": steps,
-           "nodes": sorted(int(i.nodes[0]) for i in insts)}
-    for w in (1, workers):
+    out = {"instances": count, "steps": steps, "precision": "mixed",
+           "nodes_min": min(int(i.nodes[0]) for i in insts),
+           "nodes_max": max(int(i.nodes[0]) for i in insts)}
+    kept = {}
+    for ex in ("lockstep", "streams"):
         b = ctd.Batch(insts, precision="mixed", init=init)
-        b.set_workers(w)
+        b.set_mode(ex)
+        b.set_workers(workers)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.step(steps)
+        infos = b.step(steps)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        if ex == "lockstep":
+            kept = {i: b.modes(i) for i in sample if i < count}
         b.close()
-        out[f"instance_steps_per_s_w{w}"] = count * steps / el
-        log(f"  [batched] {count} instances x {steps} steps, {w} workers: {el:.2f} s")
+        out[f"instance_steps_per_s_{ex}"] = count * steps / el
+        out[f"s_{ex}"] = el
+        out[f"sweeps_{ex}"] = int(sum(r["sweeps"] for inf in infos for r in inf))
+        log(f"  [batched] {count} instances x {steps} steps, {ex}: {el:.2f} s")
+    same = True
+    for i, (amp, fac) in kept.items():
+        with ctd.Solver(insts[i], precision="mixed", init=init) as s:
+            s.step(steps)
+            ra, rf = s.modes()
+        same = same and np.array_equal(amp, ra) and all(np.array_equal(x, y) for x, y in zip(fac, rf))
+    out["sampled_equal_standalone"] = bool(same)
     return out
 
 
@@ -357,22 +476,91 @@ def served_leg(ctd, count=32, step_scale=20, workers=8, init="warm"):
                        f"divided by {step_scale}")}
 
 
+def _serve_stream(ctd, reqs, rate_scale, workers, init):
+    """Submit (arrival time / rate_scale, instance) pairs on their arrival
+    times, wait for all; returns per-request statuses, server stats and the
+    wall time of the run."""
+    srv = ctd.Server(workers=workers)
+    t0 = time.perf_counter()
+    tickets = []
+    for t_arr, inst in reqs:
+        dt = t_arr / rate_scale - (time.perf_counter() - t0)
+        if dt > 0:
+            time.sleep(dt)
+        tickets.append(srv.submit(inst, precision="mixed", init=init))
+    for t in tickets:
+        srv.wait(t)
+    wall = time.perf_counter() - t0
+    st = [srv.status(t) for t in tickets]
+    stats = srv.stats()
+    for t in tickets:
+        srv.fetch(t)
+    srv.close()
+    return st, stats, wall
+
+
+def served_load_leg(ctd, count=64, workers=8, init="warm"):
+    """The served workload as generated (Poisson arrivals at 200 req/s, 20 %
+    3D with 64-512 nodes per axis, 2D with 64-2048, 20-500 steps per
+    request; parameters as the batched workload), its first `count`
+    requests: capacity (steps and requests completed per second of busy
+    time), p50/p99 latency from arrival to completion at the offered 200
+    req/s (the queue grows: the offered load is above capacity), then the same
+    requests offered at 70 % of the measured request capacity."""
+    import numpy as np
+    from workloads import make_requests, CONFIGS
+    cfg = CONFIGS["serve_mix"]
+    reqs = make_requests(count=count)
+    out = {"requests": count, "workers": workers, "offered_rate_per_s": cfg["rate"],
+           "steps_total": int(sum(i.steps for _, i in reqs)),
+           "p3d": float(np.mean([i.dim == 3 for _, i in reqs]))}
+    runs = []
+    for label, scale in (("offered", 1.0), ("70pct", None)):
+        if scale is None:
+            cap = runs[0]["requests_per_s_capacity"]
+            scale = cfg["rate"] / (0.7 * cap)        # stretch the arrival times
+        # arrival times are divided by rate_scale: 1 = as generated, 1/scale = stretched
+        st, stats, wall = _serve_stream(ctd, reqs, 1.0 / scale, workers, init)
+        lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in st])
+        wait = np.array([x["t_start_ms"] - x["t_submit_ms"] for x in st])
+        steps = sum(x["steps_done"] for x in st)
+        busy_s = stats["busy_ms"] / 1e3
+        r = {"label": label, "offered_rate_per_s": cfg["rate"] / scale if label != "offered" else cfg["rate"],
+             "wall_s": wall, "busy_s": busy_s, "steps_done": int(steps),
+             "steps_per_s_capacity": steps / busy_s, "requests_per_s_capacity": count / busy_s,
+             "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+             "queue_wait_ms_p50": float(np.percentile(wait, 50)), "queue_wait_ms_p99": float(np.percentile(wait, 99)),
+             "failed": int(stats["failed"])}
+        runs.append(r)
+        log(f"  [served load {label}] offered {r['offered_rate_per_s']:.2f} req/s: {steps} steps in "
+            f"{wall:.1f} s (busy {busy_s:.1f} s), capacity {r['steps_per_s_capacity']:.0f} steps/s "
+            f"{r['requests_per_s_capacity']:.2f} req/s, p50 {r['latency_ms_p50']:.0f} ms "
+            f"p99 {r['latency_ms_p99']:.0f} ms")
+    out["runs"] = runs
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="ac3d_n1024")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the batched and served samples")
     ap.add_argument("--no-ps", action="store_true", help="skip the (p, s) sweep")
     ap.add_argument("--no-actd", action="store_true", help="skip the full-solve fallback leg")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the 2D 128^2 and 3D 256^3 workload legs")
     ap.add_argument("--init", choices=["warm", "hash"], default="warm",
                     help="initial guess of a mode: mode m of u^k (warm) or the counter-based vector")
     ap.add_argument("--no-alt-init", action="store_true", help="skip the leg with the other initial guess")
-    ap.add_argument("--only", choices=["actd", "batched", "served", "ps"],
+    ap.add_argument("--only", choices=["actd", "batched", "served", "ps", "ac2d", "ac3d_n256",
+                                       "served_load"],
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
+    ap.add_argument("--requests", type=int, default=64,
+                    help="requests of the served workload for --only served_load")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
@@ -400,7 +588,9 @@ def main():
     if args.only:
         legs = {"actd": lambda c: actd_leg(c), "batched": lambda c: batched_leg(c, init=args.init),
                 "served": lambda c: served_leg(c, init=args.init),
-                "ps": lambda c: ps_sweep_leg(c, init=args.init)}
+                "ps": lambda c: ps_sweep_leg(c, init=args.init),
+                "ac2d": lambda c: ac2d_leg(c), "ac3d_n256": lambda c: ac3d_n256_leg(c),
+                "served_load": lambda c: served_load_leg(c, count=args.requests, init=args.init)}
         print(json.dumps({args.only: legs[args.only](ctd)}))
         return
     inst = make_instance(args.workload)
@@ -408,8 +598,10 @@ def main():
         f"max_modes={inst.max_modes}")
 
     # leg 1: mixed, adaptive (the headline)
+    warm_infos = []
     s_mix, infos, elapsed, prof, dec_all = run_leg(ctd, inst, "mixed", args.warmup, args.steps,
-                                                   init=args.init)
+                                                   init=args.init, warm_infos=warm_infos)
+    step0 = (warm_infos[0]["ms"], warm_infos[0]["sweeps"]) if warm_infos else (None, None)
     value = args.steps / elapsed
     dom, roof = roofline_of(prof["timed"], "mixed", args.workload)
     sweeps_per_step = float(np.mean([i["sweeps"] for i in infos]))
@@ -533,7 +725,10 @@ def main():
     other = "hash" if args.init == "warm" else "warm"
     alt_init = None if args.no_alt_init else init_leg(ctd, inst, args.warmup, args.steps, other)
     actd = None if args.no_actd else actd_leg(ctd)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(inst, sweeps_per_step)
+    workloads = None
+    if not args.no_workloads:
+        workloads = {"ac2d_n128": ac2d_leg(ctd), "ac3d_n256": ac3d_n256_leg(ctd)}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(inst, step0[0], step0[1])
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",
         "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -552,6 +747,7 @@ def main():
         "ps_sweep": ps_sweep,
         "alt_init": alt_init,
         "actd": actd,
+        "workloads": workloads,
         "detail": extra,
     }
     print(json.dumps(out))

@@ -221,13 +221,13 @@ void ctd_destroy(ctd_solver* s);   /* NULL-safe; synchronises the stream */
 int ctd_footprint_bytes(const ctd_problem* p, int32_t m0, uint64_t* bytes);
 
 /* ---------------------------------------------------------------------- *
- * Batched execution (many independent, uneven instances; the batched
- * workload of the paper's comparisons is its own).  The instances advance
- * concurrently: a pool of worker threads, each with its own non-blocking
- * HIP stream, takes instances longest-first (cost ~ sweeps x directions x
- * per-sweep work, from the shape and mode cap) so that the GPU runs several
- * instances' kernels at once.  Each instance's arithmetic is that of a
- * single ctd_solver: a result does not depend on the batch around it.
+ * Batched execution (many independent, uneven instances).  The instances
+ * advance concurrently, either in lockstep rounds of multi-instance launches
+ * (2D) or on a pool of worker threads, each with its own non-blocking HIP
+ * stream, taking instances longest-first (cost ~ sweeps x directions x
+ * per-sweep work, from the shape and mode cap); see ctd_batch_set_mode.
+ * Each instance's arithmetic is that of a single ctd_solver: a result does
+ * not depend on the batch around it.
  * ---------------------------------------------------------------------- */
 typedef struct ctd_batch ctd_batch;
 
@@ -239,6 +239,17 @@ int ctd_batch_create(int32_t count, const ctd_problem* problems,
                      ctd_batch** out);
 /* Worker threads (and streams) of the pool, 1..64; default 8. */
 int ctd_batch_set_workers(ctd_batch* b, int32_t workers);
+/* Executor.  LOCKSTEP: the instances advance together in rounds, each round
+ * one multi-instance launch per phase of a sweep (mode initialisation,
+ * right-hand sides, banded solves, Grams) for every instance at that phase,
+ * and one read-back of all instances' decision scalars; each instance takes
+ * its own decisions (Sec. 3.3 adaptive algorithm) and ends its steps with its
+ * own launches.  Needs 2D instances, adaptive schedule, cyclic-reduction
+ * solves of one band width (CTD_EUNSUPPORTED otherwise).  STREAMS: the
+ * worker pool above.  AUTO (default): LOCKSTEP when every instance allows
+ * it, else STREAMS.  Results are the same under either executor. */
+enum { CTD_BATCH_AUTO = 0, CTD_BATCH_LOCKSTEP = 1, CTD_BATCH_STREAMS = 2 };
+int ctd_batch_set_mode(ctd_batch* b, int32_t mode);
 /* Advance every instance nsteps steps; info: count * nsteps entries
  * (instance-major) or NULL.  Returns when all are done (or on the first
  * error, after the running instances reach a step boundary). */

@@ -1,12 +1,15 @@
 // Batched execution of many independent CTD instances.
 //
-// Instances advance concurrently: a pool of worker threads, each owning a
-// non-blocking HIP stream, takes instances longest-first from a shared
-// counter and steps each one on its own stream, so the kernels of several
-// instances are in flight on the device at once (small instances cannot fill
-// the chip alone, and each sweep ends in a host decision).  An instance is
-// stepped by exactly one worker per call and its arithmetic is that of a
-// single ctd_solver, so its result does not depend on the batch around it.
+// Two executors.  Lockstep (the default when every instance is a 2D one
+// with cyclic-reduction solves of one band width): the instances advance
+// together in rounds of multi-instance launches, one launch per phase of a
+// sweep for all of them and one read-back of all their scalars per round
+// (solver.hip, lockstep_steps).  Worker streams (otherwise, or on request):
+// a pool of worker threads, each owning a non-blocking HIP stream, takes
+// instances longest-first from a shared counter and steps each one on its
+// own stream, so the kernels of several instances are in flight at once.
+// Either way an instance's arithmetic is that of a single ctd_solver, so its
+// result does not depend on the batch around it.
 #include <algorithm>
 #include <atomic>
 #include <numeric>
@@ -21,6 +24,7 @@ struct ctd_batch {
   std::vector<double> cost;      // relative cost of one step (longest first)
   hipStream_t home = nullptr;    // stream the instances were set up on
   int workers = 8;
+  int mode = CTD_BATCH_AUTO;
   std::string err = "no error";
 };
 
@@ -74,10 +78,35 @@ int ctd_batch_set_workers(ctd_batch* b, int32_t workers) {
   return CTD_OK;
 }
 
+namespace {
+// every instance 2D, adaptive, cyclic-reduction solves, and one band width
+bool lockstep_batch(const ctd_batch* b) {
+  for (auto* s : b->inst)
+    if (!ctd::lockstep_eligible(s) || ctd::band_halfwidth(s) != ctd::band_halfwidth(b->inst[0])) return false;
+  return true;
+}
+}  // namespace
+
+int ctd_batch_set_mode(ctd_batch* b, int32_t mode) {
+  if (!b || (mode != CTD_BATCH_AUTO && mode != CTD_BATCH_LOCKSTEP && mode != CTD_BATCH_STREAMS))
+    return CTD_EINVAL;
+  if (mode == CTD_BATCH_LOCKSTEP && !lockstep_batch(b)) {
+    b->err = "lockstep needs 2D instances with cyclic-reduction solves of one band width";
+    return CTD_EUNSUPPORTED;
+  }
+  b->mode = mode;
+  return CTD_OK;
+}
+
 int ctd_batch_step(ctd_batch* b, int32_t nsteps, ctd_step_info* info) {
   if (!b || nsteps < 0) return CTD_EINVAL;
   const int count = (int)b->inst.size();
   if (nsteps == 0 || count == 0) return CTD_OK;
+  if (b->mode != CTD_BATCH_STREAMS && lockstep_batch(b)) {
+    const int rc = ctd::lockstep_steps(b->inst, nsteps, info, b->home, b->err);
+    for (auto* s : b->inst) ctd::solver_bind_stream(s, b->home);
+    return rc;
+  }
   std::vector<int> order(count);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->cost[x] > b->cost[y]; });

@@ -108,8 +108,24 @@ struct DevInst {
   DevScalars* sc;
   DevAxis ax[kMaxDim];
   // cubic route (3D)
-  const int4* tri;   // (A, B, C, weight) per triple, C-major order
-  void* gpart;       // nsplit_g x ntri x 4096 (T)
+  const int4* tri;   // (A, B, C, weight) per triple, C-major order (g, S)
+  // the h contraction's view of the triples, C-groups kept and each sorted
+  // by column tile: (first, second, column tile, pair skip); (b <= c) pairs
+  // for A < B = C, (a <= b) pairs when A = B, all 256 pairs otherwise
+  const int4* trih;
+  const int2* trimap; // per triple of tri: (position in trih, 1 if h takes it transposed)
+  const int* thinv;   // per position of trih: the triple of tri
+  // FP32 g by triple class: tlist holds the triples with three distinct
+  // tiles (16 chains of 16 x 16 outputs) in C-major order, then those with
+  // a repeated tile (9 blocks of 16 mode pairs x 16 outputs); trank[t] =
+  // (class: 0 distinct, 1 A = B < C, 2 A < B = C, 3 A = B = C; rank in its list)
+  const int* tlist;          // distinct-tile triples (all mode tiles of the handle)
+  const int* tlist_p;        // repeated-tile triples (a prefix serves fewer tiles)
+  const int2* trank;
+  int ntri_d, ntri_p;        // distinct / repeated-tile triples of the current M_k
+  int nsplit_p;              // point splits of a repeated-tile triple (nsplit_g: distinct)
+  void* gpart;       // split-K partials of g: FP64 nsplit_g x ntri x 4096; FP32 by
+                     // class: [rank][split][4096] distinct, then [rank][split][2304]
   void* S;           // ntri x 4096 (T), weighted g_e * g_f
   double* hpart;     // nsplit_h x nqmax
   double* bcr_ws;    // cyclic-reduction block data in HBM for axes too large for LDS (else null)
@@ -215,6 +231,41 @@ hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();
 int num_cus();
+
+// Lockstep batch (2D): per-instance arguments of a multi-instance launch,
+// launch kinds and the group's grid bounds.
+struct LsArg {
+  int inst;       // index into the device DevInst array
+  int M;          // modes of u^{k+1} built so far (append: the count after it)
+  int sweep;      // sweep number of the current mode (1-based)
+  int mode;       // current mode index
+  int warm;       // initial guess: mode m of u^k
+  int flag;       // append pending / leading signature of a continued sweep
+  int nlin;       // linear RHS column chunks for M
+  int nld[2];     // load chunks of the RHS of direction 0, 1
+  int pad;
+  int64_t step;   // time-step index (keys the counter-based guess)
+};
+enum { kLsReset = 0, kLsAppend, kLsInit, kLsFinalizeInit, kLsSignatureAll, kLsSignature,
+       kLsSignatureFlag, kLsRhs, kLsSolve, kLsGather };
+struct LsGrid {
+  int nmax = 0;      // largest node count of the launched axis / instance
+  int ndot = 0;      // signature dot blocks
+  int nchunk = 0;    // RHS chunks (linear + load)
+  int B = 0;         // band half-width shared by the group
+  int mode = 0, threads = 0;   // BCR storage class and threads
+  size_t shm = 0;
+};
+hipError_t launch_multi(int kind, DevInst* insts, const LsArg* args, int count, const LsGrid& g,
+                        hipStream_t st, int d = 0, DevScalars* out = nullptr);
+void bcr_launch_class(int n, int B, int& mode, int& threads, size_t& shm);
+
+// Lockstep execution of 2D instances (solver.hip): adaptive, cyclic-reduction
+// solves, one band width; results equal the instances' own ctd_step.
+bool lockstep_eligible(const ctd_solver* s);
+int band_halfwidth(const ctd_solver* s);
+int lockstep_steps(std::vector<ctd_solver*>& S, int nsteps, ctd_step_info* info, hipStream_t st,
+                   std::string& err);
 
 // Instance plumbing for the executors (batch, server).
 void solver_bind_stream(ctd_solver* s, hipStream_t st);   // between ctd_step calls

@@ -8,7 +8,6 @@
 #include "ctd_internal.h"
 
 #include <algorithm>
-#include <type_traits>
 #include <cmath>
 #include <mutex>
 
@@ -154,10 +153,10 @@ __device__ __forceinline__ uint64_t sm64(uint64_t x) {
   return z ^ (z >> 31);
 }
 
-__global__ void k_init_mode(DevInst I, uint64_t step, int mode, int warm) {
-  const int d = blockIdx.y;
+__device__ __forceinline__ void init_mode_body(const DevInst& I, uint64_t step, int mode, int warm,
+                                               int bx, int d) {
   const DevAxis& A = I.ax[d];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   double val;
   if (warm && mode < I.Mk) {
@@ -171,6 +170,10 @@ __global__ void k_init_mode(DevInst I, uint64_t step, int mode, int warm) {
     val = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
   }
   A.u[i] = val;
+}
+
+__global__ void k_init_mode(DevInst I, uint64_t step, int mode, int warm) {
+  init_mode_body(I, step, mode, warm, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_init_mode(const DevInst& I, int64_t step, int mode, int warm,
@@ -425,13 +428,14 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
 // Grams of the freshly solved factor u_d against the stored columns
 // (gm = X^T M u, gk = X^T K u over the M modes of u^{k+1}, gmk = X^kT M u)
 // and v = W * (Phi u) at the Gauss points (3D cubic route).
-__global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v) {
-  // d < 0: every direction at once, direction blockIdx.y (the initial guesses)
-  DevAxis& A = I.ax[d < 0 ? (int)blockIdx.y : d];
+__device__ __forceinline__ void signature_body(const DevInst& I, int d, int M, int ndot_blocks, int want_v,
+                                               int bx, int by) {
+  // d < 0: every direction at once, direction by (the initial guesses)
+  const DevAxis& A = I.ax[d < 0 ? by : d];
   const int n = A.n;
-  if ((int)blockIdx.x < ndot_blocks) {
+  if (bx < ndot_blocks) {
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + w;
+    const int idx = bx * 4 + w;
     const int total = 2 * M + I.Mk;
     if (idx >= total) return;
     const double* col;
@@ -447,7 +451,7 @@ __global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v
     return;
   }
   if (!want_v) return;
-  const int q = (blockIdx.x - ndot_blocks) * blockDim.x + threadIdx.x;
+  const int q = (bx - ndot_blocks) * blockDim.x + threadIdx.x;
   if (q >= A.nq) return;
   const int st = elem_start(q / A.ng, A.s, n, A.SW);
   const double* ph = A.phi + (size_t)q * A.SW;
@@ -456,6 +460,10 @@ __global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v
   val *= A.w[q];
   A.v[q] = val;
   if (I.mixed) A.vf[q] = (float)val;
+}
+
+__global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v) {
+  signature_body(I, d, M, ndot_blocks, want_v, blockIdx.x, blockIdx.y);
 }
 
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st) {
@@ -494,16 +502,16 @@ __device__ __forceinline__ int rhs_columns(const DevInst& I, int M, int load_onl
   return load_only ? (I.dim == 3 ? I.Mk : 0) : I.Mk + 2 * M;
 }
 
-__global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
+__device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int load_only, int nchunk,
+                                         int bx, int y) {
   // nchunk: the linear column chunks; the load chunks follow
   extern __shared__ double hl[];
   __shared__ double coef[64];
   __shared__ double part[256];
-  DevAxis& A = I.ax[d];
+  const DevAxis& A = I.ax[d];
   const int n = A.n;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int r0 = blockIdx.x * 64, i = r0 + l;
-  const int y = blockIdx.y;
+  const int r0 = bx * 64, i = r0 + l;
   if (y < nchunk) {
     const int ctot = rhs_columns(I, M, load_only);
     // 16 columns per wave, loaded before the coefficients are ready
@@ -628,6 +636,10 @@ __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_o
     if (w == 0) F = I.omega * (part[l] + part[64 + l] + part[128 + l] + part[192 + l]);
   }
   if (w == 0 && i < n) A.rpart[(size_t)nchunk * n + i] = load_only ? F : -F;
+}
+
+__global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
+  rhs_body(I, d, M, load_only, nchunk, blockIdx.x, blockIdx.y);
 }
 
 static int rhs_linear_chunks(const DevInst& I, int M, int load_only) {
@@ -1347,10 +1359,10 @@ hipError_t launch_copy16(void* dst, const void* src, size_t bytes, hipStream_t s
 // Append the converged rank-one term as mode M and take the enrichment
 // decision: stop when its nodal max sigma * prod max|u_d| <= enrich_tol, or
 // at the mode cap.
-__global__ void k_append(DevInst I, int M) {
+__device__ __forceinline__ void append_body(const DevInst& I, int M) {
   const double sigma = I.sc->sigma[I.dim - 1];
   for (int d = 0; d < I.dim; ++d) {
-    DevAxis& A = I.ax[d];
+    const DevAxis& A = I.ax[d];
     for (int i = threadIdx.x; i < A.n; i += blockDim.x) {
       A.X[(size_t)M * A.n + i] = A.u[i];
       A.MX[(size_t)M * A.n + i] = A.Mu[i];
@@ -1367,6 +1379,8 @@ __global__ void k_append(DevInst I, int M) {
     I.sc->stop = (t <= I.enrich_tol) ? 1 : ((M + 1 >= I.max_modes) ? 2 : 0);
   }
 }
+
+__global__ void k_append(DevInst I, int M) { append_body(I, M); }
 
 hipError_t launch_append(const DevInst& I, int M, hipStream_t st) {
   k_append<<<1, 256, 0, st>>>(I, M);
@@ -1526,6 +1540,227 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
   }
 }
 
+// g for the FP32 path, by triple class.  A workgroup takes one triple and
+// one range of Gauss points (split-K), staged in 64-point chunks exactly as
+// in k_cubic_g (global_load_lds into two buffers, one barrier per chunk).
+// Triples of three distinct tiles (A < B < C): each wave runs 4 of the 16
+// chains (mode a of A) over every point of a chunk, output blocks (b, c).
+// Triples with a repeated tile hold each unordered mode pair of that tile
+// once: 136 pairs in 9 blocks of 16 rows, row i of block k the pair
+// (i, i + k mod 16) (block 8 holds each of its 8 pairs twice), against the
+// 16 modes of the other tile as columns; for A = B <= C the pairs are those
+// of A against C, for A < B = C those of B against A.  There each wave runs
+// the 9 blocks over 16 of a chunk's 64 points, the A operand of row i the
+// product Y_i Y_{i+k} v of its own point, and the four waves' sums are added
+// in LDS at the end.  9 blocks instead of 16 chains: the repeated-tile
+// triples run about 16/9 as many points per split (more points, fewer
+// splits), so all workgroups carry about the same work.
+__global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
+  constexpr int TS = kTileSq * kTile;
+  constexpr int PS9 = 9 * kTileSq;                  // outputs of a repeated-tile triple
+  constexpr int RW = 12;                            // 16-byte words per Gauss point (3 segments)
+  constexpr int NW = RW * kGChunk / 256;            // words per thread per chunk
+  constexpr int VW = kGChunk * 4 / 16;              // words of v per chunk
+  constexpr int SS = kGChunk * kTile;               // segment stride (floats)
+  const DevAxis& A = I.ax[d];
+  const float* Y = A.Xhf;
+  const float* vq = A.vf;
+  const int nd = I.ntri_d, np = I.ntri_p;
+  const int b = blockIdx.x;
+  int rank, split, t;
+  bool rep;
+  if (b < nd * I.nsplit_g) {
+    rank = b % nd;
+    split = b / nd;
+    rep = false;
+    t = I.tlist[rank];
+  } else {
+    const int b2 = b - nd * I.nsplit_g;
+    rank = b2 % np;
+    split = b2 / np;
+    rep = true;
+    t = I.tlist_p[rank];
+  }
+  const int nsplit = rep ? I.nsplit_p : I.nsplit_g;
+  const int4 tr = I.tri[t];
+  const int col0[3] = {tr.x * kTile, tr.y * kTile, tr.z * kTile};
+  const int nq = A.nq;
+  const int per = ((nq + nsplit - 1) / nsplit + kGChunk - 1) / kGChunk * kGChunk;
+  const int qbeg = split * per;
+  const int qend = qbeg + per < nq ? qbeg + per : nq;
+  const int nchunk = qend > qbeg ? (qend - qbeg + kGChunk - 1) / kGChunk : 0;
+  __shared__ uint4 ysA[kGChunk * RW], ysB[kGChunk * RW];
+  __shared__ uint4 vsA[VW], vsB[VW];
+  const int tid = threadIdx.x, l = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const size_t nqp = (size_t)(nq + 63) / 64 * 64;
+  // word f = tid + 256 k of a chunk: segment f / 256 (= k), point
+  // (f % 256) / 4, part f % 4 (the tile-major table: a wave reads 1 KB of
+  // consecutive memory)
+  auto load_chunk = [&](int q0, uint4* ys, uint4* vs) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int f = tid + 256 * k;
+      const int arr = f >> 8, row = (f & 255) >> 2, part = f & 3;
+      const float* src = Y + ((size_t)(col0[arr] >> 4) * nqp + q0 + row) * kTile + part * 4;
+      __builtin_amdgcn_global_load_lds((const void*)src, CTD_LDS(ys + 256 * k + 64 * w), 16, 0, 0);
+    }
+    if (w == 0 && l < VW)
+      __builtin_amdgcn_global_load_lds((const void*)((const uint4*)(vq + q0) + l), CTD_LDS(vs), 16, 0, 0);
+  };
+  const int e = l & 15;
+  auto slot = [](int m) { return ((m & 3) << 2) + (m >> 2); };   // mode m of a tile row
+  const int es = slot(e);
+  auto chunk_loop = [&](auto compute) {
+    auto step = [&](int ci, const uint4* ys, const uint4* vs, uint4* ysn, uint4* vsn) {
+      if (ci + 1 < nchunk) load_chunk(qbeg + (ci + 1) * kGChunk, ysn, vsn);
+      __builtin_amdgcn_sched_barrier(0);
+      compute((const float*)ys, (const float*)vs);
+      __syncthreads();
+    };
+    if (nchunk > 0) load_chunk(qbeg, ysA, vsA);
+    __syncthreads();
+    for (int ci = 0; ci < nchunk; ci += 2) {
+      step(ci, ysA, vsA, ysB, vsB);
+      if (ci + 1 < nchunk) step(ci + 1, ysB, vsB, ysA, vsA);
+    }
+  };
+  float* gp = (float*)I.gpart;
+  if (!rep) {
+    f4 acc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = f4{0, 0, 0, 0};
+    chunk_loop([&](const float* ys, const float* vs) {
+#pragma unroll
+      for (int ks = 0; ks < kGChunk / 4; ++ks) {
+        const int qq = ks * 4 + (l >> 4);
+        const float* yr = ys + qq * kTile;
+        const float bval = yr[2 * SS + es];
+        const float ybv = yr[SS + es] * vs[qq];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          // chain r: mode w + 4 r of A, slot 4 w + r (the wave's four values are one word)
+          acc[r] = mfma16(yr[w * 4 + r] * ybv, bval, acc[r]);
+      }
+    });
+    float* out = gp + ((size_t)rank * I.nsplit_g + split) * TS;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        out[((w + 4 * r) * kTile + mfma_row<float>(l, k)) * kTile + (l & 15)] = acc[r][k];
+    return;
+  }
+  // repeated tile: pair tile and column tile (segments of the chunk)
+  const bool p2 = tr.x < tr.y;                        // A < B = C: pairs of B, columns A
+  const int pa = p2 ? 1 : 0, pc = p2 ? 0 : 2;
+  int off[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) off[k] = pa * SS + slot((e + k) & 15);
+  f4 acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = f4{0, 0, 0, 0};
+  chunk_loop([&](const float* ys, const float* vs) {
+#pragma unroll 1
+    for (int ks = 0; ks < 4; ++ks) {
+      const int qq = w * 16 + ks * 4 + (l >> 4);      // this lane's point of the chunk
+      const float* yr = ys + qq * kTile;
+      const float own = yr[off[0]] * vs[qq];
+      const float bval = yr[pc * SS + es];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] = mfma16(own * yr[off[k]], bval, acc[k]);
+    }
+  });
+  // add the four waves' sums (wave order), three blocks at a time
+  float* red = (float*)ysA;                           // 3 waves x 3 blocks x 256 values
+  float* out = gp + (size_t)nd * I.nsplit_g * TS + ((size_t)rank * I.nsplit_p + split) * PS9;
+#pragma unroll
+  for (int h = 0; h < 3; ++h) {
+    if (w > 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) red[(((w - 1) * 3 + r) * 4 + k) * 64 + l] = acc[h * 3 + r][k];
+    }
+    __syncthreads();
+    if (w == 0) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int blk = h * 3 + r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          float sum = acc[blk][k];
+#pragma unroll
+          for (int u = 0; u < 3; ++u) sum += red[((u * 3 + r) * 4 + k) * 64 + l];
+          out[(blk * kTile + mfma_row<float>(l, k)) * kTile + (l & 15)] = sum;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Split-K reduction of the FP32 g by class (fixed split order), and S = w g_d
+// g_other in the h kernel's order and layout.  One thread per element of an
+// h tile (first mode, second mode, column mode); for a repeated-tile triple
+// the element reads its pair's block and row ((f, s) with s - f = k <= 8:
+// block k, row f; else block 16 - k, row s), and pairs with f > s are zero.
+// g_d is kept in the class layout (only the elements read here are written).
+__global__ __launch_bounds__(256) void k_cubic_gred32(DevInst I, int d, int e_other) {
+  constexpr int TS = kTileSq * kTile;
+  constexpr int PS9 = 9 * kTileSq;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)I.ntri * TS) return;
+  const int p = (int)(idx / TS);
+  const int eh = (int)(idx - (size_t)p * TS);
+  const int f = eh >> 8, sc = (eh >> 4) & 15, col = eh & 15;
+  const int t = I.thinv[p];
+  const int2 cr = I.trank[t];
+  const int nd = I.ntri_d;
+  const float* gp = (const float*)I.gpart;
+  size_t base, stride, goff;
+  int ns, el;
+  double pw = 1.0;
+  if (cr.x == 0) {
+    el = eh;                                           // distinct tiles: (a, b, c) = (f, s, col)
+    base = (size_t)cr.y * I.nsplit_g * TS;
+    stride = TS;
+    ns = I.nsplit_g;
+    goff = (size_t)cr.y * TS;
+  } else {
+    pw = f < sc ? 2.0 : (f == sc ? 1.0 : 0.0);
+    const int k = sc - f;
+    const int blk = k <= 8 ? k : 16 - k, row = k <= 8 ? f : sc;
+    el = (blk * kTile + row) * kTile + col;
+    base = (size_t)nd * I.nsplit_g * TS + (size_t)cr.y * I.nsplit_p * PS9;
+    stride = PS9;
+    ns = I.nsplit_p;
+    goff = (size_t)nd * TS + (size_t)cr.y * PS9;
+  }
+  float* gd = (float*)I.ax[d].g;
+  double s = 0.0;
+  if (pw != 0.0) {
+    int sp = 0;
+    for (; sp + 8 <= ns; sp += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = gp[base + (size_t)(sp + u) * stride + el];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; sp < ns; ++sp) s += (double)gp[base + (size_t)sp * stride + el];
+    gd[goff + el] = (float)s;
+  }
+  if (e_other >= 0) {
+    const float* go = (const float*)I.ax[e_other].g;
+    const float val = pw == 0.0 ? 0.0f : (float)((double)I.tri[t].w * pw * s * (double)go[goff + el]);
+    // element eh = 64 ks + l of the tile (k-step ks, lane l) goes where lane
+    // l finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
+    const int ks = eh >> 6, l = eh & 63;
+    ((float*)I.S)[(size_t)p * TS + ((((ks >> 2) << 6) + l) << 2) + (ks & 3)] = val;
+  }
+}
+
 // Split-K reduction of g in fixed split order, and S = w g_d g_other.  A
 // separate launch: a cross-workgroup reduction inside k_cubic_g needs device-
 // scope fences, whose L2 write-back/invalidate on this chip costs more than
@@ -1553,22 +1788,27 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
     const int t = (int)(idx / per);
     const T* go = (const T*)I.ax[e_other].g;
     const int4 tr = I.tri[t];
+    const int2 hm = I.trimap[t];
     const int e = (int)(idx - (size_t)t * per);
-    // tile element e = (a 16 + b) 16 + c.  When the first two tiles coincide
-    // the h contraction runs over pairs a <= b only: weight 2 off the
-    // diagonal, 1 on it, 0 below (S is symmetric in a, b there).
+    // tile element e = (a 16 + b) 16 + c of triple (A, B, C).  h runs the
+    // triple at position hm.x of its own order over (first, second) mode
+    // pairs against a column tile: (a, b) against c, or for A < B = C
+    // (hm.y = 1) the pairs (b, c) against a, so the element goes to
+    // e' = (b 16 + c) 16 + a.  Where the two pair tiles coincide only pairs
+    // first <= second are taken: weight 2 off the diagonal, 1 on it, 0 below
+    // (S is symmetric in the pair there).
+    const int a = e >> 8, b = (e >> 4) & 15, c = e & 15;
+    const int f = hm.y ? b : a, sec = hm.y ? c : b, col = hm.y ? a : c;
     double wt = (double)tr.w;
-    if (tr.x == tr.y) {
-      const int a = e >> 8, b = (e >> 4) & 15;
-      wt *= a < b ? 2.0 : (a == b ? 1.0 : 0.0);
-    }
+    if (hm.y || tr.x == tr.y) wt *= f < sec ? 2.0 : (f == sec ? 1.0 : 0.0);
     const T val = (T)(wt * s * (double)go[idx]);
-    size_t dst = idx;
+    const int eh = (f * 16 + sec) * 16 + col;
+    size_t dst = (size_t)hm.x * per + eh;
     if (sizeof(T) == 4) {
-      // element e = 64 ks + l of the tile (k-step ks, lane l) goes where lane l
-      // finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
-      const int ks = e >> 6, l = e & 63;
-      dst = (size_t)t * per + ((((ks >> 2) << 6) + l) << 2) + (ks & 3);
+      // element eh = 64 ks + l of the tile (k-step ks, lane l) goes where lane
+      // l finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
+      const int ks = eh >> 6, l = eh & 63;
+      dst = (size_t)hm.x * per + ((((ks >> 2) << 6) + l) << 2) + (ks & 3);
     }
     ((T*)I.S)[dst] = val;
   }
@@ -1625,7 +1865,7 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
   float xb[HR][4], xbn[HR][4];
 #define H32_FETCH(tt, XA, XB)                                                    \
   do {                                                                          \
-    const int4 tr_ = I.tri[tt];                                                 \
+    const int4 tr_ = I.trih[tt];                                                \
     const size_t base_ = (size_t)(tt) * TW + tid;                               \
     _Pragma("unroll") for (int v = 0; v < TW / 256; ++v) pre[v] = Sp[base_ + v * 256]; \
     _Pragma("unroll") for (int rb = 0; rb < HR; ++rb) {                         \
@@ -1669,7 +1909,8 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
     }
   };
   for (int t = t0; t < t1; ++t) {
-    const int cz = I.tri[t].z;
+    const int4 th = I.trih[t];
+    const int cz = th.z;
     H32_FETCH(t + 1 < tlast ? t + 1 : tlast, xan, xbn);
     if (cz != curC) {
       if (curC >= 0) close_c();
@@ -1677,9 +1918,10 @@ __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
     }
     const float4* sq = sb + ((t - t0) & 1) * TW;
     // k-step ks = 4 j + u pairs mode a = j of the first tile with b = 4 u + g
-    // of the second; when the two tiles coincide, the k-steps whose four b
-    // all lie below a (u < j / 4) meet only zero weights in S and are skipped
-    const bool full = I.tri[t].x != I.tri[t].y;
+    // of the second; when the pairs are taken once (first tile = second
+    // tile), the k-steps whose four b all lie below a (u < j / 4) meet only
+    // zero weights in S and are skipped
+    const bool full = th.w == 0;
 #pragma unroll
     for (int j = 0; j < kTileSq / 16; ++j) {
       const float4 b4 = sq[j * 64 + l];
@@ -1765,7 +2007,7 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   V acc = V{0, 0, 0, 0};
   int curC = -1;
   for (int t = t0; t < t1; ++t) {
-    const int4 tr = I.tri[t];
+    const int4 tr = I.trih[t];
     {
       const int tn = t + 1 < tlast ? t + 1 : tlast;
       const uint4* src = (const uint4*)((const T*)I.S + (size_t)tn * TS);
@@ -1795,8 +2037,8 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
     for (int a = 0; a < kTile; ++a) xa[a] = xs[rowA * ldx + A0 + a];
 #pragma unroll
     for (int m = 0; m < 4; ++m) xb[m] = xs[rowA * ldx + B0 + 4 * m + (l >> 4)];
-    // symmetric pair skip when the first two tiles coincide (as in the FP32 kernel)
-    const bool full = tr.x != tr.y;
+    // symmetric pair skip when the pair tiles coincide (as in the FP32 kernel)
+    const bool full = tr.w == 0;
 #pragma unroll
     for (int ks = 0; ks < kTileSq / 4; ++ks) {
       if ((ks & 3) < (ks >> 4) && !full) continue;
@@ -1833,16 +2075,19 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
 }
 
 hipError_t launch_cubic_g(const DevInst& I, int d, hipStream_t st) {
-  const int grid = I.ntri * I.nsplit_g;
-  if (I.mixed) k_cubic_g<float><<<grid, 256, 0, st>>>(I, d);
-  else k_cubic_g<double><<<grid, 256, 0, st>>>(I, d);
+  if (I.mixed) {
+    const int grid = I.ntri_d * I.nsplit_g + I.ntri_p * I.nsplit_p;
+    k_cubic_g32<<<grid, 256, 0, st>>>(I, d);
+  } else {
+    k_cubic_g<double><<<I.ntri * I.nsplit_g, 256, 0, st>>>(I, d);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t st) {
   const size_t total = (size_t)I.ntri * kTileSq * kTile;
   const int blocks = (int)((total + 255) / 256);
-  if (I.mixed) k_cubic_gred<float><<<blocks, 256, 0, st>>>(I, d, e_other);
+  if (I.mixed) k_cubic_gred32<<<blocks, 256, 0, st>>>(I, d, e_other);
   else k_cubic_gred<double><<<blocks, 256, 0, st>>>(I, d, e_other);
   return hipGetLastError();
 }
@@ -2332,6 +2577,148 @@ hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
   if (dtype == CTD_DTYPE_F32) k_reconstruct<float><<<blocks, 256, 0, st>>>(I, M, (float*)out);
   else k_reconstruct<double><<<blocks, 256, 0, st>>>(I, M, (double*)out);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ lockstep batch
+// Multi-instance launches: one launch serves a group of 2D instances at the
+// same phase of their own step (each with its own mode count, sweep number
+// and sizes).  blockIdx.z selects the group entry (LsArg); the grid covers
+// the largest instance of the group and the blocks an instance does not need
+// return at once.  Each instance's arithmetic is that of its own launches.
+__global__ void k_reset_scalars_m(DevInst* insts, const LsArg* args) {
+  DevScalars* sc = insts[args[blockIdx.z].inst].sc;
+  if (threadIdx.x == 0) {
+    sc->converged = 0;
+    sc->zero = 0;
+    sc->nonfinite = 0;
+    sc->change = -1.0;
+    sc->sigma_prev = 0.0;
+  }
+}
+
+__global__ void k_append_m(DevInst* insts, const LsArg* args) {
+  const LsArg& a = args[blockIdx.z];
+  if (!a.flag) return;
+  append_body(insts[a.inst], a.M - 1);
+}
+
+__global__ void k_init_mode_m(DevInst* insts, const LsArg* args) {
+  const LsArg& a = args[blockIdx.z];
+  const DevInst& I = insts[a.inst];
+  const int d = blockIdx.y;
+  if ((int)blockIdx.x * (int)blockDim.x >= I.ax[d].n) return;
+  init_mode_body(I, (uint64_t)a.step, a.mode, a.warm, blockIdx.x, d);
+}
+
+template <int B>
+__global__ __launch_bounds__(1024) void k_finalize_init_m(DevInst* insts, const LsArg* args) {
+  __shared__ double red[96];
+  extern __shared__ double ul[];
+  DevInst& I = insts[args[blockIdx.z].inst];
+  finalize_body<B>(I, (int)blockIdx.x, 0, 1, red, ul, 0);
+}
+
+// d < 0: every direction (the initial guesses), direction blockIdx.y
+__global__ void k_signature_m(DevInst* insts, const LsArg* args, int d, int need_flag) {
+  const LsArg& a = args[blockIdx.z];
+  if (need_flag && !a.flag) return;
+  const DevInst& I = insts[a.inst];
+  const int ndot = (2 * a.M + I.Mk + 3) / 4;
+  if ((int)blockIdx.x >= ndot) return;
+  signature_body(I, d, a.M, ndot, 0, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(256) void k_rhs_m(DevInst* insts, const LsArg* args, int d) {
+  const LsArg& a = args[blockIdx.z];
+  const DevInst& I = insts[a.inst];
+  if ((int)blockIdx.x * 64 >= I.ax[d].n || (int)blockIdx.y >= a.nlin + a.nld[d]) return;
+  rhs_body(I, d, a.M, 0, a.nlin, blockIdx.x, blockIdx.y);
+}
+
+template <int B, int MODE>
+__global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr_m(DevInst* insts, const LsArg* args, int d) {
+  extern __shared__ double lds[];
+  const LsArg& a = args[blockIdx.z];
+  DevInst& I = insts[a.inst];
+  double* gws = MODE == 0 ? nullptr : I.bcr_ws;
+  BcrMem<B, MODE> mem{MODE == 1 ? gws : lds, MODE == 2 ? gws : nullptr};
+  double* sm = MODE == 1 ? gws : lds;
+  __shared__ double red[96];
+  __shared__ double ab[2];
+  DevAxis& A = I.ax[d];
+  if (threadIdx.x == 0) {
+    directional_coeffs(I, d, ab[0], ab[1]);
+    I.sc->alpha[d] = ab[0];
+    I.sc->beta[d] = ab[1];
+  }
+  __syncthreads();
+  bcr_solve_par<B, MODE>(A.n, A.Mb, A.Kb, ab[0], ab[1], A.rpart, a.nlin + a.nld[d] - 1, A.u, mem);
+  finalize_body<B>(I, d, a.sweep, 0, red, sm);
+}
+
+__global__ void k_gather_scalars_m(DevInst* insts, const LsArg* args, DevScalars* out) {
+  const LsArg& a = args[blockIdx.z];
+  const int* src = (const int*)insts[a.inst].sc;
+  int* dst = (int*)(out + blockIdx.z);
+  for (int k = threadIdx.x; k < (int)(sizeof(DevScalars) / sizeof(int)); k += blockDim.x) dst[k] = src[k];
+}
+
+hipError_t launch_multi(int kind, DevInst* insts, const LsArg* args, int count, const LsGrid& g,
+                        hipStream_t st, int d, DevScalars* out) {
+  if (count <= 0) return hipSuccess;
+  switch (kind) {
+    case kLsReset: k_reset_scalars_m<<<dim3(1, 1, count), 64, 0, st>>>(insts, args); break;
+    case kLsAppend: k_append_m<<<dim3(1, 1, count), 256, 0, st>>>(insts, args); break;
+    case kLsInit: k_init_mode_m<<<dim3((g.nmax + 255) / 256, 2, count), 256, 0, st>>>(insts, args); break;
+    case kLsFinalizeInit: {
+      // g.threads: the workgroup size of the instances' own launch (the
+      // reductions' order depends on it), g.nmax: their largest axis
+      const size_t shm = sizeof(double) * 3 * (size_t)g.nmax;
+      const int nt = g.threads;
+      if (nt < 64 || nt > 1024 || nt < (g.nmax >= 1024 ? 1024 : (g.nmax + 63) / 64 * 64))
+        return hipErrorInvalidValue;
+      switch (g.B) {
+        case 3: k_finalize_init_m<3><<<dim3(2, 1, count), nt, shm, st>>>(insts, args); break;
+        case 5: k_finalize_init_m<5><<<dim3(2, 1, count), nt, shm, st>>>(insts, args); break;
+        case 7: k_finalize_init_m<7><<<dim3(2, 1, count), nt, shm, st>>>(insts, args); break;
+        default: return hipErrorInvalidValue;
+      }
+      break;
+    }
+    case kLsSignatureAll:
+      k_signature_m<<<dim3(g.ndot, 2, count), 256, 0, st>>>(insts, args, -1, 0);
+      break;
+    case kLsSignature: k_signature_m<<<dim3(g.ndot, 1, count), 256, 0, st>>>(insts, args, d, 0); break;
+    case kLsSignatureFlag: k_signature_m<<<dim3(g.ndot, 1, count), 256, 0, st>>>(insts, args, d, 1); break;
+    case kLsRhs: k_rhs_m<<<dim3((g.nmax + 63) / 64, g.nchunk, count), 256, 0, st>>>(insts, args, d); break;
+    case kLsSolve: {
+#define SOLVE_M(BW)                                                                                   \
+  (g.mode == 0 ? k_solve_bcr_m<BW, 0><<<dim3(1, 1, count), g.threads, g.shm, st>>>(insts, args, d)    \
+               : g.mode == 2 ? k_solve_bcr_m<BW, 2><<<dim3(1, 1, count), g.threads, g.shm, st>>>(insts, args, d) \
+                             : k_solve_bcr_m<BW, 1><<<dim3(1, 1, count), g.threads, 0, st>>>(insts, args, d))
+      switch (g.B) {
+        case 3: SOLVE_M(3); break;
+        case 5: SOLVE_M(5); break;
+        case 7: SOLVE_M(7); break;
+        default: return hipErrorInvalidValue;
+      }
+#undef SOLVE_M
+      break;
+    }
+    case kLsGather: k_gather_scalars_m<<<dim3(1, 1, count), 64, 0, st>>>(insts, args, out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// BCR launch class of an axis: storage mode (0 LDS, 2 split, 1 workspace),
+// threads and dynamic LDS bytes
+void bcr_launch_class(int n, int B, int& mode, int& threads, size_t& shm) {
+  const bool fits = bcr_fits(n, B);
+  const bool split = !fits && bcr_split_fits(n, B);
+  mode = fits ? 0 : (split ? 2 : 1);
+  threads = bcr_threads(n, B);
+  shm = fits ? bcr_lds_bytes(n, B) : (split ? bcr_split_lds_bytes(n, B) : 0);
 }
 
 // Strided placement of a C-ordered nodal grid (caller layouts of

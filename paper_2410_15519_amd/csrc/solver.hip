@@ -16,6 +16,7 @@
 #include <mutex>
 #include <limits>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ctd_internal.h"
@@ -302,6 +303,49 @@ std::vector<int4> make_triples(int nb) {
   return t;
 }
 
+// The h contraction's order of the same triples.  h runs each triple as an
+// MFMA product over pairs of modes (first, second tile) against the modes of
+// the column tile; where two tiles coincide it takes their pairs once (the
+// ordered pairs below the diagonal meet zero weights and are skipped): A = B
+// pairs (a <= b) with column C; A < B = C pairs (b <= c) with column A.  The
+// C-groups of the C-major order stay in place (a step with fewer mode tiles
+// uses a prefix), and inside a group the triples are sorted by column tile so
+// that the per-column closing sums run once per column.
+// Class lists of the FP32 g contraction (C-major order kept inside each list,
+// so a step with fewer mode tiles uses a prefix of both).
+void make_g_classes(const std::vector<int4>& tri, std::vector<int>& tlist, std::vector<int2>& trank) {
+  const int n = (int)tri.size();
+  std::vector<int> d, p;
+  trank.assign(n, int2{0, 0});
+  for (int i = 0; i < n; ++i) {
+    const int4 t = tri[i];
+    const int cls = t.x < t.y && t.y < t.z ? 0 : (t.x == t.y && t.y < t.z ? 1 : (t.x < t.y ? 2 : 3));
+    if (cls == 0) { trank[i] = int2{0, (int)d.size()}; d.push_back(i); }
+    else { trank[i] = int2{cls, (int)p.size()}; p.push_back(i); }
+  }
+  tlist = d;
+  tlist.insert(tlist.end(), p.begin(), p.end());
+}
+
+void make_h_order(const std::vector<int4>& tri, std::vector<int4>& trih, std::vector<int2>& map) {
+  const int n = (int)tri.size();
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  auto col = [&](int i) { const int4 t = tri[i]; return (t.x < t.y && t.y == t.z) ? t.x : t.z; };
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    if (tri[a].z != tri[b].z) return tri[a].z < tri[b].z;
+    return col(a) < col(b);
+  });
+  trih.assign(n, int4{0, 0, 0, 0});
+  map.assign(n, int2{0, 0});
+  for (int p = 0; p < n; ++p) {
+    const int4 t = tri[ord[p]];
+    const bool p2 = t.x < t.y && t.y == t.z;
+    trih[p] = p2 ? int4{t.y, t.z, t.x, 1} : int4{t.x, t.y, t.z, t.x == t.y ? 1 : 0};
+    map[ord[p]] = int2{p, p2 ? 1 : 0};
+  }
+}
+
 // ---- tuning table of the 3D cubic contraction (see ctd_tuning_set)
 namespace {
 std::mutex g_tune_mu;
@@ -315,6 +359,53 @@ bool tuning_lookup(int nb, int nq, int& ng, int& nh) {
   ng = it->second.first;
   nh = it->second.second;
   return true;
+}
+
+// Point splits of the FP32 g contraction by triple class.  A distinct-tile
+// triple costs 16 chains per point, a repeated-tile one 9 pair blocks, so the
+// latter get about 16/9 as many points per split; the distinct split count is
+// the one that minimises the launch length (longest workgroup times the
+// rounds of resident workgroups), or the tuning table's entry when it has
+// one.  Splits are whole 64-point chunks; the partials stay within what the
+// handle allocated.
+void fp32_g_splits(ctd_solver* s, int nq, int forced) {
+  DevInst& I = s->I;
+  const int nb = I.nb;
+  int nd = 0;
+  for (int C = 0; C < nb; ++C)
+    for (int B = 0; B <= C; ++B)
+      for (int A = 0; A <= B; ++A) nd += (A < B && B < C) ? 1 : 0;
+  I.ntri_d = nd;
+  I.ntri_p = I.ntri - nd;
+  const int nchunk = (nq + 63) / 64;
+  const double slots = (double)num_cus() * 4.0;
+  auto plan = [&](int nsd, int& pd, int& pp, int& nsp) {
+    pd = (nchunk + nsd - 1) / nsd * 64;
+    pp = std::min(nchunk * 64, ((pd * 16 + 8) / 9 + 63) / 64 * 64);
+    nsp = (nq + pp - 1) / pp;
+  };
+  int best = 1;
+  double best_cost = 1e300;
+  for (int nsd = 1; nsd <= nchunk; ++nsd) {
+    int pd, pp, nsp;
+    plan(nsd, pd, pp, nsp);
+    const int nsd_eff = (nq + pd - 1) / pd;
+    const double wgs = (double)nd * nsd_eff + (double)I.ntri_p * nsp;
+    const double floats = (double)nd * nsd_eff * 4096.0 + (double)I.ntri_p * nsp * 2304.0;
+    if (floats > (double)s->nsplit_g_cap * 4096.0) continue;
+    const double len = std::max(16.0 * (nd ? pd : 0), 9.0 * (I.ntri_p ? pp : 0));
+    const double cost = len * std::ceil(wgs / slots);
+    if (forced > 0 ? nsd == std::min(forced, nchunk) : cost < best_cost * 0.999) {
+      best = nsd;
+      best_cost = cost;
+      if (forced > 0) break;
+    }
+  }
+  int pd, pp, nsp;
+  plan(best, pd, pp, nsp);
+  // the kernel spreads each axis' Gauss points over these split counts
+  I.nsplit_g = (nq + pd - 1) / pd;
+  I.nsplit_p = nsp;
 }
 
 void update_view(ctd_solver* s) {
@@ -340,11 +431,14 @@ void update_view(ctd_solver* s) {
     if (tuning_lookup(I.nb, nqmin, tg, th)) {
       ng = tg;
       nh = th;
+    } else {
+      tg = 0;
     }
     ng = std::min(ng, (nqmin + 63) / 64);
     ng = std::min(ng, s->nsplit_g_cap / I.ntri);
     I.nsplit_g = std::max(1, ng);
     I.nsplit_h = std::max(1, std::min(I.ntri, nh));
+    if (I.mixed) fp32_g_splits(s, nqmin, tg > 0 ? tg : 0);
   }
 }
 
@@ -459,6 +553,37 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(td, sizeof(int4) * tri.size());
     HIPCHK(s, copy_sync(s, td, tri.data(), sizeof(int4) * tri.size(), hipMemcpyHostToDevice));
     I.tri = td;
+    std::vector<int4> trih;
+    std::vector<int2> map;
+    make_h_order(tri, trih, map);
+    std::vector<int> inv(map.size());
+    for (size_t t = 0; t < map.size(); ++t) inv[map[t].x] = (int)t;
+    int4* thd;
+    int2* tmd;
+    int* tid;
+    AL(thd, sizeof(int4) * trih.size());
+    AL(tmd, sizeof(int2) * map.size());
+    AL(tid, sizeof(int) * inv.size());
+    HIPCHK(s, copy_sync(s, thd, trih.data(), sizeof(int4) * trih.size(), hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, tmd, map.data(), sizeof(int2) * map.size(), hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, tid, inv.data(), sizeof(int) * inv.size(), hipMemcpyHostToDevice));
+    I.trih = thd;
+    I.trimap = tmd;
+    I.thinv = tid;
+    std::vector<int> tlist;
+    std::vector<int2> trank;
+    make_g_classes(tri, tlist, trank);
+    int* tld;
+    int2* trd;
+    AL(tld, sizeof(int) * tlist.size());
+    AL(trd, sizeof(int2) * trank.size());
+    HIPCHK(s, copy_sync(s, tld, tlist.data(), sizeof(int) * tlist.size(), hipMemcpyHostToDevice));
+    HIPCHK(s, copy_sync(s, trd, trank.data(), sizeof(int2) * trank.size(), hipMemcpyHostToDevice));
+    int ndmax = 0;
+    for (const int2& r : trank) ndmax += r.x == 0 ? 1 : 0;
+    I.tlist = tld;
+    I.tlist_p = tld + ndmax;
+    I.trank = trd;
     AL(I.gpart, Tsz * (size_t)s->nsplit_g_cap * kTileSq * kTile);
     AL(I.S, Tsz * (size_t)s->ntri_max * kTileSq * kTile);
     const int nqt = (nqmax + 63) / 64;
@@ -882,6 +1007,320 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
   return CTD_OK;
 }
 
+// ---------------------------------------------------------------- lockstep
+// Many 2D instances advanced together: every round, the instances that start
+// a mode run its initialisation launches together (multi-instance launches),
+// then every instance in a mode runs one sweep together, and one read-back
+// of all instances' scalars feeds each instance's own decisions (the same
+// decisions, in the same order, as one_step's adaptive schedule).  Steps end
+// per instance (finish_step, energy) with that instance's own launches.  The
+// arithmetic of every instance is that of its standalone launches: results
+// are identical to ctd_step on the instance alone.
+struct LockstepInst {
+  ctd_solver* s = nullptr;
+  int M = 0, mode = 0, it = 1, sweeps = 0, unconv = 0, zero = 0, capped = 0;
+  int steps_done = 0;
+  bool pending_append = false;   // appended mode's kernel goes with the next launch group
+  bool start = true;             // the next round initialises a mode
+  bool done = false;
+  double last_term = 0.0;
+  std::vector<int32_t> iters;
+  std::chrono::steady_clock::time_point t0;
+};
+
+int lockstep_finish(LockstepInst& L, ctd_step_info* info, std::vector<int32_t>& log) {
+  ctd_solver* s = L.s;
+  if (L.pending_append) {
+    HIPCHK(s, launch_append(s->I, L.M - 1, s->stream));
+    L.pending_append = false;
+  }
+  int rc = finish_step(s, L.M);
+  if (rc) return rc;
+  ++s->step_index;
+  log.push_back(L.M);
+  for (int v : L.iters) log.push_back(v);
+  if (info) {
+    info->full_solve = 0;
+    info->modes = L.M;
+    info->sweeps = L.sweeps;
+    info->capped = L.capped;
+    info->fp_unconverged = L.unconv;
+    info->zero_mode = L.zero;
+    info->last_term_max = L.last_term;
+    info->energy = std::numeric_limits<double>::quiet_NaN();
+    info->energy_increase = 0;
+    info->stability_warning = s->alpha < 4.0 * s->a0 ? 1 : 0;
+  }
+  if (s->P.energy_each_step) {
+    double E;
+    rc = energy_of_uk(s, &E);
+    if (rc) return rc;
+    if (info) {
+      info->energy = E;
+      info->energy_increase = std::isfinite(s->energy_prev) && E > s->energy_prev * (1.0 + 1e-12) + 1e-300;
+    }
+    s->energy_prev = E;
+  } else {
+    HIPCHK(s, sync_collect(s));
+  }
+  if (info) {
+    auto t1 = std::chrono::steady_clock::now();
+    info->ms = std::chrono::duration<double, std::milli>(t1 - L.t0).count();
+  }
+  // next step from mode 0
+  L.M = 0; L.mode = 0; L.it = 1; L.sweeps = 0; L.unconv = 0; L.zero = 0; L.capped = 0;
+  L.last_term = 0.0;
+  L.iters.clear();
+  L.start = true;
+  ++L.steps_done;
+  L.t0 = std::chrono::steady_clock::now();
+  return CTD_OK;
+}
+
+}  // namespace
+
+namespace ctd {
+
+bool lockstep_eligible(const ctd_solver* s) {
+  return s->dim == 2 && s->P.schedule == CTD_SCHED_ADAPTIVE && !s->actd && !s->use_fd[0] &&
+         !s->use_fd[1] && s->ax[0].B == s->ax[1].B;
+}
+
+int band_halfwidth(const ctd_solver* s) { return s->ax[0].B; }
+
+int lockstep_steps(std::vector<ctd_solver*>& S, int nsteps, ctd_step_info* info, hipStream_t st,
+                   std::string& err) {
+  const int N = (int)S.size();
+  if (N == 0 || nsteps <= 0) return CTD_OK;
+  const int B = S[0]->ax[0].B;
+  for (ctd_solver* s : S) {
+    if (!lockstep_eligible(s) || s->ax[0].B != B) { err = "instance not eligible for lockstep"; return CTD_EINVAL; }
+    solver_bind_stream(s, st);
+  }
+  // device and pinned host mirrors: DevInst per instance, two argument
+  // arrays (initialisation group, sweep group), gathered scalars
+  DevInst* dI = nullptr;
+  LsArg* dA = nullptr;
+  DevScalars* dS = nullptr;
+  DevInst* hI = nullptr;
+  LsArg* hA = nullptr;
+  DevScalars* hS = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    if (dI) (void)hipFree(dI);
+    if (dA) (void)hipFree(dA);
+    if (dS) (void)hipFree(dS);
+    if (hI) (void)hipHostFree(hI);
+    if (hA) (void)hipHostFree(hA);
+    if (hS) (void)hipHostFree(hS);
+  };
+  auto hip = [&](hipError_t e, const char* where) {
+    if (e == hipSuccess) return CTD_OK;
+    err = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
+    return CTD_EDEVICE;
+  };
+  int rc = CTD_OK;
+  if ((rc = hip(hipMalloc(&dI, sizeof(DevInst) * N), "lockstep alloc")) ||
+      (rc = hip(hipMalloc(&dA, sizeof(LsArg) * 4 * N), "lockstep alloc")) ||
+      (rc = hip(hipMalloc(&dS, sizeof(DevScalars) * N), "lockstep alloc")) ||
+      (rc = hip(hipHostMalloc(&hI, sizeof(DevInst) * N, hipHostMallocDefault), "lockstep alloc")) ||
+      (rc = hip(hipHostMalloc(&hA, sizeof(LsArg) * 4 * N, hipHostMallocDefault), "lockstep alloc")) ||
+      (rc = hip(hipHostMalloc(&hS, sizeof(DevScalars) * N, hipHostMallocDefault), "lockstep alloc"))) {
+    cleanup();
+    return rc;
+  }
+  std::vector<LockstepInst> L(N);
+  std::vector<std::vector<int32_t>> logs(N);
+  auto upload = [&](int i) {
+    update_view(S[i]);
+    hI[i] = S[i]->I;
+    return hip(hipMemcpyAsync(dI + i, hI + i, sizeof(DevInst), hipMemcpyHostToDevice, st), "lockstep upload");
+  };
+  for (int i = 0; i < N; ++i) {
+    L[i].s = S[i];
+    L[i].t0 = std::chrono::steady_clock::now();
+    if ((rc = upload(i))) { cleanup(); return rc; }
+  }
+  auto fill = [&](LsArg& a, int i) {
+    const ctd_solver* s = S[i];
+    a.inst = i;
+    a.M = L[i].M;
+    a.sweep = L[i].it;
+    a.mode = L[i].mode;
+    a.warm = s->P.init_mode == CTD_INIT_WARM;
+    a.nlin = (s->Mk + 2 * L[i].M + 63) / 64;
+    for (int d = 0; d < 2; ++d) a.nld[d] = (s->ax[1 - d].n + 63) / 64;
+    a.step = s->step_index;
+  };
+  // workgroup size of an instance's own initial-guess finalisation
+  auto finalize_threads = [&](int i) {
+    const int n = std::max(S[i]->ax[0].n, S[i]->ax[1].n);
+    return n >= 1024 ? 1024 : (n + 63) / 64 * 64;
+  };
+  for (;;) {
+    // groups of this round; the initialisation group ordered by its
+    // finalisation workgroup size (one launch per size)
+    std::vector<int> gi, gs;
+    for (int i = 0; i < N; ++i) {
+      if (L[i].done) continue;
+      if (L[i].start) gi.push_back(i);
+      gs.push_back(i);
+    }
+    if (gs.empty()) break;
+    std::stable_sort(gi.begin(), gi.end(),
+                     [&](int a, int b) { return finalize_threads(a) < finalize_threads(b); });
+    const int ni = (int)gi.size(), ns = (int)gs.size();
+    LsArg* hAi = hA;
+    LsArg* hAs = hA + N;
+    for (int k = 0; k < ni; ++k) { fill(hAi[k], gi[k]); hAi[k].flag = L[gi[k]].pending_append ? 1 : 0; }
+    for (int k = 0; k < ns; ++k) { fill(hAs[k], gs[k]); hAs[k].flag = L[gs[k]].it > 1 ? 1 : 0; }
+    // the solve launches: sweep entries regrouped per direction by BCR
+    // storage class and thread count (blocks [2N, 3N) and [3N, 4N))
+    struct SolveClass { int mode, threads, first, count; size_t shm; };
+    std::vector<SolveClass> scls[2];
+    for (int d = 0; d < 2; ++d) {
+      std::map<std::pair<int, int>, std::vector<int>> cls;
+      std::map<std::pair<int, int>, size_t> shm;
+      for (int k = 0; k < ns; ++k) {
+        int mode, threads;
+        size_t sh;
+        bcr_launch_class(S[gs[k]]->ax[d].n, B, mode, threads, sh);
+        cls[{mode, threads}].push_back(k);
+        shm[{mode, threads}] = std::max(shm[{mode, threads}], sh);
+      }
+      LsArg* dst = hA + (2 + d) * N;
+      int at = 0;
+      for (auto& kv : cls) {
+        scls[d].push_back({kv.first.first, kv.first.second, at, (int)kv.second.size(), shm[kv.first]});
+        for (int k : kv.second) dst[at++] = hAs[k];
+      }
+    }
+    if ((rc = hip(hipMemcpyAsync(dA, hA, sizeof(LsArg) * 4 * N, hipMemcpyHostToDevice, st), "lockstep args"))) break;
+    LsArg* dAi = dA;
+    LsArg* dAs = dA + N;
+    auto grid_of = [&](const std::vector<int>& g, const LsArg* a, int d) {
+      LsGrid G;
+      G.B = B;
+      for (size_t k = 0; k < g.size(); ++k) {
+        const ctd_solver* s = S[g[k]];
+        const int n = d < 0 ? std::max(s->ax[0].n, s->ax[1].n) : s->ax[d].n;
+        G.nmax = std::max(G.nmax, n);
+        G.ndot = std::max(G.ndot, (2 * a[k].M + s->Mk + 3) / 4);
+        if (d >= 0) G.nchunk = std::max(G.nchunk, a[k].nlin + a[k].nld[d]);
+      }
+      G.ndot = std::max(G.ndot, 1);
+      return G;
+    };
+    // mode initialisation (after the append of the previous mode)
+    if (ni > 0) {
+      const LsGrid G = grid_of(gi, hAi, -1);
+      if ((rc = hip(launch_multi(kLsAppend, dI, dAi, ni, G, st), "append")) ||
+          (rc = hip(launch_multi(kLsReset, dI, dAi, ni, G, st), "reset")) ||
+          (rc = hip(launch_multi(kLsInit, dI, dAi, ni, G, st), "init")))
+        break;
+      for (int k0 = 0; k0 < ni && rc == CTD_OK;) {
+        int k1 = k0;
+        LsGrid Gf;
+        Gf.B = B;
+        Gf.threads = finalize_threads(gi[k0]);
+        while (k1 < ni && finalize_threads(gi[k1]) == Gf.threads) {
+          Gf.nmax = std::max(Gf.nmax, std::max(S[gi[k1]]->ax[0].n, S[gi[k1]]->ax[1].n));
+          ++k1;
+        }
+        rc = hip(launch_multi(kLsFinalizeInit, dI, dAi + k0, k1 - k0, Gf, st), "finalize");
+        k0 = k1;
+      }
+      if (rc || (rc = hip(launch_multi(kLsSignatureAll, dI, dAi, ni, G, st), "signature"))) break;
+      for (int i : gi) { L[i].pending_append = false; L[i].start = false; }
+    }
+    // one sweep of every instance in a mode: the signature of the last
+    // direction (continued sweeps only), then per direction RHS and solve,
+    // and the signature of every direction but the last
+    {
+      LsGrid G1 = grid_of(gs, hAs, 1);
+      if ((rc = hip(launch_multi(kLsSignatureFlag, dI, dAs, ns, G1, st, 1), "signature"))) break;
+      for (int d = 0; d < 2 && rc == CTD_OK; ++d) {
+        const LsGrid G = grid_of(gs, hAs, d);
+        if ((rc = hip(launch_multi(kLsRhs, dI, dAs, ns, G, st, d), "rhs"))) break;
+        // the solve: one launch per BCR storage class and thread count
+        for (const SolveClass& c : scls[d]) {
+          LsGrid G2;
+          G2.B = B;
+          G2.mode = c.mode;
+          G2.threads = c.threads;
+          G2.shm = c.shm;
+          if ((rc = hip(launch_multi(kLsSolve, dI, dA + (2 + d) * N + c.first, c.count, G2, st, d), "solve")))
+            break;
+        }
+        if (rc) break;
+        if (d == 0) {
+          const LsGrid G0 = grid_of(gs, hAs, 0);
+          if ((rc = hip(launch_multi(kLsSignature, dI, dAs, ns, G0, st, 0), "signature"))) break;
+        }
+      }
+      if (rc) break;
+    }
+    // one read-back of every instance's scalars
+    if ((rc = hip(launch_multi(kLsGather, dI, dAs, ns, LsGrid{}, st, 0, dS), "gather")) ||
+        (rc = hip(hipMemcpyAsync(hS, dS, sizeof(DevScalars) * ns, hipMemcpyDeviceToHost, st), "gather")) ||
+        (rc = hip(hipStreamSynchronize(st), "gather")))
+      break;
+    // decisions, as one_step takes them
+    for (int k = 0; k < ns && rc == CTD_OK; ++k) {
+      const int i = gs[k];
+      LockstepInst& Li = L[i];
+      ctd_solver* s = S[i];
+      const DevScalars& sc = hS[k];
+      const int nsw = std::max(1, s->P.fp_max_iter);
+      bool end_step = false;
+      if (sc.zero) {
+        Li.zero = 1;
+        end_step = true;
+      } else {
+        if (sc.nonfinite) { err = "non-finite mode amplitude"; rc = CTD_ENONFINITE; break; }
+        const bool conv = sc.converged != 0 && Li.it >= 2;
+        const bool last = Li.it == nsw || conv;
+        if (!last) {
+          ++Li.it;
+          continue;
+        }
+        Li.sweeps += Li.it;
+        if (!conv) ++Li.unconv;
+        ++Li.M;
+        Li.iters.push_back(Li.it);
+        Li.pending_append = true;
+        double pu = 1.0;
+        for (int d = 0; d < 2; ++d) pu *= sc.umax[d];
+        Li.last_term = sc.sigma[1] * pu;
+        if (Li.last_term <= s->P.enrich_tol) {
+          end_step = true;
+        } else if (Li.M >= s->P.max_modes) {
+          Li.capped = 1;
+          end_step = true;
+        } else {
+          ++Li.mode;
+          Li.it = 1;
+          Li.start = true;
+        }
+      }
+      if (end_step) {
+        rc = lockstep_finish(Li, info ? info + (size_t)i * nsteps + Li.steps_done : nullptr, logs[i]);
+        if (rc) { err = s->err; break; }
+        if (Li.steps_done >= nsteps) Li.done = true;
+        else if ((rc = upload(i))) break;
+      }
+    }
+    if (rc) break;
+  }
+  cleanup();
+  if (rc == CTD_OK)
+    for (int i = 0; i < N; ++i) S[i]->decisions_last.swap(logs[i]);
+  return rc;
+}
+
+}  // namespace ctd
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -1204,7 +1643,8 @@ extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const*
     if (rc) return rc;
     rc = cubic_after(s, e2, d);
     if (rc) return rc;
-    HIPCHK(s, launch_cubic_h(s->I, d, s->stream));
+    Work w = w_cubic(s, d);
+    LAUNCH(s, CTD_K_CUBIC_H, w.flops, w.bytes, launch_cubic_h(s->I, d, s->stream));
   }
   HIPCHK(s, launch_rhs(s->I, d, 0, s->stream, 1));
   HIPCHK(s, launch_rhs_sum(s->I, d, 0, 1, s->stream));

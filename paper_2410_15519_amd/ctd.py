@@ -24,6 +24,7 @@ SCHED = {"adaptive": 0, "replay": 1}
 INIT = {"hash": 0, "warm": 1}
 DTYPE = {"f64": 0, "f32": 1}
 SOLVE = {"auto": 0, "bcr": 1, "fd": 2}
+BATCH_MODE = {"auto": 0, "lockstep": 1, "streams": 2}
 KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
            "mxy_build", "energy", "quad_eval", "other", "finalize", "full_solve"]
 
@@ -111,6 +112,7 @@ def _load():
         "ctd_batch_create": (C.c_int, [C.c_int32, P(Problem), P(C.c_int32), P(P(P(C.c_double))),
                                        P(P(C.c_double)), vp, P(vp)]),
         "ctd_batch_set_workers": (C.c_int, [vp, C.c_int32]),
+        "ctd_batch_set_mode": (C.c_int, [vp, C.c_int32]),
         "ctd_batch_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
         "ctd_footprint_bytes": (C.c_int, [P(Problem), C.c_int32, P(C.c_uint64)]),
         "ctd_server_create": (C.c_int, [C.c_uint64, C.c_int32, P(vp)]),
@@ -315,11 +317,13 @@ class Solver:
         of the grid's shape, any positive strides (filled in place)."""
         if out is not None:
             if hasattr(out, "data_ptr"):
-                strides = (C.c_int64 * 3)(*out.stride())
+                # a flat buffer (or any contiguous tensor) is taken in C order
+                strides = None if out.dim() != self.dim else (C.c_int64 * 3)(*out.stride())
                 self._check(LIB.ctd_reconstruct(self.h, C.c_void_p(out.data_ptr()), DTYPE[dtype], 1,
                                                 strides))
             else:
-                strides = (C.c_int64 * 3)(*[st // out.itemsize for st in out.strides])
+                strides = (None if out.ndim != self.dim else
+                           (C.c_int64 * 3)(*[st // out.itemsize for st in out.strides]))
                 self._check(LIB.ctd_reconstruct(self.h, out.ctypes.data_as(C.c_void_p), DTYPE[dtype],
                                                 0, strides))
             return out
@@ -469,6 +473,12 @@ class Batch:
         rc = LIB.ctd_batch_set_workers(self.h, int(workers))
         if rc != CTD_OK:
             raise CtdError(rc, "ctd_batch_set_workers")
+
+    def set_mode(self, mode):
+        """"auto" | "lockstep" | "streams" (ctd_batch_set_mode)."""
+        rc = LIB.ctd_batch_set_mode(self.h, BATCH_MODE[mode])
+        if rc != CTD_OK:
+            raise CtdError(rc, LIB.ctd_batch_last_error(self.h).decode())
 
     def modes(self, i):
         m = C.c_int32()
@@ -628,3 +638,4 @@ def band_solve(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):
                                    stream if stream is not None else current_stream())
     if rc != CTD_OK:
         raise CtdError(rc, "ctd_kernel_band_solve")
+

@@ -131,13 +131,18 @@ def test_step_energy_law_1024_cubed_mixed(ctd):
 
 
 def test_fast_diag_equals_cyclic_reduction_256_cubed(ctd):
-    """The two directional solvers on a full 256^3 step (FP64, same decisions)."""
+    """The two directional solvers on a full 256^3 step (FP64, same decisions).
+    The counter-based initial guess of a mode is used: with it this step
+    amplifies rounding differences about 200x; from the warm guess (mode m of
+    the 8-mode u^k) it amplifies them about 1e4x (18 of its 64 modes stop at
+    the sweep limit), which would test the step's conditioning rather than
+    the solvers."""
     import torch
     inst = make_instance("ac3d_n256")
     fields = {}
     dec = None
     for solve in ("bcr", "fd"):
-        kw = dict(precision="fp64", solve=solve)
+        kw = dict(precision="fp64", solve=solve, init="hash")
         if dec is not None:
             kw["schedule"] = "replay"
         with ctd.Solver(inst, **kw) as s:

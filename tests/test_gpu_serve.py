@@ -42,11 +42,14 @@ def uneven_2d(count, seed=11):
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("init", ["hash", "warm"])
-def test_batch_concurrent_equals_standalone(ctd, prec, init):
+@pytest.mark.parametrize("executor", ["lockstep", "streams"])
+def test_batch_concurrent_equals_standalone(ctd, prec, init, executor):
     insts = uneven_2d(6)
-    print(f"batch sizes {[i.nodes[0] for i in insts]} prec={prec} init={init}", flush=True)
+    print(f"batch sizes {[i.nodes[0] for i in insts]} prec={prec} init={init} "
+          f"executor={executor}", flush=True)
     b = ctd.Batch(insts, precision=prec, init=init)
     try:
+        b.set_mode(executor)
         b.set_workers(4)
         b.step(2)
         got = [b.modes(i) for i in range(len(insts))]
@@ -54,6 +57,67 @@ def test_batch_concurrent_equals_standalone(ctd, prec, init):
         b.close()
     for i, inst in enumerate(insts):
         assert same_modes(got[i], standalone(ctd, inst, 2, precision=prec, init=init)), f"instance {i}"
+
+
+def _with_n(inst, n, **kw):
+    """The instance's parameters on an n x n grid (its modes resampled)."""
+    t = np.arange(n, dtype=np.float64) / (n - 1)
+    src = np.arange(inst.nodes[0], dtype=np.float64) / (inst.nodes[0] - 1)
+    f = [np.ascontiguousarray(np.stack([np.interp(t, src, x[:, m]) for m in range(x.shape[1])], 1))
+         for x in inst.factors]
+    p = inst.params()
+    p.update(nodes=(n, n), **kw)
+    return Instance(amp=inst.amp.copy(), factors=f, **p)
+
+
+def test_lockstep_storage_classes_zero_and_energy(ctd):
+    """Lockstep over every storage class of the banded solve (LDS, split,
+    workspace) and both finalisation widths, with a zero initial field (its
+    first mode has zero amplitude: u^{k+1} = 0) and the energy of every step:
+    modes, step records and energies identical to the standalone solver."""
+    base = uneven_2d(4, seed=31)
+    insts = [_with_n(base[0], 40), _with_n(base[1], 700), _with_n(base[2], 2048),
+             _with_n(base[3], 2600)]
+    z = _with_n(base[1], 64)
+    z.amp = np.zeros_like(z.amp)
+    insts.append(z)
+    kw = dict(precision="fp64", energy=True)
+    print(f"lockstep classes sizes {[i.nodes[0] for i in insts]}", flush=True)
+    b = ctd.Batch(insts, **kw)
+    try:
+        b.set_mode("lockstep")
+        infos = b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        with ctd.Solver(inst, **kw) as s:
+            ref_info = s.step(2)
+            ref = s.modes()
+        assert same_modes(got[i], ref), f"instance {i}"
+        for a, r in zip(infos[i], ref_info):
+            for key in ("modes", "sweeps", "capped", "fp_unconverged", "zero_mode", "last_term_max"):
+                assert a[key] == r[key], (i, key)
+            assert a["energy"] == r["energy"] or (np.isnan(a["energy"]) and np.isnan(r["energy"]))
+    assert infos[-1][0]["zero_mode"] == 1 and infos[-1][0]["modes"] == 0
+
+
+def test_lockstep_needs_one_band_width(ctd):
+    """Instances of two patch sizes (two band widths): lockstep is refused,
+    the default executor falls back to worker streams, results unchanged."""
+    insts = uneven_2d(3, seed=41)
+    insts[1] = _with_n(insts[1], insts[1].nodes[0], patch_s=1, poly_p=1)
+    b = ctd.Batch(insts, precision="fp64")
+    try:
+        with pytest.raises(ctd.CtdError):
+            b.set_mode("lockstep")
+        b.set_mode("auto")
+        b.step(1)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        assert same_modes(got[i], standalone(ctd, inst, 1, precision="fp64")), f"instance {i}"
 
 
 def test_served_alone_equals_mix(ctd):
@@ -159,12 +223,14 @@ def _field(amp, factors):
     return np.einsum(sub, amp, *factors)
 
 
-def test_batched_instances_match_oracle(ctd):
+@pytest.mark.parametrize("executor", ["lockstep", "streams"])
+def test_batched_instances_match_oracle(ctd, executor):
     """Instances stepped inside a concurrent batch against the CPU oracle
     (FP64, adaptive on both sides: same decisions, fields to 1e-10)."""
     insts = uneven_2d(5, seed=21)
     b = ctd.Batch(insts, precision="fp64")
     try:
+        b.set_mode(executor)
         b.set_workers(3)
         b.step(2)
         got = [b.modes(i) for i in range(len(insts))]
