@@ -349,6 +349,22 @@ int ctd_kernel_band_solve(int32_t n, int32_t bw, const double* Mb,
                           const double* beta, const double* b, double* x,
                           int32_t count, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as ctd_kernel_band_solve, same arguments and results, allocating
+ * nothing.  The cyclic-reduction workspace of systems too large for LDS lives
+ * in a static device array of CTD_NOALLOC_SCRATCH_BYTES per device, held
+ * until the process ends; a call whose count x per-system workspace exceeds
+ * it returns CTD_ENOMEM and launches nothing.  Every call on one device
+ * shares that array: calls that overlap on a device (different streams or
+ * threads) race and must be serialised by the caller.  The array needs no
+ * clearing (each system writes its block data before reading them). */
+#define CTD_NOALLOC_SCRATCH_BYTES (16u << 20)
+int ctd_kernel_band_solve_noalloc(int32_t n, int32_t bw, const double* Mb,
+                                  const double* Kb, const double* alpha,
+                                  const double* beta, const double* b, double* x,
+                                  int32_t count, void* hip_stream);
+
 /* Per-kernel timing of the handle's launches with HIP events recorded on the
  * handle's stream (enable resets the counters).  For each kernel class:
  * launches, summed device time (ms), and the summed algorithmic flops and

@@ -132,6 +132,8 @@ def _load():
         "ctd_batch_destroy": (None, [vp]),
         "ctd_kernel_band_solve": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
                                             C.c_int32, vp]),
+        "ctd_kernel_band_solve_noalloc": (C.c_int, [C.c_int32, C.c_int32, vp, vp, vp, vp, vp, vp,
+                                                    C.c_int32, vp]),
         "ctd_nonlinear_load": (C.c_int, [vp, C.c_int32, P(P(C.c_double)), P(C.c_double)]),
         "ctd_kernel_copy": (C.c_int, [vp, vp, C.c_uint64, vp]),
         "ctd_axis_fast_diag": (C.c_int, [C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32,
@@ -639,3 +641,13 @@ def band_solve(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):
     if rc != CTD_OK:
         raise CtdError(rc, "ctd_kernel_band_solve")
 
+
+def band_solve_noalloc(n, bw, Mb, Kb, alpha, beta, b, x, count, stream=None):
+    """ctd_kernel_band_solve_noalloc on torch device tensors (float64): the
+    same solve with its workspace in the library's static device array."""
+    rc = LIB.ctd_kernel_band_solve_noalloc(n, bw, C.c_void_p(Mb.data_ptr()), C.c_void_p(Kb.data_ptr()),
+                                           C.c_void_p(alpha.data_ptr()), C.c_void_p(beta.data_ptr()),
+                                           C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), count,
+                                           stream if stream is not None else current_stream())
+    if rc != CTD_OK:
+        raise CtdError(rc, "ctd_kernel_band_solve_noalloc")
