@@ -389,6 +389,10 @@ enum {
                           reduction kernel otherwise)                     */
   CTD_K_FULL_SOLVE,    /* full CFE step of actd: dense products in the
                           eigenbases (2D, FP64 MFMA)                      */
+  CTD_K_SKIPPED,       /* launches of a sweep enqueued ahead of the host's
+                          decision, after which the mode had ended: they
+                          returned at once (any class; timed when the
+                          class of the launch is selected)                */
   CTD_K_COUNT
 };
 int ctd_profile_enable(ctd_solver* s, int32_t on);

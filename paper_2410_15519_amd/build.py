@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import os
+import re
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -28,14 +29,49 @@ def _hipcc():
     return "hipcc"
 
 
+# the compiler's per-kernel resource report (registers, scratch, LDS,
+# occupancy), taken from the same compile and kept beside the library
+RESOURCE_FLAG = "-Rpass-analysis=kernel-resource-usage"
+RESOURCE_REPORT = os.path.join(HERE, "_build", "kernel_resources.txt")
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     cmd = [_hipcc(), *COMMON]
+    if src.endswith(".hip"):
+        cmd += [RESOURCE_FLAG]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     return src, obj, r.returncode, r.stdout + r.stderr
+
+
+def kernel_resources(text: str) -> dict:
+    """Per-kernel fields of the compiler's resource remarks:
+    {mangled name: {"VGPRs": .., "ScratchSize [bytes/lane]": .., ...}}."""
+    out, cur = {}, None
+    for line in text.splitlines():
+        m = re.search(r"remark:\s+(.*?)\s*\[-Rpass-analysis=kernel-resource-usage\]", line)
+        if not m:
+            continue
+        field = m.group(1)
+        if field.startswith("Function Name:"):
+            cur = field.split(":", 1)[1].strip()
+            out[cur] = {}
+        elif cur is not None and ":" in field:
+            k, v = field.rsplit(":", 1)
+            out[cur][k.strip()] = v.strip()
+    return out
+
+
+def _remarks_only(out: str) -> str:
+    keep = []
+    for l in out.splitlines():
+        if "packed-fp32-ops" in l or "kernel-resource-usage" in l:
+            continue
+        keep.append(l)
+    return "\n".join(keep)
 
 
 def build(verbose: bool = False) -> str:
@@ -45,11 +81,22 @@ def build(verbose: bool = False) -> str:
     failed = [r for r in results if r[2] != 0]
     for src, _, rc, out in results:
         if verbose or rc != 0:
-            msg = "\n".join(l for l in out.splitlines() if "packed-fp32-ops" not in l)
+            msg = _remarks_only(out)
             if msg.strip():
                 print(f"[{src}]\n{msg}", file=sys.stderr)
     if failed:
         raise RuntimeError("HIP compile failed: " + ", ".join(f[0] for f in failed))
+    # no kernel may use scratch memory: a copy of a by-value argument, a
+    # register spill or an outlined call shows up there first
+    res = {}
+    for src, _, _, out in results:
+        res.update(kernel_resources(out))
+    with open(RESOURCE_REPORT, "w") as f:
+        for name in sorted(res):
+            f.write(name + "\t" + "\t".join(f"{k}={v}" for k, v in res[name].items()) + "\n")
+    scratch = sorted(n for n, r in res.items() if r.get("ScratchSize [bytes/lane]", "0") != "0")
+    if scratch:
+        raise RuntimeError("kernels using scratch memory: " + ", ".join(scratch))
     tmp = LIB + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp,
            *[r[1] for r in results]]

@@ -87,7 +87,7 @@ struct DevScalars {
   int32_t nonfinite;
   int32_t nmodes;
   int32_t stop;            // 1 tol, 2 cap
-  int32_t pad;
+  int32_t done;            // the mode's last sweep has run (set when DevInst::spec_nsw > 0)
 };
 
 // Everything a kernel may need about one instance, passed by value.
@@ -99,6 +99,12 @@ struct DevInst {
   int ntri;          // tile triples A <= B <= C
   int Mcap;          // capacity of factor matrices
   int mixed;
+  // speculative sweeps: with spec_nsw > 0 the finalisation of the last
+  // direction sets sc->done when the sweep ends the mode (zero amplitude,
+  // non-finite, converged, or sweep spec_nsw); a launch with spec_check set
+  // returns at once when sc->done is set
+  int spec_nsw;
+  int spec_check;
   double c, lam, omega, a0, kappa;
   double fp_tol, enrich_tol;
   int max_modes;

@@ -34,6 +34,12 @@ template <class T> __device__ __forceinline__ int mfma_row(int l, int k);
 template <> __device__ __forceinline__ int mfma_row<float>(int l, int k) { return (l >> 4) * 4 + k; }
 template <> __device__ __forceinline__ int mfma_row<double>(int l, int k) { return (l >> 4) + 4 * k; }
 
+// A speculatively enqueued sweep launch whose mode already ended: return at
+// once (the flag was written by an earlier launch on the same stream).
+__device__ __forceinline__ bool spec_skip(const DevInst& I) {
+  return I.spec_check && I.sc->done;
+}
+
 __device__ __forceinline__ int elem_start(int e, int s, int n, int SW) {
   int st = e - s;
   st = st < 0 ? 0 : st;
@@ -269,9 +275,9 @@ __device__ __forceinline__ double band_row_apply(const BandRow<B>& r, int n, con
 // the sums of the unnormalised u are rescaled by 1/sigma afterwards.
 // red: >= 96 doubles of LDS; ul: 3n doubles of scratch (LDS) for u, M u, K u.
 template <int B>
-__device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, double* red, double* ul,
+__device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep, int from_init, double* red, double* ul,
                               int nparts = 0) {
-  DevAxis& A = I.ax[d];
+  const DevAxis& A = I.ax[d];
   DevScalars* sc = I.sc;
   const int n = A.n;
   double* ml = ul + n;
@@ -367,6 +373,7 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
       if (bad) sc->nonfinite = 1;
       if (zero) sc->zero = 1;
       if (d == I.dim - 1) {
+        int conv = 0;
         if (sweep >= 2) {
           // products over the directions, in direction order (this one last)
           const double puu = puu_o * uu, pupup = pupup_o * upup, puup = puup_o * uup;
@@ -377,9 +384,13 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
           r2 = r2 > 0.0 ? r2 : 0.0;
           double r = nn > 0.0 ? sqrt(r2 / nn) : 0.0;
           sc->change = r;
-          sc->converged = r <= I.fp_tol ? 1 : 0;
+          conv = r <= I.fp_tol ? 1 : 0;
+          sc->converged = conv;
         }
         sc->sigma_prev = sigma;
+        // the host's end-of-mode test, for the speculatively enqueued next sweep
+        if (I.spec_nsw > 0)
+          sc->done = (sc->zero || sc->nonfinite || conv || sweep >= I.spec_nsw) ? 1 : 0;
       }
     }
   }
@@ -387,6 +398,7 @@ __device__ void finalize_body(DevInst& I, int d, int sweep, int from_init, doubl
 
 template <int B>
 __global__ __launch_bounds__(1024) void k_finalize(DevInst I, int d, int sweep, int from_init, int nparts) {
+  if (spec_skip(I)) return;
   __shared__ double red[96];
   extern __shared__ double ul[];
   // d < 0: every direction at once, one workgroup each (the initial guesses)
@@ -463,6 +475,7 @@ __device__ __forceinline__ void signature_body(const DevInst& I, int d, int M, i
 }
 
 __global__ void k_signature(DevInst I, int d, int M, int ndot_blocks, int want_v) {
+  if (spec_skip(I)) return;
   signature_body(I, d, M, ndot_blocks, want_v, blockIdx.x, blockIdx.y);
 }
 
@@ -514,14 +527,20 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
   const int r0 = bx * 64, i = r0 + l;
   if (y < nchunk) {
     const int ctot = rhs_columns(I, M, load_only);
-    // 16 columns per wave, loaded before the coefficients are ready
+    // 16 columns per wave, loaded before the coefficients are ready.  The
+    // column bases are read into registers first: choosing between fields
+    // of the by-value instance by address would make the compiler copy the
+    // whole instance to scratch memory.
+    const double* const MXk = A.MXk;
+    const double* const MX = A.MX;
+    const double* const KX = A.KX;
     double cv[16];
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
       const int c = y * 64 + w * 16 + cc;
-      const double* col = c < I.Mk ? A.MXk + (size_t)c * n
-                                   : (c < I.Mk + M ? A.MX + (size_t)(c - I.Mk) * n
-                                                   : A.KX + (size_t)(c - I.Mk - M) * n);
+      const double* col = c < I.Mk ? MXk + (size_t)c * n
+                                   : (c < I.Mk + M ? MX + (size_t)(c - I.Mk) * n
+                                                   : KX + (size_t)(c - I.Mk - M) * n);
       cv[cc] = (c < ctot && i < n) ? col[i] : 0.0;
     }
     const double ck = load_only ? -I.omega : (I.dim == 3 ? I.c + I.omega : I.c);
@@ -563,7 +582,9 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
     // the coefficients -u_e[j] (+u_e[j] for the load alone)
     const int o = 1 - d, nco = I.ax[o].n;
     const int j0 = (y - nchunk) * 64;
-    const void* base = d == 0 ? I.MxyT : I.Mxy;
+    const void* const mxyt = I.MxyT;
+    const void* const mxy = I.Mxy;
+    const void* base = d == 0 ? mxyt : mxy;
     double cv[16];
 #pragma unroll
     for (int cc = 0; cc < 16; ++cc) {
@@ -639,6 +660,7 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
 }
 
 __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
+  if (spec_skip(I)) return;
   rhs_body(I, d, M, load_only, nchunk, blockIdx.x, blockIdx.y);
 }
 
@@ -1094,6 +1116,7 @@ __device__ __forceinline__ void directional_coeffs(const DevInst& I, int d, doub
 // so that LDS data keep LDS addressing)
 template <int B, int MODE>
 __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr(DevInst I, int d, int sweep, int nchunk, double* gws) {
+  if (spec_skip(I)) return;
   extern __shared__ double lds[];
   BcrMem<B, MODE> mem{MODE == 1 ? gws : lds, MODE == 2 ? gws : nullptr};
   double* sm = MODE == 1 ? gws : lds;
@@ -1195,6 +1218,7 @@ hipError_t launch_band_solve_batch(int n, int bw, const double* Mb,
 // row range is summed from its partials into LDS first (same order as the
 // cyclic reduction takes them); eight rows' loads are in flight per thread.
 __global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk) {
+  if (spec_skip(I)) return;
   const DevAxis& A = I.ax[d];
   const int n = A.n;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1252,6 +1276,7 @@ __global__ __launch_bounds__(256) void k_fd_project(DevInst I, int d, int nchunk
 // along k, all loads of a lane issued together); the finalize pass adds the
 // kFdKb partials in fixed order.
 __global__ __launch_bounds__(256) void k_fd_apply(DevInst I, int d) {
+  if (spec_skip(I)) return;
   DevAxis& A = I.ax[d];
   const int n = A.n;
   const int K = (n + kFdKb - 1) / kFdKb;
@@ -1389,6 +1414,7 @@ hipError_t launch_append(const DevInst& I, int M, hipStream_t st) {
 
 __global__ void k_reset_scalars(DevScalars* sc) {
   if (threadIdx.x == 0) {
+    sc->done = 0;
     sc->converged = 0;
     sc->zero = 0;
     sc->nonfinite = 0;
@@ -1428,6 +1454,7 @@ constexpr int kGChunk = 64;
 // workgroup writes its split partial.
 template <class T>
 __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst I, int d) {
+  if (spec_skip(I)) return;
   typedef typename Vec4<T>::type V;
   constexpr int TS = kTileSq * kTile;
   constexpr int WPS = (int)sizeof(T);               // 16-byte words per 16-wide row segment
@@ -1556,6 +1583,7 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
 // triples run about 16/9 as many points per split (more points, fewer
 // splits), so all workgroups carry about the same work.
 __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
+  if (spec_skip(I)) return;
   constexpr int TS = kTileSq * kTile;
   constexpr int PS9 = 9 * kTileSq;                  // outputs of a repeated-tile triple
   constexpr int RW = 12;                            // 16-byte words per Gauss point (3 segments)
@@ -1707,6 +1735,7 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
 // block k, row f; else block 16 - k, row s), and pairs with f > s are zero.
 // g_d is kept in the class layout (only the elements read here are written).
 __global__ __launch_bounds__(256) void k_cubic_gred32(DevInst I, int d, int e_other) {
+  if (spec_skip(I)) return;
   constexpr int TS = kTileSq * kTile;
   constexpr int PS9 = 9 * kTileSq;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1767,6 +1796,7 @@ __global__ __launch_bounds__(256) void k_cubic_gred32(DevInst I, int d, int e_ot
 // the extra launch.
 template <class T>
 __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_other) {
+  if (spec_skip(I)) return;
   const size_t per = (size_t)kTileSq * kTile;
   const size_t total = (size_t)I.ntri * per;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1831,6 +1861,7 @@ constexpr int kHQ = 64 * kHRows;       // Gauss points per workgroup
 
 template <int HR>
 __global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
+  if (spec_skip(I)) return;
   extern __shared__ unsigned char smraw[];
   constexpr int TW = kTileSq * kTile / 4;   // 16-byte words per S tile
   const DevAxis& A = I.ax[d];
@@ -1967,6 +1998,7 @@ __host__ __device__ constexpr int h_lds_stride(int ldh) { return ldh + 16 / (int
 
 template <class T>
 __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
+  if (spec_skip(I)) return;
   typedef typename Vec4<T>::type V;
   constexpr int TS = kTileSq * kTile;                 // elements per S tile
   constexpr int NV = TS * (int)sizeof(T) / 16 / 256;  // 16-byte words per thread
@@ -2585,9 +2617,10 @@ hipError_t launch_reconstruct(const DevInst& I, int M, void* out, int dtype,
 // and sizes).  blockIdx.z selects the group entry (LsArg); the grid covers
 // the largest instance of the group and the blocks an instance does not need
 // return at once.  Each instance's arithmetic is that of its own launches.
-__global__ void k_reset_scalars_m(DevInst* insts, const LsArg* args) {
+__global__ void k_reset_scalars_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args) {
   DevScalars* sc = insts[args[blockIdx.z].inst].sc;
   if (threadIdx.x == 0) {
+    sc->done = 0;
     sc->converged = 0;
     sc->zero = 0;
     sc->nonfinite = 0;
@@ -2596,13 +2629,13 @@ __global__ void k_reset_scalars_m(DevInst* insts, const LsArg* args) {
   }
 }
 
-__global__ void k_append_m(DevInst* insts, const LsArg* args) {
+__global__ void k_append_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args) {
   const LsArg& a = args[blockIdx.z];
   if (!a.flag) return;
   append_body(insts[a.inst], a.M - 1);
 }
 
-__global__ void k_init_mode_m(DevInst* insts, const LsArg* args) {
+__global__ void k_init_mode_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args) {
   const LsArg& a = args[blockIdx.z];
   const DevInst& I = insts[a.inst];
   const int d = blockIdx.y;
@@ -2611,15 +2644,15 @@ __global__ void k_init_mode_m(DevInst* insts, const LsArg* args) {
 }
 
 template <int B>
-__global__ __launch_bounds__(1024) void k_finalize_init_m(DevInst* insts, const LsArg* args) {
+__global__ __launch_bounds__(1024) void k_finalize_init_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args) {
   __shared__ double red[96];
   extern __shared__ double ul[];
-  DevInst& I = insts[args[blockIdx.z].inst];
+  const DevInst& I = insts[args[blockIdx.z].inst];
   finalize_body<B>(I, (int)blockIdx.x, 0, 1, red, ul, 0);
 }
 
 // d < 0: every direction (the initial guesses), direction blockIdx.y
-__global__ void k_signature_m(DevInst* insts, const LsArg* args, int d, int need_flag) {
+__global__ void k_signature_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args, int d, int need_flag) {
   const LsArg& a = args[blockIdx.z];
   if (need_flag && !a.flag) return;
   const DevInst& I = insts[a.inst];
@@ -2628,7 +2661,7 @@ __global__ void k_signature_m(DevInst* insts, const LsArg* args, int d, int need
   signature_body(I, d, a.M, ndot, 0, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void k_rhs_m(DevInst* insts, const LsArg* args, int d) {
+__global__ __launch_bounds__(256) void k_rhs_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args, int d) {
   const LsArg& a = args[blockIdx.z];
   const DevInst& I = insts[a.inst];
   if ((int)blockIdx.x * 64 >= I.ax[d].n || (int)blockIdx.y >= a.nlin + a.nld[d]) return;
@@ -2636,16 +2669,16 @@ __global__ __launch_bounds__(256) void k_rhs_m(DevInst* insts, const LsArg* args
 }
 
 template <int B, int MODE>
-__global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr_m(DevInst* insts, const LsArg* args, int d) {
+__global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args, int d) {
   extern __shared__ double lds[];
   const LsArg& a = args[blockIdx.z];
-  DevInst& I = insts[a.inst];
+  const DevInst& I = insts[a.inst];
   double* gws = MODE == 0 ? nullptr : I.bcr_ws;
   BcrMem<B, MODE> mem{MODE == 1 ? gws : lds, MODE == 2 ? gws : nullptr};
   double* sm = MODE == 1 ? gws : lds;
   __shared__ double red[96];
   __shared__ double ab[2];
-  DevAxis& A = I.ax[d];
+  const DevAxis& A = I.ax[d];
   if (threadIdx.x == 0) {
     directional_coeffs(I, d, ab[0], ab[1]);
     I.sc->alpha[d] = ab[0];
@@ -2656,7 +2689,7 @@ __global__ __launch_bounds__(64 * bcr_max_waves(B)) void k_solve_bcr_m(DevInst* 
   finalize_body<B>(I, d, a.sweep, 0, red, sm);
 }
 
-__global__ void k_gather_scalars_m(DevInst* insts, const LsArg* args, DevScalars* out) {
+__global__ void k_gather_scalars_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args, DevScalars* out) {
   const LsArg& a = args[blockIdx.z];
   const int* src = (const int*)insts[a.inst].sc;
   int* dst = (int*)(out + blockIdx.z);

@@ -86,10 +86,11 @@ struct DeviceArena {
 struct Profiler {
   bool on = false;
   uint32_t mask = ~0u;   // kernel classes bracketed with events
-  struct Pending { int id; int ev; double flops, bytes; };
+  struct Pending { int id; int ev; double flops, bytes; int64_t tag; };
   std::vector<hipEvent_t> pool;
   std::vector<Pending> pending;
   int used = 0;
+  int64_t tag = 0;       // launches of a speculative sweep carry its serial number
   int64_t launches[CTD_K_COUNT] = {};
   double ms[CTD_K_COUNT] = {}, flops[CTD_K_COUNT] = {}, bytes[CTD_K_COUNT] = {};
   hipError_t event_pair(int& idx) {
@@ -118,6 +119,12 @@ struct Profiler {
     used = 0;
     return hipSuccess;
   }
+  // a speculative sweep whose mode had ended: its launches returned at once
+  // on the device and are booked apart from the kernels' own classes
+  void skipped(int64_t t) {
+    for (auto it = pending.rbegin(); it != pending.rend() && it->tag >= t; ++it)
+      if (it->tag == t) it->id = CTD_K_SKIPPED;
+  }
   void reset() {
     pending.clear();
     used = 0;
@@ -144,7 +151,9 @@ struct ctd_solver {
   AxisTables ax[kMaxDim];
   DeviceArena arena;
   DevInst I{};
-  DevScalars* sc_host = nullptr;   // pinned
+  DevScalars* sc_host = nullptr;   // pinned, two slots (slot 0: the last scalars read)
+  hipEvent_t sc_ev[2] = {};        // completion of the scalar copy into each slot
+  int64_t spec_serial = 0;         // tag of the launches of speculative sweeps (profiling)
   double* KXk[kMaxDim] = {};       // K X^k (energy of u^k)
   int Mk = 0, Mcap = 0, Mkp_max = 0, ntri_max = 0;
   int Mcap_ctd = 0;                // modes of a CTD state (max_modes, initial count)
@@ -189,7 +198,7 @@ struct ctd_solver {
       HIPCHK(s, hipEventRecord((s)->prof.pool[_ev], (st)));                  \
       HIPCHK(s, expr);                                                       \
       HIPCHK(s, hipEventRecord((s)->prof.pool[_ev + 1], (st)));              \
-      (s)->prof.pending.push_back({(id), _ev, (double)(fl), (double)(by)});  \
+      (s)->prof.pending.push_back({(id), _ev, (double)(fl), (double)(by), (s)->prof.tag}); \
     } else {                                                                 \
       HIPCHK(s, expr);                                                       \
     }                                                                        \
@@ -668,7 +677,10 @@ int alloc_instance(ctd_solver* s, int m0) {
     if (ws) AL(I.bcr_ws, ws);
   }
 #undef AL
-  if (!A.dry) HIPCHK(s, hipHostMalloc((void**)&s->sc_host, sizeof(DevScalars), hipHostMallocDefault));
+  if (!A.dry) {
+    HIPCHK(s, hipHostMalloc((void**)&s->sc_host, 2 * sizeof(DevScalars), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k) HIPCHK(s, hipEventCreateWithFlags(&s->sc_ev[k], hipEventDisableTiming));
+  }
   return CTD_OK;
 }
 
@@ -883,9 +895,9 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     }
     const int nsw = adaptive ? std::max(1, s->P.fp_max_iter) : replay[mode];
     if (nsw < 1) return s->fail(CTD_EINVAL, "replayed sweep count must be >= 1");
-    int it = 0;
-    bool conv = false;
-    for (it = 1; it <= nsw; ++it) {
+    // one sweep: every direction's load, right-hand side and solve, and the
+    // Grams of every direction but the last
+    auto sweep = [&](int it) -> int {
       for (int d = 0; d < D; ++d) {
         if (D == 3) {
           Work w = w_cubic(s, d);
@@ -915,27 +927,67 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
           if (rc) return rc;
         }
       }
+      return CTD_OK;
+    };
+    // the start of a further sweep: the last direction's Grams
+    auto carry = [&]() -> int {
+      Work w = w_sig(s, D - 1, M);
+      LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
+      return cubic_after(s, D - 1, 0);
+    };
+    // Adaptive: sweep it + 1 is enqueued before the host waits for the
+    // scalars of sweep it, its launches marked to return at once on the
+    // device if sweep it ended the mode (the finalisation of the last
+    // direction records that, with the host's own test), so the device keeps
+    // working while the host reads and decides.  The decisions and the
+    // arithmetic of every sweep that runs are those of the plain sequence.
+    s->I.spec_nsw = adaptive ? nsw : 0;
+    int it = 0;
+    bool conv = false;
+    bool queued = false;   // sweep it was enqueued speculatively
+    int rc = CTD_OK;
+    for (it = 1; it <= nsw; ++it) {
+      if (!queued && (rc = sweep(it))) break;
+      queued = false;
       bool last = it == nsw;
       if (adaptive) {
-        int rc = read_scalars(s);
-        if (rc) return rc;
+        DevScalars* slot = s->sc_host + (it & 1);
+        HIPCHK(s, hipMemcpyAsync(slot, s->I.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(s, hipEventRecord(s->sc_ev[it & 1], s->stream));
+        if (it < nsw) {
+          s->I.spec_check = 1;
+          s->prof.tag = ++s->spec_serial;
+          rc = carry();
+          if (rc == CTD_OK) rc = sweep(it + 1);
+          s->I.spec_check = 0;
+          s->prof.tag = 0;
+          if (rc) break;
+          queued = true;
+        }
+        HIPCHK(s, hipEventSynchronize(s->sc_ev[it & 1]));
+        if (slot != s->sc_host) s->sc_host[0] = *slot;
         // a zero amplitude ends the mode (Sec. 3.3 stopping) before the
         // non-finite test: the directions solved after it in the same sweep
         // see zero fixed factors and produce NaN for a mode that is dropped
-        if (s->sc_host->zero) { zero = 1; break; }
-        if (s->sc_host->nonfinite) return s->fail(CTD_ENONFINITE, "non-finite mode amplitude");
+        if (s->sc_host->zero) {
+          zero = 1;
+          if (queued) s->prof.skipped(s->spec_serial);
+          break;
+        }
+        if (s->sc_host->nonfinite) { rc = s->fail(CTD_ENONFINITE, "non-finite mode amplitude"); break; }
         conv = s->sc_host->converged != 0 && it >= 2;
         if (conv) last = true;
       }
-      if (!last) {
-        Work w = w_sig(s, D - 1, M);
-        LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
-        int rc = cubic_after(s, D - 1, 0);
-        if (rc) return rc;
-      } else {
+      if (last) {
+        if (queued) s->prof.skipped(s->spec_serial);
         break;
       }
+      if (!queued && (rc = carry())) break;
     }
+    s->I.spec_nsw = 0;
+    s->I.spec_check = 0;
+    s->prof.tag = 0;
+    if (rc) return rc;
     if (zero) break;
     if (it > nsw) it = nsw;
     sweeps += it;
@@ -1369,7 +1421,15 @@ int ctd_init(const ctd_problem* p, int32_t m0, const double* const* init,
   rc = setup_host(s, p, hip_stream, err);
   if (rc) { g_init_error = err; delete s; return rc; }
   rc = alloc_instance(s, m0);
-  if (rc) { g_init_error = s->err; s->arena.release(); if (s->sc_host) (void)hipHostFree(s->sc_host); delete s; return rc; }
+  if (rc) {
+    g_init_error = s->err;
+    s->arena.release();
+    if (s->sc_host) (void)hipHostFree(s->sc_host);
+    for (hipEvent_t e : s->sc_ev)
+      if (e) (void)hipEventDestroy(e);
+    delete s;
+    return rc;
+  }
   // initial modes: fold amplitude signs into axis 0, |amp| into sk
   std::vector<double> sk(m0);
   std::vector<double> col;
@@ -1555,6 +1615,8 @@ void ctd_destroy(ctd_solver* s) {
   s->arena.release();
   s->prof.release();
   if (s->sc_host) (void)hipHostFree(s->sc_host);
+  for (hipEvent_t e : s->sc_ev)
+    if (e) (void)hipEventDestroy(e);
   delete s;
 }
 

@@ -26,7 +26,7 @@ DTYPE = {"f64": 0, "f32": 1}
 SOLVE = {"auto": 0, "bcr": 1, "fd": 2}
 BATCH_MODE = {"auto": 0, "lockstep": 1, "streams": 2}
 KERNELS = ["cubic_g", "cubic_gred", "cubic_h", "rhs", "solve", "signature", "gemv",
-           "mxy_build", "energy", "quad_eval", "other", "finalize", "full_solve"]
+           "mxy_build", "energy", "quad_eval", "other", "finalize", "full_solve", "skipped"]
 
 
 class CtdError(RuntimeError):
