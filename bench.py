@@ -61,8 +61,8 @@ PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
 # HBM traffic per launch measured with rocprofv3 counters on this workload
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ctd_step_ac3d_n1024_mixed_hbm_traffic.md")
 # kernel [grid work-items] of each class at the timed shape (M_k = 128)
-KERNEL_NAMES = {"cubic_g": "k_cubic_g<float> [245760]", "cubic_h": "k_cubic_h32 [245760]",
-                "cubic_gred": "k_cubic_gred<float> [491520]", "finalize": "k_finalize<5> [1024]"}
+KERNEL_NAMES = {"cubic_g": "k_cubic_g32 [196608]", "cubic_h": "k_cubic_h32<1> [245760]",
+                "cubic_gred": "k_cubic_gred32 [491520]", "finalize": "k_finalize<5> [1024]"}
 
 
 def log(*a):
@@ -476,18 +476,26 @@ def served_leg(ctd, count=32, step_scale=20, workers=8, init="warm"):
                        f"divided by {step_scale}")}
 
 
-def _serve_stream(ctd, reqs, rate_scale, workers, init):
+def _serve_stream(ctd, reqs, rate_scale, workers, init, lockstep=True):
     """Submit (arrival time / rate_scale, instance) pairs on their arrival
-    times, wait for all; returns per-request statuses, server stats and the
-    wall time of the run."""
-    srv = ctd.Server(workers=workers)
+    times, wait for all (a progress line every 10 s); returns per-request
+    statuses, server stats and the wall time of the run."""
+    srv = ctd.Server(workers=workers, lockstep=lockstep)
     t0 = time.perf_counter()
     tickets = []
-    for t_arr, inst in reqs:
-        dt = t_arr / rate_scale - (time.perf_counter() - t0)
-        if dt > 0:
-            time.sleep(dt)
-        tickets.append(srv.submit(inst, precision="mixed", init=init))
+    last = t0
+    pending = list(reqs)
+    while pending or tickets and srv.stats()["completed"] + srv.stats()["failed"] < len(reqs):
+        now = time.perf_counter()
+        while pending and pending[0][0] / rate_scale <= now - t0:
+            tickets.append(srv.submit(pending.pop(0)[1], precision="mixed", init=init))
+        if now - last >= 10.0:
+            st = srv.stats()
+            log(f"    [serve] {now - t0:.0f} s: submitted {st['submitted']}, done {st['completed']}, "
+                f"running {st['running']}, queued {st['queued']}, steps {st['steps_done']}")
+            last = now
+        nxt = pending[0][0] / rate_scale - (time.perf_counter() - t0) if pending else 0.05
+        time.sleep(min(max(nxt, 0.0005), 0.05))
     for t in tickets:
         srv.wait(t)
     wall = time.perf_counter() - t0
@@ -499,35 +507,40 @@ def _serve_stream(ctd, reqs, rate_scale, workers, init):
     return st, stats, wall
 
 
-def served_load_leg(ctd, count=64, workers=8, init="warm"):
+def served_load_leg(ctd, count=64, workers=8, init="warm", lockstep=True, count70=32):
     """The served workload as generated (Poisson arrivals at 200 req/s, 20 %
     3D with 64-512 nodes per axis, 2D with 64-2048, 20-500 steps per
     request; parameters as the batched workload), its first `count`
     requests: capacity (steps and requests completed per second of busy
     time), p50/p99 latency from arrival to completion at the offered 200
-    req/s (the queue grows: the offered load is above capacity), then the same
-    requests offered at 70 % of the measured request capacity."""
+    req/s (the queue grows: the offered load is above capacity), then the
+    first `count70` requests offered at 70 % of the measured request
+    capacity."""
     import numpy as np
     from workloads import make_requests, CONFIGS
     cfg = CONFIGS["serve_mix"]
     reqs = make_requests(count=count)
     out = {"requests": count, "workers": workers, "offered_rate_per_s": cfg["rate"],
+           "lockstep_route": bool(lockstep),
            "steps_total": int(sum(i.steps for _, i in reqs)),
            "p3d": float(np.mean([i.dim == 3 for _, i in reqs]))}
     runs = []
     for label, scale in (("offered", 1.0), ("70pct", None)):
+        sub = reqs
         if scale is None:
             cap = runs[0]["requests_per_s_capacity"]
             scale = cfg["rate"] / (0.7 * cap)        # stretch the arrival times
+            sub = reqs[:count70]
         # arrival times are divided by rate_scale: 1 = as generated, 1/scale = stretched
-        st, stats, wall = _serve_stream(ctd, reqs, 1.0 / scale, workers, init)
+        st, stats, wall = _serve_stream(ctd, sub, 1.0 / scale, workers, init, lockstep)
         lat = np.array([x["t_done_ms"] - x["t_submit_ms"] for x in st])
         wait = np.array([x["t_start_ms"] - x["t_submit_ms"] for x in st])
         steps = sum(x["steps_done"] for x in st)
         busy_s = stats["busy_ms"] / 1e3
-        r = {"label": label, "offered_rate_per_s": cfg["rate"] / scale if label != "offered" else cfg["rate"],
+        r = {"label": label, "requests": len(sub),
+             "offered_rate_per_s": cfg["rate"] / scale if label != "offered" else cfg["rate"],
              "wall_s": wall, "busy_s": busy_s, "steps_done": int(steps),
-             "steps_per_s_capacity": steps / busy_s, "requests_per_s_capacity": count / busy_s,
+             "steps_per_s_capacity": steps / busy_s, "requests_per_s_capacity": len(sub) / busy_s,
              "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
              "queue_wait_ms_p50": float(np.percentile(wait, 50)), "queue_wait_ms_p99": float(np.percentile(wait, 99)),
              "failed": int(stats["failed"])}
@@ -561,6 +574,8 @@ def main():
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--requests", type=int, default=64,
                     help="requests of the served workload for --only served_load")
+    ap.add_argument("--no-lockstep", action="store_true",
+                    help="served workload: every request on the worker-stream route")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
                     help="first run the plain copy kernel on MIB MiB (scale for traffic counters)")
     args = ap.parse_args()
@@ -590,7 +605,8 @@ def main():
                 "served": lambda c: served_leg(c, init=args.init),
                 "ps": lambda c: ps_sweep_leg(c, init=args.init),
                 "ac2d": lambda c: ac2d_leg(c), "ac3d_n256": lambda c: ac3d_n256_leg(c),
-                "served_load": lambda c: served_load_leg(c, count=args.requests, init=args.init)}
+                "served_load": lambda c: served_load_leg(c, count=args.requests, init=args.init,
+                                                          lockstep=not args.no_lockstep)}
         print(json.dumps({args.only: legs[args.only](ctd)}))
         return
     inst = make_instance(args.workload)

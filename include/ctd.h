@@ -263,14 +263,20 @@ void ctd_batch_destroy(ctd_batch* b);
 
 /* ---------------------------------------------------------------------- *
  * Served execution with continuous batching.  Requests (a problem, its
- * initial modes and a step count) are queued in arrival order; worker
- * threads, each with its own non-blocking HIP stream, admit the oldest
- * request as soon as a worker is idle and the summed device footprint of
- * the admitted-but-unfetched requests plus its own stays within the HBM
- * budget, so requests that arrive while others run are started as slots and
- * memory free up and their work overlaps on the device.  Results (the
- * modes) stay device-resident until fetched.  A request's arithmetic is that
- * of a single ctd_solver on its own stream: the same alone and in any mix.
+ * initial modes and a step count) are queued in arrival order, by route.
+ * 2D adaptive requests with cyclic-reduction solves (the 2D default) run in
+ * lockstep: a server thread admits each as soon as the summed device
+ * footprint of the admitted-but-unfetched requests plus its own stays
+ * within the HBM budget, adds it to the running set at its first step, and
+ * advances the whole set in rounds of multi-instance launches (see
+ * ctd_batch_set_mode); a request leaves the set when its steps are done.
+ * Other requests go to worker threads, each with its own non-blocking HIP
+ * stream, which admit the oldest one as soon as a worker is idle and its
+ * footprint fits.  Requests that arrive while others run thus start as
+ * memory (and workers) free up, and their work overlaps on the device.
+ * Results (the modes) stay device-resident until fetched.  A request's
+ * arithmetic is that of a single ctd_solver: the same alone, in any mix and
+ * on either route.
  * ---------------------------------------------------------------------- */
 typedef struct ctd_server ctd_server;
 
@@ -317,9 +323,12 @@ int ctd_server_fetch(ctd_server* srv, int64_t ticket, int32_t* m, double* amp,
                      double* const* out, int32_t cap, int32_t release);
 int ctd_server_get_stats(ctd_server* srv, ctd_server_stats* st);
 const char* ctd_server_last_error(const ctd_server* srv);   /* never NULL */
-/* Stops admitting, lets running requests finish their current step, frees
- * everything.  NULL-safe. */
+/* Stops admitting, lets running requests finish their current step (or
+ * lockstep round), frees everything.  NULL-safe. */
 void ctd_server_destroy(ctd_server* srv);
+/* on = 0: later submissions all take the worker route (default 1: eligible
+ * 2D requests run in lockstep).  Results do not depend on the route. */
+int ctd_server_set_lockstep(ctd_server* srv, int32_t on);
 
 /* ---------------------------------------------------------------------- *
  * Low-level kernel entry points on caller device memory (tests, tuning).

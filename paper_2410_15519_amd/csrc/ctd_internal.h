@@ -270,6 +270,29 @@ void bcr_launch_class(int n, int B, int& mode, int& threads, size_t& shm);
 // solves, one band width; results equal the instances' own ctd_step.
 bool lockstep_eligible(const ctd_solver* s);
 int band_halfwidth(const ctd_solver* s);
+// The engine behind it: instances join (add) between rounds and leave when
+// their steps are done; one round is one sweep of every instance in a mode
+// (with the initialisation of those starting one) and one read-back.
+class Lockstep {
+ public:
+  explicit Lockstep(hipStream_t st);
+  ~Lockstep();
+  Lockstep(const Lockstep&) = delete;
+  Lockstep& operator=(const Lockstep&) = delete;
+  // the instance runs `nsteps` steps from its next one, on the engine's stream
+  int add(ctd_solver* s, int nsteps, int* slot, std::string& err);
+  // one round: `steps` gets (slot, record) of every step that ended in it,
+  // `finished` the slots whose steps are all done (they leave the engine).
+  // An instance that fails (non-finite amplitude) leaves the engine with its
+  // (slot, error) in `failed` when given, else the round returns the error.
+  int round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vector<int>& finished,
+            std::string& err, std::vector<std::pair<int, int>>* failed = nullptr);
+  bool empty() const;
+  int band() const;   // band half-width of the instances (0 before the first)
+ private:
+  struct Impl;
+  Impl* p;
+};
 int lockstep_steps(std::vector<ctd_solver*>& S, int nsteps, ctd_step_info* info, hipStream_t st,
                    std::string& err);
 

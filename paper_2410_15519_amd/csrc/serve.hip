@@ -1,12 +1,18 @@
 // Served execution with continuous batching.
 //
-// Requests wait in arrival order.  A pool of worker threads, each owning a
-// non-blocking HIP stream, admits the oldest request whenever a worker is
-// idle and the device bytes of the admitted-but-unfetched requests plus its
-// own footprint (the exact allocation ctd_init will make) stay within the
-// budget; the worker then sets the instance up and steps it on its stream.
-// Requests arriving while others run are thus started as soon as a slot and
-// memory are free, and the kernels of all running requests overlap on the
+// Requests wait in arrival order, in one of two queues by route.  2D
+// requests whose steps can run in lockstep (adaptive, cyclic-reduction
+// solves) go to the lockstep thread: it admits them as soon as their
+// footprint fits the budget, sets each up on its own stream and adds it to
+// a lockstep engine (one per band width), and runs rounds of multi-instance
+// launches over every admitted request; a request joins at its first step
+// and leaves when its steps are done.  The other requests (3D, and 2D ones
+// that do not qualify) go to a pool of worker threads, each owning a
+// non-blocking HIP stream, which admits the oldest one whenever a worker is
+// idle and its footprint (the exact allocation ctd_init will make) fits,
+// then sets the instance up and steps it on its stream.  Requests arriving
+// while others run thus start as soon as memory (and, for the pool, a
+// worker) is free, and the kernels of all running requests overlap on the
 // device.  Finished requests keep their modes on the device until fetched.
 #include <algorithm>
 #include <chrono>
@@ -37,8 +43,16 @@ struct Request {
   double t_submit = 0, t_start = 0, t_done = 0;
   ctd_solver* solver = nullptr;
   bool busy = false;   // a fetch holds the request (claimed under the lock)
+  bool lockstep = false;   // routed to the lockstep thread
   std::string err;
 };
+
+// Route of a request: the lockstep engine takes 2D adaptive requests with
+// cyclic-reduction solves (the directional solver of 2D under the automatic
+// choice) and no full-solve fallback.
+bool lockstep_route(const ctd_problem& p) {
+  return p.dim == 2 && p.schedule == CTD_SCHED_ADAPTIVE && p.solve_method != CTD_SOLVE_FD && !p.actd;
+}
 
 }  // namespace
 
@@ -49,7 +63,11 @@ struct ctd_server {
   std::mutex mu;
   std::condition_variable cv_work;   // workers: queue, memory or stop changed
   std::condition_variable cv_done;   // waiters: a request finished
-  std::deque<Request*> queue;
+  std::deque<Request*> queue;       // worker-pool route
+  std::deque<Request*> queue_ls;    // lockstep route
+  hipStream_t ls_stream = nullptr;
+  std::thread ls_thread;
+  bool use_lockstep = true;
   std::map<int64_t, std::unique_ptr<Request>> reqs;
   std::vector<hipStream_t> streams;
   std::vector<std::thread> workers;
@@ -63,6 +81,22 @@ struct ctd_server {
 };
 
 namespace {
+
+// Mark a request finished (under the lock).
+void finish_locked(ctd_server* S, Request* r, int rc, const std::string& msg) {
+  r->t_done = S->now_ms();
+  if (rc) {
+    r->state = CTD_REQ_FAILED;
+    r->error = rc;
+    r->err = msg;
+    S->in_use -= r->footprint;
+    ++S->failed;
+  } else {
+    r->state = CTD_REQ_DONE;
+    ++S->completed;
+  }
+  if (--S->running == 0) S->busy_ms += r->t_done - S->busy_since;
+}
 
 void worker_main(ctd_server* S, int w) {
   (void)hipSetDevice(S->device);
@@ -107,22 +141,117 @@ void worker_main(ctd_server* S, int w) {
     for (auto& v : r->init) std::vector<double>().swap(v);
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      r->t_done = S->now_ms();
-      if (rc) {
-        r->state = CTD_REQ_FAILED;
-        r->error = rc;
-        r->err = msg;
-        S->in_use -= r->footprint;
-        ++S->failed;
-      } else {
-        r->state = CTD_REQ_DONE;
-        ++S->completed;
-      }
-      if (--S->running == 0) S->busy_ms += r->t_done - S->busy_since;
+      finish_locked(S, r, rc, msg);
     }
     S->cv_done.notify_all();
     S->cv_work.notify_all();
   }
+}
+
+void lockstep_main(ctd_server* S) {
+  (void)hipSetDevice(S->device);
+  hipStream_t st = S->ls_stream;
+  std::map<int, std::unique_ptr<ctd::Lockstep>> engines;   // by band half-width
+  std::map<std::pair<int, int>, Request*> running;          // (band, slot) -> request
+  std::vector<std::pair<int, ctd_step_info>> steps;
+  std::vector<int> finished;
+  std::vector<std::pair<int, int>> failed;
+  for (;;) {
+    std::vector<Request*> admit;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      auto can_admit = [&] {
+        return !S->queue_ls.empty() && S->in_use + S->queue_ls.front()->footprint <= S->budget;
+      };
+      S->cv_work.wait(lk, [&] { return S->stop || can_admit() || !running.empty(); });
+      if (S->stop) break;
+      while (can_admit()) {
+        Request* r = S->queue_ls.front();
+        S->queue_ls.pop_front();
+        S->in_use += r->footprint;
+        r->state = CTD_REQ_RUNNING;
+        r->t_start = S->now_ms();
+        if (S->running++ == 0) S->busy_since = r->t_start;
+        admit.push_back(r);
+      }
+    }
+    // set-up of the admitted requests (their own stream: the engine's)
+    for (Request* r : admit) {
+      const double* ip[3] = {r->init[0].data(), r->init[1].data(), r->init[2].data()};
+      std::string msg;
+      int rc = ctd_init(&r->P, r->m0, ip, r->amp.empty() ? nullptr : r->amp.data(), st, &r->solver);
+      if (rc) msg = ctd_last_error(nullptr);
+      for (auto& v : r->init) std::vector<double>().swap(v);
+      int slot = -1, band = 0;
+      if (rc == CTD_OK && r->nsteps > 0) {
+        band = 2 * r->P.patch_s + 1;
+        auto& e = engines[band];
+        if (!e) e.reset(new ctd::Lockstep(st));
+        rc = e->add(r->solver, r->nsteps, &slot, msg);
+      }
+      if (rc == CTD_OK && r->nsteps > 0) {
+        running[{band, slot}] = r;
+        continue;
+      }
+      if (rc && r->solver) {
+        ctd_destroy(r->solver);
+        r->solver = nullptr;
+      }
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        finish_locked(S, r, rc, msg);
+      }
+      S->cv_done.notify_all();
+      S->cv_work.notify_all();
+    }
+    // one round of every engine with requests in it
+    for (auto& kv : engines) {
+      if (kv.second->empty()) continue;
+      steps.clear();
+      finished.clear();
+      failed.clear();
+      std::string msg;
+      const int rc = kv.second->round(steps, finished, msg, &failed);
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto& f : failed) {
+        Request* r = running[{kv.first, f.first}];
+        running.erase({kv.first, f.first});
+        const std::string m = ctd_last_error(r->solver);
+        ctd_destroy(r->solver);
+        r->solver = nullptr;
+        finish_locked(S, r, f.second, m);
+      }
+      for (auto& si : steps) {
+        Request* r = running[{kv.first, si.first}];
+        ++r->steps_done;
+        r->modes = si.second.modes;
+        ++S->steps_total;
+      }
+      for (int slot : finished) {
+        Request* r = running[{kv.first, slot}];
+        running.erase({kv.first, slot});
+        finish_locked(S, r, CTD_OK, "");
+      }
+      if (rc) {
+        // a failed round leaves the engine's instances in an unknown state:
+        // every request in it fails
+        for (auto it = running.begin(); it != running.end();) {
+          if (it->first.first != kv.first) { ++it; continue; }
+          Request* r = it->second;
+          ctd_destroy(r->solver);
+          r->solver = nullptr;
+          finish_locked(S, r, rc, msg);
+          it = running.erase(it);
+        }
+        kv.second.reset(new ctd::Lockstep(st));
+      }
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  // stopped: requests still running fail
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& kv : running) finish_locked(S, kv.second, CTD_ESTATE, "server stopped");
 }
 
 Request* find(ctd_server* S, int64_t ticket) {
@@ -157,7 +286,14 @@ int ctd_server_create(uint64_t budget_bytes, int32_t workers, ctd_server** out) 
       g_server_error = "stream creation failed";
       return CTD_EDEVICE;
     }
+  if (hipStreamCreateWithFlags(&S->ls_stream, hipStreamNonBlocking) != hipSuccess) {
+    for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+    delete S;
+    g_server_error = "stream creation failed";
+    return CTD_EDEVICE;
+  }
   for (int w = 0; w < workers; ++w) S->workers.emplace_back(worker_main, S, w);
+  S->ls_thread = std::thread(lockstep_main, S);
   *out = S;
   return CTD_OK;
 }
@@ -191,7 +327,8 @@ int ctd_server_submit(ctd_server* S, const ctd_problem* p, int32_t m0, const dou
   r->ticket = S->next_ticket++;
   r->t_submit = S->now_ms();
   *ticket = r->ticket;
-  S->queue.push_back(r.get());
+  r->lockstep = S->use_lockstep && lockstep_route(r->P);
+  (r->lockstep ? S->queue_ls : S->queue).push_back(r.get());
   S->reqs[r->ticket] = std::move(r);
   ++S->submitted;
   S->cv_work.notify_all();
@@ -278,7 +415,7 @@ int ctd_server_get_stats(ctd_server* S, ctd_server_stats* st) {
   st->submitted = S->submitted;
   st->completed = S->completed;
   st->failed = S->failed;
-  st->queued = (int64_t)S->queue.size();
+  st->queued = (int64_t)(S->queue.size() + S->queue_ls.size());
   st->running = S->running;
   st->bytes_in_use = S->in_use;
   st->budget = S->budget;
@@ -299,10 +436,19 @@ void ctd_server_destroy(ctd_server* S) {
   }
   S->cv_work.notify_all();
   for (auto& t : S->workers) t.join();
+  if (S->ls_thread.joinable()) S->ls_thread.join();
   for (auto& kv : S->reqs)
     if (kv.second->solver) ctd_destroy(kv.second->solver);
   for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+  if (S->ls_stream) (void)hipStreamDestroy(S->ls_stream);
   delete S;
+}
+
+int ctd_server_set_lockstep(ctd_server* S, int32_t on) {
+  if (!S) return CTD_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  S->use_lockstep = on != 0;
+  return CTD_OK;
 }
 
 }  // extern "C"

@@ -1140,233 +1140,366 @@ bool lockstep_eligible(const ctd_solver* s) {
 
 int band_halfwidth(const ctd_solver* s) { return s->ax[0].B; }
 
-int lockstep_steps(std::vector<ctd_solver*>& S, int nsteps, ctd_step_info* info, hipStream_t st,
-                   std::string& err) {
-  const int N = (int)S.size();
-  if (N == 0 || nsteps <= 0) return CTD_OK;
-  const int B = S[0]->ax[0].B;
-  for (ctd_solver* s : S) {
-    if (!lockstep_eligible(s) || s->ax[0].B != B) { err = "instance not eligible for lockstep"; return CTD_EINVAL; }
-    solver_bind_stream(s, st);
-  }
-  // device and pinned host mirrors: DevInst per instance, two argument
-  // arrays (initialisation group, sweep group), gathered scalars
+// ------------------------------------------------------------ engine
+struct Lockstep::Impl {
+  hipStream_t st = nullptr;
+  int B = 0;                         // band half-width shared by the instances
+  int cap = 0;                       // slots of the device and pinned arrays
   DevInst* dI = nullptr;
   LsArg* dA = nullptr;
   DevScalars* dS = nullptr;
   DevInst* hI = nullptr;
   LsArg* hA = nullptr;
   DevScalars* hS = nullptr;
-  auto cleanup = [&]() {
-    (void)hipStreamSynchronize(st);
+  std::vector<ctd_solver*> S;        // per slot (nullptr: free)
+  std::vector<LockstepInst> L;
+  std::vector<int> remaining;        // steps still to run per slot
+  std::vector<std::vector<int32_t>> logs;
+  int live = 0;
+
+  hipError_t sync() { return hipStreamSynchronize(st); }
+  void release() {
+    (void)sync();
     if (dI) (void)hipFree(dI);
     if (dA) (void)hipFree(dA);
     if (dS) (void)hipFree(dS);
     if (hI) (void)hipHostFree(hI);
     if (hA) (void)hipHostFree(hA);
     if (hS) (void)hipHostFree(hS);
-  };
+    dI = nullptr; dA = nullptr; dS = nullptr; hI = nullptr; hA = nullptr; hS = nullptr;
+  }
+  // grow the arrays to `want` slots (the instances in use are re-uploaded)
+  hipError_t grow(int want) {
+    hipError_t e = sync();
+    if (e != hipSuccess) return e;
+    DevInst *nI = nullptr, *nhI = nullptr;
+    LsArg *nA = nullptr, *nhA = nullptr;
+    DevScalars *nS = nullptr, *nhS = nullptr;
+    if ((e = hipMalloc(&nI, sizeof(DevInst) * want)) != hipSuccess ||
+        (e = hipMalloc(&nA, sizeof(LsArg) * 4 * want)) != hipSuccess ||
+        (e = hipMalloc(&nS, sizeof(DevScalars) * want)) != hipSuccess ||
+        (e = hipHostMalloc(&nhI, sizeof(DevInst) * want, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&nhA, sizeof(LsArg) * 4 * want, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&nhS, sizeof(DevScalars) * want, hipHostMallocDefault)) != hipSuccess) {
+      if (nI) (void)hipFree(nI);
+      if (nA) (void)hipFree(nA);
+      if (nS) (void)hipFree(nS);
+      if (nhI) (void)hipHostFree(nhI);
+      if (nhA) (void)hipHostFree(nhA);
+      if (nhS) (void)hipHostFree(nhS);
+      return e;
+    }
+    if (cap) std::memcpy(nhI, hI, sizeof(DevInst) * cap);
+    release();
+    dI = nI; dA = nA; dS = nS; hI = nhI; hA = nhA; hS = nhS;
+    S.resize(want, nullptr);
+    L.resize(want);
+    remaining.resize(want, 0);
+    logs.resize(want);
+    cap = want;
+    for (int i = 0; i < cap; ++i)
+      if (S[i] && (e = hipMemcpyAsync(dI + i, hI + i, sizeof(DevInst), hipMemcpyHostToDevice, st)) != hipSuccess)
+        return e;
+    return hipSuccess;
+  }
+  hipError_t upload(int i) {
+    update_view(S[i]);
+    hI[i] = S[i]->I;
+    return hipMemcpyAsync(dI + i, hI + i, sizeof(DevInst), hipMemcpyHostToDevice, st);
+  }
+};
+
+Lockstep::Lockstep(hipStream_t st) : p(new Impl) { p->st = st; }
+
+Lockstep::~Lockstep() {
+  p->release();
+  delete p;
+}
+
+bool Lockstep::empty() const { return p->live == 0; }
+
+int Lockstep::band() const { return p->B; }
+
+int Lockstep::add(ctd_solver* s, int nsteps, int* slot, std::string& err) {
+  if (!lockstep_eligible(s)) {
+    err = "lockstep needs a 2D adaptive instance with cyclic-reduction solves";
+    return CTD_EUNSUPPORTED;
+  }
+  if (p->live > 0 && s->ax[0].B != p->B) {
+    err = "lockstep instances must share one band width";
+    return CTD_EUNSUPPORTED;
+  }
+  if (nsteps < 1) {
+    err = "lockstep needs at least one step";
+    return CTD_EINVAL;
+  }
+  int i = 0;
+  while (i < p->cap && p->S[i]) ++i;
+  if (i == p->cap) {
+    hipError_t e = p->grow(std::max(16, 2 * p->cap));
+    if (e != hipSuccess) {
+      err = std::string("HIP error in lockstep arrays: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? CTD_ENOMEM : CTD_EDEVICE;
+    }
+  }
+  p->B = s->ax[0].B;
+  solver_bind_stream(s, p->st);
+  p->S[i] = s;
+  p->L[i] = LockstepInst{};
+  p->L[i].s = s;
+  p->L[i].t0 = std::chrono::steady_clock::now();
+  p->remaining[i] = nsteps;
+  p->logs[i].clear();
+  ++p->live;
+  hipError_t e = p->upload(i);
+  if (e != hipSuccess) {
+    err = std::string("HIP error in lockstep upload: ") + hipGetErrorString(e);
+    return CTD_EDEVICE;
+  }
+  *slot = i;
+  return CTD_OK;
+}
+
+int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vector<int>& finished,
+                    std::string& err, std::vector<std::pair<int, int>>* failed) {
+  Impl& E = *p;
+  if (E.live == 0) return CTD_OK;
+  hipStream_t st = E.st;
+  const int B = E.B;
+  const int N = E.cap;
   auto hip = [&](hipError_t e, const char* where) {
     if (e == hipSuccess) return CTD_OK;
     err = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
     return CTD_EDEVICE;
   };
-  int rc = CTD_OK;
-  if ((rc = hip(hipMalloc(&dI, sizeof(DevInst) * N), "lockstep alloc")) ||
-      (rc = hip(hipMalloc(&dA, sizeof(LsArg) * 4 * N), "lockstep alloc")) ||
-      (rc = hip(hipMalloc(&dS, sizeof(DevScalars) * N), "lockstep alloc")) ||
-      (rc = hip(hipHostMalloc(&hI, sizeof(DevInst) * N, hipHostMallocDefault), "lockstep alloc")) ||
-      (rc = hip(hipHostMalloc(&hA, sizeof(LsArg) * 4 * N, hipHostMallocDefault), "lockstep alloc")) ||
-      (rc = hip(hipHostMalloc(&hS, sizeof(DevScalars) * N, hipHostMallocDefault), "lockstep alloc"))) {
-    cleanup();
-    return rc;
-  }
-  std::vector<LockstepInst> L(N);
-  std::vector<std::vector<int32_t>> logs(N);
-  auto upload = [&](int i) {
-    update_view(S[i]);
-    hI[i] = S[i]->I;
-    return hip(hipMemcpyAsync(dI + i, hI + i, sizeof(DevInst), hipMemcpyHostToDevice, st), "lockstep upload");
-  };
-  for (int i = 0; i < N; ++i) {
-    L[i].s = S[i];
-    L[i].t0 = std::chrono::steady_clock::now();
-    if ((rc = upload(i))) { cleanup(); return rc; }
-  }
   auto fill = [&](LsArg& a, int i) {
-    const ctd_solver* s = S[i];
+    const ctd_solver* s = E.S[i];
     a.inst = i;
-    a.M = L[i].M;
-    a.sweep = L[i].it;
-    a.mode = L[i].mode;
+    a.M = E.L[i].M;
+    a.sweep = E.L[i].it;
+    a.mode = E.L[i].mode;
     a.warm = s->P.init_mode == CTD_INIT_WARM;
-    a.nlin = (s->Mk + 2 * L[i].M + 63) / 64;
+    a.nlin = (s->Mk + 2 * E.L[i].M + 63) / 64;
     for (int d = 0; d < 2; ++d) a.nld[d] = (s->ax[1 - d].n + 63) / 64;
     a.step = s->step_index;
   };
   // workgroup size of an instance's own initial-guess finalisation
   auto finalize_threads = [&](int i) {
-    const int n = std::max(S[i]->ax[0].n, S[i]->ax[1].n);
+    const int n = std::max(E.S[i]->ax[0].n, E.S[i]->ax[1].n);
     return n >= 1024 ? 1024 : (n + 63) / 64 * 64;
   };
-  for (;;) {
-    // groups of this round; the initialisation group ordered by its
-    // finalisation workgroup size (one launch per size)
-    std::vector<int> gi, gs;
-    for (int i = 0; i < N; ++i) {
-      if (L[i].done) continue;
-      if (L[i].start) gi.push_back(i);
-      gs.push_back(i);
+  // groups of this round; the initialisation group ordered by its
+  // finalisation workgroup size (one launch per size)
+  std::vector<int> gi, gs;
+  for (int i = 0; i < N; ++i) {
+    if (!E.S[i]) continue;
+    if (E.L[i].start) gi.push_back(i);
+    gs.push_back(i);
+  }
+  std::stable_sort(gi.begin(), gi.end(),
+                   [&](int a, int b) { return finalize_threads(a) < finalize_threads(b); });
+  const int ni = (int)gi.size(), ns = (int)gs.size();
+  LsArg* hAi = E.hA;
+  LsArg* hAs = E.hA + N;
+  for (int k = 0; k < ni; ++k) { fill(hAi[k], gi[k]); hAi[k].flag = E.L[gi[k]].pending_append ? 1 : 0; }
+  for (int k = 0; k < ns; ++k) { fill(hAs[k], gs[k]); hAs[k].flag = E.L[gs[k]].it > 1 ? 1 : 0; }
+  // the solve launches: sweep entries regrouped per direction by BCR
+  // storage class and thread count (blocks [2N, 3N) and [3N, 4N))
+  struct SolveClass { int mode, threads, first, count; size_t shm; };
+  std::vector<SolveClass> scls[2];
+  for (int d = 0; d < 2; ++d) {
+    std::map<std::pair<int, int>, std::vector<int>> cls;
+    std::map<std::pair<int, int>, size_t> shm;
+    for (int k = 0; k < ns; ++k) {
+      int mode, threads;
+      size_t sh;
+      bcr_launch_class(E.S[gs[k]]->ax[d].n, B, mode, threads, sh);
+      cls[{mode, threads}].push_back(k);
+      shm[{mode, threads}] = std::max(shm[{mode, threads}], sh);
     }
-    if (gs.empty()) break;
-    std::stable_sort(gi.begin(), gi.end(),
-                     [&](int a, int b) { return finalize_threads(a) < finalize_threads(b); });
-    const int ni = (int)gi.size(), ns = (int)gs.size();
-    LsArg* hAi = hA;
-    LsArg* hAs = hA + N;
-    for (int k = 0; k < ni; ++k) { fill(hAi[k], gi[k]); hAi[k].flag = L[gi[k]].pending_append ? 1 : 0; }
-    for (int k = 0; k < ns; ++k) { fill(hAs[k], gs[k]); hAs[k].flag = L[gs[k]].it > 1 ? 1 : 0; }
-    // the solve launches: sweep entries regrouped per direction by BCR
-    // storage class and thread count (blocks [2N, 3N) and [3N, 4N))
-    struct SolveClass { int mode, threads, first, count; size_t shm; };
-    std::vector<SolveClass> scls[2];
+    LsArg* dst = E.hA + (2 + d) * N;
+    int at = 0;
+    for (auto& kv : cls) {
+      scls[d].push_back({kv.first.first, kv.first.second, at, (int)kv.second.size(), shm[kv.first]});
+      for (int k : kv.second) dst[at++] = hAs[k];
+    }
+  }
+  DevInst* dI = E.dI;
+  LsArg* dA = E.dA;
+  int rc = CTD_OK;
+  if ((rc = hip(hipMemcpyAsync(dA, E.hA, sizeof(LsArg) * 4 * N, hipMemcpyHostToDevice, st), "lockstep args")))
+    return rc;
+  LsArg* dAi = dA;
+  LsArg* dAs = dA + N;
+  auto grid_of = [&](const std::vector<int>& g, const LsArg* a, int d) {
+    LsGrid G;
+    G.B = B;
+    for (size_t k = 0; k < g.size(); ++k) {
+      const ctd_solver* s = E.S[g[k]];
+      const int n = d < 0 ? std::max(s->ax[0].n, s->ax[1].n) : s->ax[d].n;
+      G.nmax = std::max(G.nmax, n);
+      G.ndot = std::max(G.ndot, (2 * a[k].M + s->Mk + 3) / 4);
+      if (d >= 0) G.nchunk = std::max(G.nchunk, a[k].nlin + a[k].nld[d]);
+    }
+    G.ndot = std::max(G.ndot, 1);
+    return G;
+  };
+  // mode initialisation (after the append of the previous mode)
+  if (ni > 0) {
+    const LsGrid G = grid_of(gi, hAi, -1);
+    if ((rc = hip(launch_multi(kLsAppend, dI, dAi, ni, G, st), "append")) ||
+        (rc = hip(launch_multi(kLsReset, dI, dAi, ni, G, st), "reset")) ||
+        (rc = hip(launch_multi(kLsInit, dI, dAi, ni, G, st), "init")))
+      return rc;
+    for (int k0 = 0; k0 < ni;) {
+      int k1 = k0;
+      LsGrid Gf;
+      Gf.B = B;
+      Gf.threads = finalize_threads(gi[k0]);
+      while (k1 < ni && finalize_threads(gi[k1]) == Gf.threads) {
+        Gf.nmax = std::max(Gf.nmax, std::max(E.S[gi[k1]]->ax[0].n, E.S[gi[k1]]->ax[1].n));
+        ++k1;
+      }
+      if ((rc = hip(launch_multi(kLsFinalizeInit, dI, dAi + k0, k1 - k0, Gf, st), "finalize"))) return rc;
+      k0 = k1;
+    }
+    if ((rc = hip(launch_multi(kLsSignatureAll, dI, dAi, ni, G, st), "signature"))) return rc;
+    for (int i : gi) { E.L[i].pending_append = false; E.L[i].start = false; }
+  }
+  // one sweep of every instance in a mode: the signature of the last
+  // direction (continued sweeps only), then per direction RHS and solve,
+  // and the signature of every direction but the last
+  {
+    LsGrid G1 = grid_of(gs, hAs, 1);
+    if ((rc = hip(launch_multi(kLsSignatureFlag, dI, dAs, ns, G1, st, 1), "signature"))) return rc;
     for (int d = 0; d < 2; ++d) {
-      std::map<std::pair<int, int>, std::vector<int>> cls;
-      std::map<std::pair<int, int>, size_t> shm;
-      for (int k = 0; k < ns; ++k) {
-        int mode, threads;
-        size_t sh;
-        bcr_launch_class(S[gs[k]]->ax[d].n, B, mode, threads, sh);
-        cls[{mode, threads}].push_back(k);
-        shm[{mode, threads}] = std::max(shm[{mode, threads}], sh);
+      const LsGrid G = grid_of(gs, hAs, d);
+      if ((rc = hip(launch_multi(kLsRhs, dI, dAs, ns, G, st, d), "rhs"))) return rc;
+      // the solve: one launch per BCR storage class and thread count
+      for (const SolveClass& c : scls[d]) {
+        LsGrid G2;
+        G2.B = B;
+        G2.mode = c.mode;
+        G2.threads = c.threads;
+        G2.shm = c.shm;
+        if ((rc = hip(launch_multi(kLsSolve, dI, dA + (2 + d) * N + c.first, c.count, G2, st, d), "solve")))
+          return rc;
       }
-      LsArg* dst = hA + (2 + d) * N;
-      int at = 0;
-      for (auto& kv : cls) {
-        scls[d].push_back({kv.first.first, kv.first.second, at, (int)kv.second.size(), shm[kv.first]});
-        for (int k : kv.second) dst[at++] = hAs[k];
+      if (d == 0) {
+        const LsGrid G0 = grid_of(gs, hAs, 0);
+        if ((rc = hip(launch_multi(kLsSignature, dI, dAs, ns, G0, st, 0), "signature"))) return rc;
       }
     }
-    if ((rc = hip(hipMemcpyAsync(dA, hA, sizeof(LsArg) * 4 * N, hipMemcpyHostToDevice, st), "lockstep args"))) break;
-    LsArg* dAi = dA;
-    LsArg* dAs = dA + N;
-    auto grid_of = [&](const std::vector<int>& g, const LsArg* a, int d) {
-      LsGrid G;
-      G.B = B;
-      for (size_t k = 0; k < g.size(); ++k) {
-        const ctd_solver* s = S[g[k]];
-        const int n = d < 0 ? std::max(s->ax[0].n, s->ax[1].n) : s->ax[d].n;
-        G.nmax = std::max(G.nmax, n);
-        G.ndot = std::max(G.ndot, (2 * a[k].M + s->Mk + 3) / 4);
-        if (d >= 0) G.nchunk = std::max(G.nchunk, a[k].nlin + a[k].nld[d]);
-      }
-      G.ndot = std::max(G.ndot, 1);
-      return G;
+  }
+  // one read-back of every instance's scalars
+  if ((rc = hip(launch_multi(kLsGather, dI, dAs, ns, LsGrid{}, st, 0, E.dS), "gather")) ||
+      (rc = hip(hipMemcpyAsync(E.hS, E.dS, sizeof(DevScalars) * ns, hipMemcpyDeviceToHost, st), "gather")) ||
+      (rc = hip(hipStreamSynchronize(st), "gather")))
+    return rc;
+  // decisions, as one_step takes them
+  for (int k = 0; k < ns; ++k) {
+    const int i = gs[k];
+    LockstepInst& Li = E.L[i];
+    ctd_solver* s = E.S[i];
+    const DevScalars& sc = E.hS[k];
+    const int nsw = std::max(1, s->P.fp_max_iter);
+    bool end_step = false;
+    // an instance that fails leaves the engine (failed != nullptr) or ends
+    // the round with its error
+    auto fail_inst = [&](int code, const std::string& msg) -> int {
+      err = msg;
+      if (!failed) return code;
+      failed->push_back({i, code});
+      E.logs[i].clear();
+      E.S[i] = nullptr;
+      --E.live;
+      return CTD_OK;
     };
-    // mode initialisation (after the append of the previous mode)
-    if (ni > 0) {
-      const LsGrid G = grid_of(gi, hAi, -1);
-      if ((rc = hip(launch_multi(kLsAppend, dI, dAi, ni, G, st), "append")) ||
-          (rc = hip(launch_multi(kLsReset, dI, dAi, ni, G, st), "reset")) ||
-          (rc = hip(launch_multi(kLsInit, dI, dAi, ni, G, st), "init")))
-        break;
-      for (int k0 = 0; k0 < ni && rc == CTD_OK;) {
-        int k1 = k0;
-        LsGrid Gf;
-        Gf.B = B;
-        Gf.threads = finalize_threads(gi[k0]);
-        while (k1 < ni && finalize_threads(gi[k1]) == Gf.threads) {
-          Gf.nmax = std::max(Gf.nmax, std::max(S[gi[k1]]->ax[0].n, S[gi[k1]]->ax[1].n));
-          ++k1;
-        }
-        rc = hip(launch_multi(kLsFinalizeInit, dI, dAi + k0, k1 - k0, Gf, st), "finalize");
-        k0 = k1;
+    if (sc.zero) {
+      Li.zero = 1;
+      end_step = true;
+    } else {
+      if (sc.nonfinite) {
+        s->err = "non-finite mode amplitude";
+        if ((rc = fail_inst(CTD_ENONFINITE, s->err))) return rc;
+        continue;
       }
-      if (rc || (rc = hip(launch_multi(kLsSignatureAll, dI, dAi, ni, G, st), "signature"))) break;
-      for (int i : gi) { L[i].pending_append = false; L[i].start = false; }
-    }
-    // one sweep of every instance in a mode: the signature of the last
-    // direction (continued sweeps only), then per direction RHS and solve,
-    // and the signature of every direction but the last
-    {
-      LsGrid G1 = grid_of(gs, hAs, 1);
-      if ((rc = hip(launch_multi(kLsSignatureFlag, dI, dAs, ns, G1, st, 1), "signature"))) break;
-      for (int d = 0; d < 2 && rc == CTD_OK; ++d) {
-        const LsGrid G = grid_of(gs, hAs, d);
-        if ((rc = hip(launch_multi(kLsRhs, dI, dAs, ns, G, st, d), "rhs"))) break;
-        // the solve: one launch per BCR storage class and thread count
-        for (const SolveClass& c : scls[d]) {
-          LsGrid G2;
-          G2.B = B;
-          G2.mode = c.mode;
-          G2.threads = c.threads;
-          G2.shm = c.shm;
-          if ((rc = hip(launch_multi(kLsSolve, dI, dA + (2 + d) * N + c.first, c.count, G2, st, d), "solve")))
-            break;
-        }
-        if (rc) break;
-        if (d == 0) {
-          const LsGrid G0 = grid_of(gs, hAs, 0);
-          if ((rc = hip(launch_multi(kLsSignature, dI, dAs, ns, G0, st, 0), "signature"))) break;
-        }
+      const bool conv = sc.converged != 0 && Li.it >= 2;
+      const bool last = Li.it == nsw || conv;
+      if (!last) {
+        ++Li.it;
+        continue;
       }
-      if (rc) break;
-    }
-    // one read-back of every instance's scalars
-    if ((rc = hip(launch_multi(kLsGather, dI, dAs, ns, LsGrid{}, st, 0, dS), "gather")) ||
-        (rc = hip(hipMemcpyAsync(hS, dS, sizeof(DevScalars) * ns, hipMemcpyDeviceToHost, st), "gather")) ||
-        (rc = hip(hipStreamSynchronize(st), "gather")))
-      break;
-    // decisions, as one_step takes them
-    for (int k = 0; k < ns && rc == CTD_OK; ++k) {
-      const int i = gs[k];
-      LockstepInst& Li = L[i];
-      ctd_solver* s = S[i];
-      const DevScalars& sc = hS[k];
-      const int nsw = std::max(1, s->P.fp_max_iter);
-      bool end_step = false;
-      if (sc.zero) {
-        Li.zero = 1;
+      Li.sweeps += Li.it;
+      if (!conv) ++Li.unconv;
+      ++Li.M;
+      Li.iters.push_back(Li.it);
+      Li.pending_append = true;
+      double pu = 1.0;
+      for (int d = 0; d < 2; ++d) pu *= sc.umax[d];
+      Li.last_term = sc.sigma[1] * pu;
+      if (Li.last_term <= s->P.enrich_tol) {
+        end_step = true;
+      } else if (Li.M >= s->P.max_modes) {
+        Li.capped = 1;
         end_step = true;
       } else {
-        if (sc.nonfinite) { err = "non-finite mode amplitude"; rc = CTD_ENONFINITE; break; }
-        const bool conv = sc.converged != 0 && Li.it >= 2;
-        const bool last = Li.it == nsw || conv;
-        if (!last) {
-          ++Li.it;
-          continue;
-        }
-        Li.sweeps += Li.it;
-        if (!conv) ++Li.unconv;
-        ++Li.M;
-        Li.iters.push_back(Li.it);
-        Li.pending_append = true;
-        double pu = 1.0;
-        for (int d = 0; d < 2; ++d) pu *= sc.umax[d];
-        Li.last_term = sc.sigma[1] * pu;
-        if (Li.last_term <= s->P.enrich_tol) {
-          end_step = true;
-        } else if (Li.M >= s->P.max_modes) {
-          Li.capped = 1;
-          end_step = true;
-        } else {
-          ++Li.mode;
-          Li.it = 1;
-          Li.start = true;
-        }
-      }
-      if (end_step) {
-        rc = lockstep_finish(Li, info ? info + (size_t)i * nsteps + Li.steps_done : nullptr, logs[i]);
-        if (rc) { err = s->err; break; }
-        if (Li.steps_done >= nsteps) Li.done = true;
-        else if ((rc = upload(i))) break;
+        ++Li.mode;
+        Li.it = 1;
+        Li.start = true;
       }
     }
-    if (rc) break;
+    if (end_step) {
+      ctd_step_info inf{};
+      rc = lockstep_finish(Li, &inf, E.logs[i]);
+      if (rc) {
+        if ((rc = fail_inst(rc, s->err))) return rc;
+        continue;
+      }
+      steps.push_back({i, inf});
+      if (--E.remaining[i] == 0) {
+        s->decisions_last.swap(E.logs[i]);
+        E.logs[i].clear();
+        E.S[i] = nullptr;
+        --E.live;
+        finished.push_back(i);
+      } else if ((rc = hip(E.upload(i), "lockstep upload"))) {
+        return rc;
+      }
+    }
   }
-  cleanup();
-  if (rc == CTD_OK)
-    for (int i = 0; i < N; ++i) S[i]->decisions_last.swap(logs[i]);
+  return CTD_OK;
+}
+
+int lockstep_steps(std::vector<ctd_solver*>& S, int nsteps, ctd_step_info* info, hipStream_t st,
+                   std::string& err) {
+  const int N = (int)S.size();
+  if (N == 0 || nsteps <= 0) return CTD_OK;
+  Lockstep E(st);
+  std::vector<int> slot_of(N), inst_of;
+  int rc = CTD_OK;
+  for (int i = 0; i < N && rc == CTD_OK; ++i) {
+    int slot = -1;
+    rc = E.add(S[i], nsteps, &slot, err);
+    if (rc == CTD_OK) {
+      slot_of[i] = slot;
+      if ((int)inst_of.size() <= slot) inst_of.resize(slot + 1, -1);
+      inst_of[slot] = i;
+    }
+  }
+  std::vector<int> done_steps(N, 0);
+  std::vector<std::pair<int, ctd_step_info>> steps;
+  std::vector<int> finished;
+  while (rc == CTD_OK && !E.empty()) {
+    steps.clear();
+    finished.clear();
+    rc = E.round(steps, finished, err);
+    for (auto& st_info : steps) {
+      const int i = inst_of[st_info.first];
+      if (info) info[(size_t)i * nsteps + done_steps[i]] = st_info.second;
+      ++done_steps[i];
+    }
+  }
   return rc;
 }
 

@@ -116,6 +116,7 @@ def _load():
         "ctd_batch_step": (C.c_int, [vp, C.c_int32, P(StepInfo)]),
         "ctd_footprint_bytes": (C.c_int, [P(Problem), C.c_int32, P(C.c_uint64)]),
         "ctd_server_create": (C.c_int, [C.c_uint64, C.c_int32, P(vp)]),
+        "ctd_server_set_lockstep": (C.c_int, [vp, C.c_int32]),
         "ctd_server_submit": (C.c_int, [vp, P(Problem), C.c_int32, P(P(C.c_double)), P(C.c_double),
                                         C.c_int32, P(C.c_int64)]),
         "ctd_server_status": (C.c_int, [vp, C.c_int64, P(RequestStatus)]),
@@ -545,11 +546,13 @@ def footprint_bytes(inst, m0=None, **kw):
 class Server:
     """Served execution with continuous batching (ctd_server_*)."""
 
-    def __init__(self, budget_bytes=0, workers=8):
+    def __init__(self, budget_bytes=0, workers=8, lockstep=True):
         h = C.c_void_p()
         rc = LIB.ctd_server_create(int(budget_bytes), int(workers), C.byref(h))
         if rc != CTD_OK:
             raise CtdError(rc, LIB.ctd_server_last_error(None).decode())
+        if not lockstep:
+            LIB.ctd_server_set_lockstep(h, 0)
         self.h = h
         self._nodes = {}
 

@@ -3,6 +3,7 @@
     python -m paper_2410_15519_amd.profsum trace DB TITLE CMD > summary.md
     python -m paper_2410_15519_amd.profsum pmc FETCH_CSV WRITE_CSV COPY_MIB TITLE CMD > summary.md
     python -m paper_2410_15519_amd.profsum mfma COUNTER_CSV CUS TITLE CMD > summary.md
+    python -m paper_2410_15519_amd.profsum counters CSV[:CSV...] PREFIXES TITLE CMD > summary.md
 
 `trace` groups the kernel records of a rocpd database by kernel name and
 grid.  `pmc` averages FETCH_SIZE and WRITE_SIZE (KiB per dispatch) per kernel
@@ -156,6 +157,47 @@ def mfma(csv_path: str, cus: int, title: str, cmd: str, xcds: int = 8, simds: in
     return "\n".join(out) + "\n"
 
 
+def counters(csv_paths, prefixes, title: str, cmd: str) -> str:
+    """Every counter of one or more counter runs, per-dispatch means per
+    kernel name and grid, for the kernels whose name starts with one of
+    `prefixes` (comma-separated), with the ratios used to read them: VALU
+    and LDS instructions per wave, LDS bank-conflict cycles per LDS
+    instruction, and the share of wave cycles spent waiting."""
+    vals = collections.defaultdict(dict)
+    disp = {}
+    names = set()
+    for path in csv_paths:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                names.add(row.get("Counter_Name"))
+    for path in csv_paths:
+        for c in sorted(n for n in names if n):
+            for k, (nd, v) in _per_kernel(path, c).items():
+                if any(k.startswith(p) for p in prefixes.split(",")):
+                    vals[k][c] = v
+                    disp[k] = nd
+    cols = sorted({c for v in vals.values() for c in v})
+    out = [f"# {title}", "", "Commands (run from the repository root on one MI355X):", "", "```", cmd, "```", "",
+           "Per-dispatch means per kernel name and grid size (counters summed over the device).", "",
+           f"kernel source sha256 (first 16 hex): {kernel_source_sha()}", "",
+           "| kernel [grid work-items] | dispatches | " + " | ".join(cols) + " |",
+           "|---|---|" + "---|" * len(cols)]
+    for k in sorted(vals, key=lambda k: -disp[k]):
+        out.append(f"| {k} | {disp[k]} | " + " | ".join(f"{vals[k].get(c, float('nan')):.4g}" for c in cols) + " |")
+    out += ["", "Ratios:", "", "| kernel | VALU/wave | LDS/wave | bank-conflict cycles per LDS inst | "
+            "wait / wave cycles | busy / wave cycles (VALU) |", "|---|---|---|---|---|---|"]
+    for k in sorted(vals, key=lambda k: -disp[k]):
+        v = vals[k]
+        w = v.get("SQ_WAVES", 0.0)
+        def r(a, b):
+            return f"{v[a] / v[b]:.3g}" if a in v and b in v and v[b] else "-"
+        valu = f"{v['SQ_INSTS_VALU'] / w:.0f}" if "SQ_INSTS_VALU" in v and w else "-"
+        lds = f"{v['SQ_INSTS_LDS'] / w:.0f}" if "SQ_INSTS_LDS" in v and w else "-"
+        out.append(f"| {k} | {valu} | {lds} | {r('SQ_LDS_BANK_CONFLICT', 'SQ_INSTS_LDS')} | "
+                   f"{r('SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES')} | {r('SQ_ACTIVE_INST_VALU', 'SQ_WAVE_CYCLES')} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "trace":
         sys.stdout.write(trace(argv[1], argv[2], argv[3]))
@@ -163,6 +205,8 @@ def main(argv):
         sys.stdout.write(pmc(argv[1], argv[2], float(argv[3]), argv[4], argv[5]))
     elif len(argv) >= 5 and argv[0] == "mfma":
         sys.stdout.write(mfma(argv[1], int(argv[2]), argv[3], argv[4]))
+    elif len(argv) >= 5 and argv[0] == "counters":
+        sys.stdout.write(counters(argv[1].split(":"), argv[2], argv[3], argv[4]))
     else:
         raise SystemExit(__doc__)
 

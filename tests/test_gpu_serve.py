@@ -120,7 +120,8 @@ def test_lockstep_needs_one_band_width(ctd):
         assert same_modes(got[i], standalone(ctd, inst, 1, precision="fp64")), f"instance {i}"
 
 
-def test_served_alone_equals_mix(ctd):
+@pytest.mark.parametrize("lockstep", [True, False])
+def test_served_alone_equals_mix(ctd, lockstep):
     target = small_instance(dim=2, n=40, m0=3, kmax=4, seed=5, max_modes=12)
     target3 = small_instance(dim=3, n=17, m0=3, kmax=4, seed=6, max_modes=8)
     others = [inst for _, inst in make_requests(seed=3, count=8, nodes2d_range=(24, 96),
@@ -128,12 +129,13 @@ def test_served_alone_equals_mix(ctd):
                                                 max_modes=10)]
     ref = standalone(ctd, target, 3, precision="mixed")
     ref3 = standalone(ctd, target3, 2, precision="mixed")
-    with ctd.Server(workers=1) as srv:
+    print(f"served mix, lockstep route {lockstep}", flush=True)
+    with ctd.Server(workers=1, lockstep=lockstep) as srv:
         t = srv.submit(target, nsteps=3, precision="mixed")
         assert srv.wait(t, 60000)
         alone = srv.fetch(t)
     assert same_modes(alone, ref)
-    with ctd.Server(workers=4) as srv:
+    with ctd.Server(workers=4, lockstep=lockstep) as srv:
         tickets = [srv.submit(o, precision="mixed") for o in others[:4]]
         t = srv.submit(target, nsteps=3, precision="mixed")
         t3 = srv.submit(target3, nsteps=2, precision="mixed")
@@ -152,6 +154,32 @@ def test_served_alone_equals_mix(ctd):
         assert stats["bytes_in_use"] == 0
     assert same_modes(mixed, ref)
     assert same_modes(mixed3, ref3)
+
+
+def test_served_join_while_running(ctd):
+    """Lockstep route: requests that arrive while others are mid-step join the
+    running set at their own first step; each equals its standalone run."""
+    import time
+    reqs = [small_instance(dim=2, n=n, m0=3, kmax=4, seed=20 + k, max_modes=10)
+            for k, n in enumerate((36, 90, 50, 130))]
+    refs = [standalone(ctd, r, 3, precision="fp64") for r in reqs]
+    with ctd.Server(workers=2) as srv:
+        first = srv.submit(reqs[0], nsteps=3, precision="fp64")
+        tickets = [first]
+        for r in reqs[1:]:
+            # wait until the running set has made progress, then join it
+            t0 = time.time()
+            while srv.status(tickets[-1])["state"] == "queued" and time.time() - t0 < 30:
+                time.sleep(0.001)
+            tickets.append(srv.submit(r, nsteps=3, precision="fp64"))
+        for t in tickets:
+            assert srv.wait(t, 120000)
+        st = [srv.status(t) for t in tickets]
+        got = [srv.fetch(t) for t in tickets]
+    # later requests started before earlier ones finished (they overlapped)
+    assert any(st[k + 1]["t_start_ms"] < st[k]["t_done_ms"] for k in range(len(st) - 1))
+    for k in range(len(reqs)):
+        assert same_modes(got[k], refs[k]), f"request {k}"
 
 
 def test_server_admits_by_footprint(ctd):
@@ -177,10 +205,12 @@ def test_server_admits_by_footprint(ctd):
             srv.submit(a, nsteps=1)
 
 
-def test_nonfinite_input_fails_alone(ctd):
+@pytest.mark.parametrize("lockstep", [True, False])
+def test_nonfinite_input_fails_alone(ctd, lockstep):
     """A request whose initial factors hold a NaN ends with ENONFINITE (the
     kernels run normally on it); the requests served beside it complete and
-    equal their standalone runs."""
+    equal their standalone runs (on the lockstep route the failing request
+    leaves the running set and the others go on)."""
     good = small_instance(dim=2, n=40, m0=3, kmax=4, seed=5, max_modes=12)
     bad_f = [f.copy() for f in good.factors]
     bad_f[1][7, 0] = float("nan")
@@ -190,7 +220,7 @@ def test_nonfinite_input_fails_alone(ctd):
             s.step(1)
         assert "NONFINITE" in str(ei.value)
     ref = standalone(ctd, good, 2, precision="fp64")
-    with ctd.Server(workers=2) as srv:
+    with ctd.Server(workers=2, lockstep=lockstep) as srv:
         tb = srv.submit(bad, nsteps=2, precision="fp64")
         tg = srv.submit(good, nsteps=2, precision="fp64")
         # waiting on a failed request returns its error
