@@ -11,7 +11,11 @@
 // eigenvectors Q of C = L^-1 K L^-T, C = Q diag(mu) Q^T.  C is reduced to
 // tridiagonal form by Householder reflections (accumulated into Q) and the
 // tridiagonal problem is solved by the implicit QL iteration with shifts
-// from the leading 2 x 2 block, its plane rotations applied to Q.
+// from the leading 2 x 2 block, its plane rotations applied to Q.  Both steps
+// are the published methods (Householder reduction of a symmetric matrix to
+// tridiagonal form; the QL algorithm with implicit shifts of Bowdler,
+// Martin, Reinsch and Wilkinson, Numer. Math. 11 (1968), the procedure
+// EISPACK distributes as tql2), written here for this use.
 #include "ctd_internal.h"
 
 #include <algorithm>
@@ -117,8 +121,11 @@ void tridiagonalize(int n, std::vector<double>& C, std::vector<double>& d, std::
   }
 }
 
-// Implicit QL on the tridiagonal (d, e); rotations update the rows of Qt
-// (columns of Q).  On return d holds the eigenvalues.
+// Implicit QL on the tridiagonal (d, e) (Bowdler, Martin, Reinsch and
+// Wilkinson 1968; EISPACK tql2): deflate at the first negligible
+// off-diagonal, shift by the eigenvalue of the leading 2 x 2 block nearer its
+// corner, chase the bulge with plane rotations; the rotations update the rows
+// of Qt (columns of Q).  On return d holds the eigenvalues.
 bool tridiag_ql(int n, std::vector<double>& d, std::vector<double>& e, std::vector<double>& Qt) {
   const double eps = std::numeric_limits<double>::epsilon();
   for (int l = 0; l < n; ++l) {
