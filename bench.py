@@ -285,7 +285,8 @@ def ac3d_n256_leg(ctd, steps=100):
     return out
 
 
-def batched_leg(ctd, count=512, steps=2, workers=8, init="warm", sample=(0, 255, 511)):
+def batched_leg(ctd, count=512, steps=2, workers=8, init="warm", sample=(0, 255, 511),
+                executors=("lockstep", "streams")):
     """Instance-steps/s of the uneven 2D batch (the batch2d_512 instances)
     under both executors: lockstep rounds of multi-instance launches, and
     the pool of worker streams.  Sampled instances of the lockstep run are
@@ -298,7 +299,7 @@ def batched_leg(ctd, count=512, steps=2, workers=8, init="warm", sample=(0, 255,
            "nodes_min": min(int(i.nodes[0]) for i in insts),
            "nodes_max": max(int(i.nodes[0]) for i in insts)}
     kept = {}
-    for ex in ("lockstep", "streams"):
+    for ex in executors:
         b = ctd.Batch(insts, precision="mixed", init=init)
         b.set_mode(ex)
         b.set_workers(workers)
@@ -320,7 +321,7 @@ def batched_leg(ctd, count=512, steps=2, workers=8, init="warm", sample=(0, 255,
             s.step(steps)
             ra, rf = s.modes()
         same = same and np.array_equal(amp, ra) and all(np.array_equal(x, y) for x, y in zip(fac, rf))
-    out["sampled_equal_standalone"] = bool(same)
+    out["sampled_equal_standalone"] = bool(same) if kept else None
     return out
 
 
@@ -574,6 +575,10 @@ def main():
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--requests", type=int, default=64,
                     help="requests of the served workload for --only served_load")
+    ap.add_argument("--batch-steps", type=int, default=2,
+                    help="steps of every instance in --only batched")
+    ap.add_argument("--batch-executors", default="lockstep,streams",
+                    help="executors of the batched leg run by --only batched (comma-separated)")
     ap.add_argument("--no-lockstep", action="store_true",
                     help="served workload: every request on the worker-stream route")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="MIB",
@@ -601,7 +606,9 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     if args.only:
-        legs = {"actd": lambda c: actd_leg(c), "batched": lambda c: batched_leg(c, init=args.init),
+        legs = {"actd": lambda c: actd_leg(c),
+                "batched": lambda c: batched_leg(c, init=args.init, steps=args.batch_steps,
+                                                 executors=tuple(args.batch_executors.split(","))),
                 "served": lambda c: served_leg(c, init=args.init),
                 "ps": lambda c: ps_sweep_leg(c, init=args.init),
                 "ac2d": lambda c: ac2d_leg(c), "ac3d_n256": lambda c: ac3d_n256_leg(c),

@@ -78,17 +78,23 @@ enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
  *   <= enrich_tol, or at max_modes (the cap of the adaptive variant).
  * Zero values of dilation_a, gauss_points, fp_tol, fp_max_iter select the
  * defaults 12, 5, 1e-2, 20 (ctd_problem_default fills everything).
- * actd (2D only, Sec. 3.3 adaptive algorithm): nonzero makes max_modes the
- *   critical mode count M_c of the hybrid CTD/CFE scheme: a step whose
- *   enrichment reaches max_modes with the last mode still above enrich_tol
- *   drops its modes and is computed by the full tensor-product CFE solve of
- *   the same scheme from u^k (exact, by the generalised eigenbases of
- *   (K_d, M_d)).  Its result u^{k+1} is held as nodes[1] modes (column j of
- *   the nodal field times the nodal unit vector j of axis 1, amplitude 1),
- *   which is the field itself, so the next step's CTD sees the same u^k.
- *   Needs nodes[d] <= 2048; the set-up computes both axes' eigenbases on the
- *   host (O(n^3)) and the device footprint holds nodes[1] modes of u^k.
- *   3D: CTD_EUNSUPPORTED.
+ * actd (Sec. 3.3 adaptive algorithm; Sec. 4.2 uses it in 3D): nonzero
+ *   makes max_modes the critical mode count M_c of the hybrid CTD/CFE
+ *   scheme: a step whose enrichment reaches max_modes with the last mode
+ *   still above enrich_tol drops its modes and is computed by the full
+ *   tensor-product CFE solve of the same scheme from u^k (exact, by the
+ *   generalised eigenbases of (K_d, M_d)); the next step's CTD starts from
+ *   that field.  2D: u^{k+1} is held as nodes[1] modes (column j of the
+ *   nodal field times the nodal unit vector j of axis 1, amplitude 1), which
+ *   is the field itself.  3D: u^{k+1} is held as the nodal tensor (a field
+ *   state with no modes: the warm guess falls back to the counter-based
+ *   vector); the next step's integrals of u^k come from the tensor
+ *   c M3 U - int N w(U) on the tensor Gauss grid, formed once per step.
+ *   Needs nodes[d] <= 2048, in 3D also at most 2^30 tensor Gauss points
+ *   (about 200 nodes per axis); the set-up computes the axes' eigenbases on
+ *   the host (O(n^3)); the device footprint holds nodes[1] modes of u^k
+ *   (2D) or the field, its right-hand-side tensor and two Gauss-grid
+ *   buffers (3D).
  * dev_alloc / dev_free / alloc_ctx: optional device allocator (both set or
  *   both NULL).  dev_alloc(bytes, hip_stream, ctx) returns device memory
  *   usable in stream order on hip_stream (NULL = out of memory ->
@@ -137,7 +143,9 @@ typedef struct ctd_step_info {
   int32_t fp_unconverged;   /* modes that hit fp_max_iter */
   int32_t zero_mode;        /* 1 if a zero-amplitude mode ended the step */
   int32_t energy_increase;  /* 1 if energy rose by more than 1e-12 relative */
-  int32_t full_solve;       /* 1 if the step was the full CFE solve (actd) */
+  int32_t full_solve;       /* 1 if the step was the full CFE solve (actd);
+                               modes is then nodes[1] (2D) or 0 (3D field
+                               state) */
   int32_t stability_warning;/* 1 if alpha < max(w')/2 = 4 a0: the energy law of
                                App. A is not guaranteed (Sec. 2.5)          */
   double energy;            /* E(u^{k+1}) if energy_each_step, else NaN */
@@ -189,7 +197,10 @@ int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device,
  * may be NULL to query *m only.  cap < *m with a buffer given: CTD_EINVAL.
  * Factors are unit in the M_d norm except along axis 0, which carries the
  * sign; amp >= 0.  Together with ctd_get_step_index this is a checkpoint:
- * ctd_init(p, m, out, amp, ...) and ctd_set_step_index resume the run. */
+ * ctd_init(p, m, out, amp, ...) and ctd_set_step_index resume the run.  A
+ * 3D field state (actd) is written as nodes[1] nodes[2] modes: mode
+ * j nodes[2] + k = U[:, j, k] times the unit vectors e_j and e_k, amplitude
+ * 1. */
 int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out,
                   int32_t cap);
 
@@ -397,7 +408,7 @@ enum {
                           diagonalisation solve (fused into the cyclic
                           reduction kernel otherwise)                     */
   CTD_K_FULL_SOLVE,    /* full CFE step of actd: dense products in the
-                          eigenbases (2D, FP64 MFMA)                      */
+                          eigenbases (FP64 MFMA)                          */
   CTD_K_SKIPPED,       /* launches of a sweep enqueued ahead of the host's
                           decision, after which the mode had ended: they
                           returned at once (any class; timed when the

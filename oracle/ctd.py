@@ -46,16 +46,25 @@ from .hashinit import init_vector
 
 @dataclass
 class State:
-    """Separated field u = sum_m sigma_m prod_d X_d[:, m] (nodal coefficients)."""
+    """Separated field u = sum_m sigma_m prod_d X_d[:, m] (nodal coefficients).
+
+    warm: how many of its modes a following step may take as warm initial
+    guesses (None: all of them; a 3D field state holds none, see
+    oracle.actd.field_state)."""
     sigma: np.ndarray
     factors: list
+    warm: int | None = None
 
     @property
     def modes(self):
         return len(self.sigma)
 
+    @property
+    def warm_modes(self):
+        return self.modes if self.warm is None else self.warm
+
     def copy(self):
-        return State(self.sigma.copy(), [f.copy() for f in self.factors])
+        return State(self.sigma.copy(), [f.copy() for f in self.factors], self.warm)
 
 
 def state_from_instance(inst) -> State:
@@ -250,7 +259,7 @@ def ctd_step(prob, state_k: State, step_index: int, replay=None,
     log = StepLog()
     max_modes = prob.max_modes if replay is None else len(replay)
     for mode in range(max_modes):
-        if prob.init == "warm" and mode < state_k.modes:
+        if prob.init == "warm" and mode < state_k.warm_modes:
             u = [state_k.factors[d][:, mode].copy() for d in range(D)]
         else:
             u = [init_vector(prob.seed, step_index, mode, d, ax[d].n)

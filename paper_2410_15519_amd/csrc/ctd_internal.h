@@ -105,6 +105,11 @@ struct DevInst {
   // returns at once when sc->done is set
   int spec_nsw;
   int spec_check;
+  // 3D field state (adaptive algorithm, after a full solve): u^k is the
+  // nodal tensor, the load of a directional solve is fparts chunks of the
+  // contraction of R3 (0: u^k is separated)
+  int fparts;
+  const double* R3;
   double c, lam, omega, a0, kappa;
   double fp_tol, enrich_tol;
   int max_modes;
@@ -233,6 +238,31 @@ struct GemmArgs {
 hipError_t launch_gemm64(const GemmArgs& g, hipStream_t st);
 int gemm64_blocks(int m, int n);
 hipError_t launch_unit_columns(double* X, int n, int ncols, hipStream_t st);   // X[:, m] = e_m
+// 3D field state (actd.hip): passes of a row-major (d0, d1, d2) tensor along
+// one axis -- Phi (nodes to Gauss points), Phi^T, a banded symmetric matrix,
+// the eigenvector products of the full solve -- and the pointwise steps.
+hipError_t launch_field_phi(const double* in, double* out, const int* dims, int a, const DevAxis& A,
+                            hipStream_t st);
+hipError_t launch_field_phit(const double* in, double* out, const int* dims, int a, const DevAxis& A,
+                             hipStream_t st);
+hipError_t launch_field_band(const double* in, double* out, const int* dims, int a, const double* band,
+                             int n, int B, hipStream_t st);
+hipError_t launch_field_integrand(double* G, const int* qdims, const double* w0, const double* w1,
+                                  const double* w2, double omega, double a0, double* part,
+                                  hipStream_t st);
+int64_t field_partials(int64_t total);
+hipError_t launch_field_axpby(double* R, const double* MU, const double* T, double c, int64_t total,
+                              hipStream_t st);
+hipError_t launch_field_dot(const double* x, const double* y, int64_t total, double* part, hipStream_t st);
+hipError_t launch_field_fd_div(double* T, const int* dims, const double* mu0, const double* mu1,
+                               const double* mu2, double c, double lam, hipStream_t st);
+// skip: a device flag; the launch returns at once when it is set (nullptr: never)
+hipError_t launch_field_contract(const double* R, const int* dims, int d, const double* u0, const double* u1,
+                                 const double* u2, int P, double* out, const int* skip, hipStream_t st);
+hipError_t launch_field_eig(const double* X, double* Y, const int* dims, int a, const double* V, int forward,
+                            hipStream_t st);
+hipError_t launch_field_to_f32(const double* X, float* Y, int64_t total, hipStream_t st);
+constexpr int kFieldParts = 8;   // load chunks of a directional solve from a 3D field state
 hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();

@@ -670,7 +670,8 @@ static int rhs_linear_chunks(const DevInst& I, int M, int load_only) {
 }
 
 int rhs_load_chunks(const DevInst& I, int d) {
-  return I.dim == 2 ? (I.ax[1 - d].n + 63) / 64 : 1;
+  if (I.dim == 2) return (I.ax[1 - d].n + 63) / 64;
+  return I.fparts > 0 ? I.fparts : 1;
 }
 
 int rhs_chunks(const DevInst& I, int d, int M, int load_only) {
@@ -680,6 +681,19 @@ int rhs_chunks(const DevInst& I, int d, int M, int load_only) {
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only) {
   const DevAxis& A = I.ax[d];
   const int nchunk = rhs_linear_chunks(I, M, load_only);
+  if (I.dim == 3 && I.fparts > 0) {
+    // 3D field state: the linear chunks of the new modes, then the load
+    // chunks from the contraction of R3 with the other directions' factors
+    if (nchunk > 0) {
+      dim3 grid((A.n + 63) / 64, nchunk);
+      k_rhs<<<grid, 256, 0, st>>>(I, d, M, load_only, nchunk);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    const int dims[3] = {I.ax[0].n, I.ax[1].n, I.ax[2].n};
+    return launch_field_contract(I.R3, dims, d, I.ax[0].u, I.ax[1].u, I.ax[2].u, I.fparts,
+                                 A.rpart + (size_t)nchunk * A.n, I.spec_check ? &I.sc->done : nullptr, st);
+  }
   dim3 grid((A.n + 63) / 64, nchunk + rhs_load_chunks(I, d));
   // h (qcount) and the Phi rows (qcount x SW) of the elements around a row block
   const size_t shm = sizeof(double) * (size_t)(64 + 2 * A.SW + 2) * A.ng * (1 + A.SW);
@@ -1597,15 +1611,29 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
   const int b = blockIdx.x;
   int rank, split, t;
   bool rep;
+  // Workgroups go round-robin over the 8 XCDs (b % 8).  With split counts
+  // that are multiples of 8, XCD x takes splits [x n/8, (x+1) n/8) of every
+  // triple, so each XCD's L2 holds only its eighth of the Gauss-point tables
+  // (every triple of a split reads the same point range).
+  auto place = [&](int bb, int ntr, int nsp) {
+    if ((nsp & 7) == 0) {
+      const int x = b & 7, idx = bb >> 3;
+      rank = idx % ntr;
+      split = x * (nsp >> 3) + idx / ntr;
+    } else {
+      rank = bb % ntr;
+      split = bb / ntr;
+    }
+  };
   if (b < nd * I.nsplit_g) {
-    rank = b % nd;
-    split = b / nd;
+    place(b, nd, I.nsplit_g);
     rep = false;
     t = I.tlist[rank];
   } else {
+    // the XCD of b is that of b2 when the distinct block count is a multiple of 8
     const int b2 = b - nd * I.nsplit_g;
-    rank = b2 % np;
-    split = b2 / np;
+    if (((nd * I.nsplit_g) & 7) == 0) place(b2, np, I.nsplit_p);
+    else { rank = b2 % np; split = b2 / np; }
     rep = true;
     t = I.tlist_p[rank];
   }
@@ -2813,7 +2841,13 @@ hipError_t configure_kernels() {
                       (const void*)k_cubic_h<double>,
                       (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
                       (const void*)k_reconstruct_tile<double>, (const void*)k_reconstruct_mfma<float>,
-                      (const void*)k_reconstruct_mfma<double>};
+                      (const void*)k_reconstruct_mfma<double>,
+                      (const void*)k_solve_bcr_m<3, 0>, (const void*)k_solve_bcr_m<5, 0>,
+                      (const void*)k_solve_bcr_m<7, 0>, (const void*)k_solve_bcr_m<3, 2>,
+                      (const void*)k_solve_bcr_m<5, 2>, (const void*)k_solve_bcr_m<7, 2>,
+                      (const void*)k_finalize_init_m<3>, (const void*)k_finalize_init_m<5>,
+                      (const void*)k_finalize_init_m<7>, (const void*)k_finalize<3>,
+                      (const void*)k_finalize<5>, (const void*)k_finalize<7>};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipGetLastError();

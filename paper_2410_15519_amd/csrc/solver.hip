@@ -157,7 +157,17 @@ struct ctd_solver {
   double* KXk[kMaxDim] = {};       // K X^k (energy of u^k)
   int Mk = 0, Mcap = 0, Mkp_max = 0, ntri_max = 0;
   int Mcap_ctd = 0;                // modes of a CTD state (max_modes, initial count)
-  bool actd = false;               // full CFE solve past the mode cap (2D)
+  bool actd = false;               // full CFE solve past the mode cap (2D and 3D)
+  // 3D field state of actd: u^k is the nodal tensor U3 (row-major n0 x n1 x
+  // n2), R3 the step's right-hand-side tensor c (M0 (x) M1 (x) M2) U3 minus
+  // the integrated w, G3a / G3b Gauss-grid work buffers, energy_field the
+  // energy of the field state (computed with R3)
+  bool field3 = false;
+  double* U3 = nullptr;
+  double* R3 = nullptr;
+  double* G3a = nullptr;
+  double* G3b = nullptr;
+  double energy_field = std::numeric_limits<double>::quiet_NaN();
   double* fsQ = nullptr;           // n0 x n1 temporaries of the full solve
   double* fsT = nullptr;
   int nsplit_g_cap = 0;
@@ -288,8 +298,18 @@ int validate(const ctd_problem* p, std::string& err) {
     if (!(p->S >= 0) || !std::isfinite(p->S)) { err = "S must be >= 0"; return CTD_EINVAL; }
   }
   if (p->actd) {
-    if (p->dim != 2) { err = "actd (full CFE solve past the mode cap) is 2D only"; return CTD_EUNSUPPORTED; }
-    if (p->nodes[0] > 2048 || p->nodes[1] > 2048) { err = "actd needs nodes <= 2048 per axis"; return CTD_EUNSUPPORTED; }
+    for (int d = 0; d < p->dim; ++d)
+      if (p->nodes[d] > 2048) { err = "actd needs nodes <= 2048 per axis"; return CTD_EUNSUPPORTED; }
+    if (p->dim == 3) {
+      // the full step and the field state work on the tensor Gauss grid
+      const double ng = p->gauss_points > 0 ? p->gauss_points : 5;
+      double q = 1.0;
+      for (int d = 0; d < 3; ++d) q *= ng * (p->nodes[d] - 1);
+      if (q > (double)(1u << 30)) {
+        err = "actd in 3D needs at most 2^30 tensor Gauss points (about 200 nodes per axis at 5 points)";
+        return CTD_EUNSUPPORTED;
+      }
+    }
   }
   if (p->patch_s < 1 || p->patch_s > 3) { err = "patch_s must be 1, 2 or 3"; return CTD_EINVAL; }
   if (p->poly_p < 0 || p->poly_p > p->patch_s) { err = "need 0 <= poly_p <= patch_s"; return CTD_EINVAL; }
@@ -415,11 +435,22 @@ void fp32_g_splits(ctd_solver* s, int nq, int forced) {
   // the kernel spreads each axis' Gauss points over these split counts
   I.nsplit_g = (nq + pd - 1) / pd;
   I.nsplit_p = nsp;
+  // a multiple of 8 distinct splits: the repeated-tile triples take the same
+  // point ranges, so that each XCD reads one eighth of the tables (kernel
+  // placement), when the workgroups still fit one resident round and the
+  // partial buffer
+  if (I.nsplit_g % 8 == 0 && I.nsplit_g != nsp) {
+    const double wgs = (double)nd * I.nsplit_g + (double)I.ntri_p * I.nsplit_g;
+    const double floats = (double)nd * I.nsplit_g * 4096.0 + (double)I.ntri_p * I.nsplit_g * 2304.0;
+    if (wgs <= slots && floats <= (double)s->nsplit_g_cap * 4096.0) I.nsplit_p = I.nsplit_g;
+  }
 }
 
 void update_view(ctd_solver* s) {
   DevInst& I = s->I;
   I.Mk = s->Mk;
+  I.fparts = s->field3 ? kFieldParts : 0;
+  I.R3 = s->R3;
   I.Mkp = std::max(kTile, round_up(s->Mk, kTile));
   I.nb = I.Mkp / kTile;
   I.ntri = tri_count(I.nb);
@@ -484,10 +515,11 @@ int alloc_instance(ctd_solver* s, int m0) {
   DeviceArena& A = s->arena;
   DevInst& I = s->I;
   const bool mixed = s->P.precision == CTD_PREC_MIXED;
-  s->actd = s->P.actd != 0 && s->dim == 2;
+  s->actd = s->P.actd != 0;
   s->Mcap_ctd = std::max(s->P.max_modes, m0);
-  // a field state from the full solve holds one mode per node of axis 1
-  s->Mcap = s->actd ? std::max(s->Mcap_ctd, s->ax[1].n) : s->Mcap_ctd;
+  // a 2D field state from the full solve holds one mode per node of axis 1
+  // (a 3D one is held as a tensor)
+  s->Mcap = s->actd && s->dim == 2 ? std::max(s->Mcap_ctd, s->ax[1].n) : s->Mcap_ctd;
   s->Mkp_max = std::max(kTile, round_up(s->Mcap, kTile));
   const int nbmax = s->Mkp_max / kTile;
   s->ntri_max = tri_count(nbmax);
@@ -541,7 +573,7 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.rhs, sizeof(double) * n);
     // RHS partials: linear column chunks, then the load chunks (2D: the
     // columns of the M_xy product, 64 per chunk)
-    const size_t nload = s->dim == 2 ? (size_t)(s->ax[1 - d].n + 63) / 64 : 1;
+    const size_t nload = s->dim == 2 ? (size_t)(s->ax[1 - d].n + 63) / 64 : (s->actd ? kFieldParts : 1);
     AL(X.rpart, sizeof(double) * n * ((size_t)(3 * s->Mcap + 63) / 64 + nload));
     AL(X.v, sizeof(double) * nqp);
     if (mixed) AL(X.vf, sizeof(float) * nqp);
@@ -624,6 +656,20 @@ int alloc_instance(ctd_solver* s, int m0) {
   if (s->dim == 2)
     s->energy_partial_cap = std::max<size_t>(s->energy_partial_cap,
                                              (size_t)gemm64_blocks(s->ax[0].nq, s->ax[1].nq) + 16);
+  if (s->dim == 3 && s->actd) {
+    size_t nn = 1, qq = 1;
+    for (int d = 0; d < 3; ++d) {
+      nn *= (size_t)s->ax[d].n;
+      qq *= (size_t)s->ax[d].nq;
+    }
+    AL(s->U3, sizeof(double) * nn);
+    AL(s->R3, sizeof(double) * nn);
+    // G3a also holds two n^3 products of the right-hand side (field_rhs)
+    AL(s->G3a, sizeof(double) * std::max(2 * nn, qq));
+    AL(s->G3b, sizeof(double) * std::max(nn, qq));
+    s->energy_partial_cap = std::max<size_t>(s->energy_partial_cap,
+                                             (size_t)field_partials((int64_t)std::max(nn, qq)) + 16);
+  }
   AL(s->energy_partial, sizeof(double) * s->energy_partial_cap);
   {
     // directional solve per axis: fast diagonalisation (eigenvectors shared
@@ -685,8 +731,11 @@ int alloc_instance(ctd_solver* s, int m0) {
 }
 
 // Gauss-point tables of u^k and, on the 2D route, M_xy (frozen for the step).
+int field_rhs(ctd_solver* s, bool energy);
+
 int precompute(ctd_solver* s) {
   update_view(s);
+  if (s->field3) return field_rhs(s, true);
   for (int d = 0; d < s->dim; ++d) {
     Work w = w_quad(s, d);
     LAUNCH(s, CTD_K_QUAD, w.flops, w.bytes, launch_quad_eval(s->I, d, s->stream));
@@ -706,7 +755,7 @@ int read_scalars(ctd_solver* s) {
 
 // g_d of the freshly finalised factor u_d and S for the next solve direction.
 int cubic_after(ctd_solver* s, int d, int next) {
-  if (s->dim != 3) return CTD_OK;
+  if (s->dim != 3 || s->field3) return CTD_OK;
   int other = -1;
   if (next >= 0)
     for (int e = 0; e < 3; ++e)
@@ -718,6 +767,12 @@ int cubic_after(ctd_solver* s, int d, int next) {
 }
 
 int energy_of_uk(ctd_solver* s, double* E) {
+  if (s->field3) {
+    // computed with the field state's right-hand side (field_rhs)
+    *E = s->energy_field;
+    HIPCHK(s, sync_collect(s));
+    return CTD_OK;
+  }
   // view on u^k: factor buffers X^k, M X^k, K X^k and amplitudes sk
   DevInst V = s->I;
   for (int d = 0; d < s->dim; ++d) {
@@ -786,6 +841,116 @@ int finish_step(ctd_solver* s, int M) {
   std::swap(I.sk, I.sn);
   s->Mk = M;
   return precompute(s);
+}
+
+// Right-hand-side tensor of a 3D field state U3 (Sec. 3.3 adaptive
+// algorithm; the 3D counterpart of c M_0 U M_1 - M_xy):
+//   R3 = c (M_0 (x) M_1 (x) M_2) U3 - int N~ (x) N~ (x) N~ omega (u^3 - u),
+// the integral on the tensor Gauss grid (Phi along each axis, the integrand
+// at every point, Phi^T along each axis).  With energy, also the field's
+// energy (Sec. 2.1): a0 sum_q W (u^2 - 1)^2 + kappa/2 sum_d U3 . (K_d (x)
+// M (x) M) U3.
+int field_rhs(ctd_solver* s, bool energy) {
+  const DevInst& I = s->I;
+  int dims[3] = {I.ax[0].n, I.ax[1].n, I.ax[2].n};
+  const int64_t nn = (int64_t)dims[0] * dims[1] * dims[2];
+  double* a = s->G3a;
+  double* b = s->G3b;
+  // Gauss-grid values: axis 2, 1, 0 in turn
+  int cur[3] = {dims[0], dims[1], dims[2]};
+  const double* src = s->U3;
+  for (int ax = 2; ax >= 0; --ax) {
+    double* dst = (ax % 2 == 0) ? a : b;
+    HIPCHK(s, launch_field_phi(src, dst, cur, ax, I.ax[ax], s->stream));
+    cur[ax] = I.ax[ax].nq;
+    src = dst;
+  }
+  // src == a: the Gauss-point values; integrand (and quartic energy) in place
+  const int64_t nqq = (int64_t)cur[0] * cur[1] * cur[2];
+  const int64_t npart = field_partials(nqq);
+  HIPCHK(s, launch_field_integrand(a, cur, I.ax[0].w, I.ax[1].w, I.ax[2].w, s->omega, s->a0,
+                                   energy ? s->energy_partial : nullptr, s->stream));
+  double quart = 0.0;
+  if (energy) {
+    std::vector<double> part((size_t)npart);
+    HIPCHK(s, hipMemcpyAsync(part.data(), s->energy_partial, sizeof(double) * npart, hipMemcpyDeviceToHost,
+                             s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (double v : part) quart += v;
+  }
+  // back to the nodes: axis 0, 1, 2 in turn (a -> b -> a -> b)
+  src = a;
+  for (int ax = 0; ax < 3; ++ax) {
+    double* dst = (ax % 2 == 0) ? b : a;
+    HIPCHK(s, launch_field_phit(src, dst, cur, ax, I.ax[ax], s->stream));
+    cur[ax] = I.ax[ax].n;
+    src = dst;
+  }
+  // src == b: the integrated w; c M3 U into a, then R3 = c M3 U - b
+  // (a holds the n^3 partial products; its first nn entries are free now)
+  double* t0 = a;
+  double* t1 = a + nn;
+  HIPCHK(s, launch_field_band(s->U3, t0, dims, 0, I.ax[0].Mb, dims[0], I.ax[0].B, s->stream));
+  HIPCHK(s, launch_field_band(t0, t1, dims, 1, I.ax[1].Mb, dims[1], I.ax[1].B, s->stream));
+  HIPCHK(s, launch_field_band(t1, t0, dims, 2, I.ax[2].Mb, dims[2], I.ax[2].B, s->stream));
+  HIPCHK(s, launch_field_axpby(s->R3, t0, b, s->c, nn, s->stream));
+  if (energy) {
+    // gradient part: sum_d U . (K_d (x) M_e (x) M_f) U
+    double grad = 0.0;
+    const int64_t np2 = field_partials(nn);
+    std::vector<double> part((size_t)np2);
+    for (int d = 0; d < 3; ++d) {
+      const double* in = s->U3;
+      double* bufs[2] = {t0, t1};
+      for (int ax = 0; ax < 3; ++ax) {
+        double* out = bufs[ax % 2];
+        HIPCHK(s, launch_field_band(in, out, dims, ax, ax == d ? I.ax[ax].Kb : I.ax[ax].Mb, dims[ax],
+                                    I.ax[ax].B, s->stream));
+        in = out;
+      }
+      HIPCHK(s, launch_field_dot(s->U3, in, nn, s->energy_partial, s->stream));
+      HIPCHK(s, hipMemcpyAsync(part.data(), s->energy_partial, sizeof(double) * np2, hipMemcpyDeviceToHost,
+                               s->stream));
+      HIPCHK(s, hipStreamSynchronize(s->stream));
+      double g = 0.0;
+      for (double v : part) g += v;
+      grad += g;
+    }
+    s->energy_field = quart + 0.5 * s->kappa * grad;
+  }
+  return CTD_OK;
+}
+
+// Full CFE step of the adaptive algorithm in 3D: u^{k+1} of the tensor-
+// product system (c M3 + lam (K_0 (x) M (x) M + M (x) K_1 (x) M + M (x) M (x)
+// K_2)) u = R3, exactly, in the eigenbases of (K_d, M_d):
+//   U' = (V_0 (x) V_1 (x) V_2) [((V_0 (x) V_1 (x) V_2)^T R3) / (c + lam (mu_0i + mu_1j + mu_2k))].
+// From a separated u^k its field is formed first (and R3 from it); a field
+// state's R3 is the step's own.  The result is the new field state.
+int full_step_3d(ctd_solver* s) {
+  const DevInst& I = s->I;
+  int dims[3] = {I.ax[0].n, I.ax[1].n, I.ax[2].n};
+  if (!s->field3) {
+    DevInst V = s->I;
+    for (int d = 0; d < 3; ++d) V.ax[d].X = s->I.ax[d].Xk;
+    V.sn = s->I.sk;
+    HIPCHK(s, launch_reconstruct(V, s->Mk, s->U3, CTD_DTYPE_F64, s->stream));
+    int rc = field_rhs(s, false);
+    if (rc) return rc;
+  }
+  double* a = s->G3a;
+  double* b = s->G3b;
+  const double n3 = (double)dims[0] * dims[1] * dims[2];
+  const double fl = 2.0 * n3 * (dims[0] + dims[1] + dims[2]);
+  LAUNCH(s, CTD_K_FULL_SOLVE, fl, 8.0 * n3 * 2, launch_field_eig(s->R3, a, dims, 0, I.ax[0].fdV, 1, s->stream));
+  LAUNCH(s, CTD_K_FULL_SOLVE, 0.0, 0.0, launch_field_eig(a, b, dims, 1, I.ax[1].fdV, 1, s->stream));
+  LAUNCH(s, CTD_K_FULL_SOLVE, 0.0, 0.0, launch_field_eig(b, a, dims, 2, I.ax[2].fdV, 1, s->stream));
+  HIPCHK(s, launch_field_fd_div(a, dims, I.ax[0].fdmu, I.ax[1].fdmu, I.ax[2].fdmu, s->c, s->lam, s->stream));
+  LAUNCH(s, CTD_K_FULL_SOLVE, fl, 8.0 * n3 * 2, launch_field_eig(a, b, dims, 0, I.ax[0].fdV, 0, s->stream));
+  LAUNCH(s, CTD_K_FULL_SOLVE, 0.0, 0.0, launch_field_eig(b, a, dims, 1, I.ax[1].fdV, 0, s->stream));
+  LAUNCH(s, CTD_K_FULL_SOLVE, 0.0, 0.0, launch_field_eig(a, s->U3, dims, 2, I.ax[2].fdV, 0, s->stream));
+  s->field3 = true;
+  return CTD_OK;
 }
 
 // Full CFE step of the adaptive algorithm (2D): u^{k+1} of the tensor-product
@@ -899,7 +1064,7 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
     // Grams of every direction but the last
     auto sweep = [&](int it) -> int {
       for (int d = 0; d < D; ++d) {
-        if (D == 3) {
+        if (D == 3 && !s->field3) {
           Work w = w_cubic(s, d);
           LAUNCH(s, CTD_K_CUBIC_H, w.flops, w.bytes, launch_cubic_h(s->I, d, s->stream));
         }
@@ -1012,10 +1177,16 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
   }
   // adaptive algorithm: a step that needs more than M_c modes is the full solve
   const bool full = full_replay || (s->actd && capped);
-  if (full) {
+  if (full && D == 3) {
+    int rc = full_step_3d(s);
+    if (rc) return rc;
+    M = 0;
+  } else if (full) {
     int rc = full_step_2d(s);
     if (rc) return rc;
     M = s->ax[1].n;
+  } else {
+    s->field3 = false;   // a CTD step's u^{k+1} is separated
   }
   int rc = finish_step(s, M);   // M == 0: the zero field
   if (rc) return rc;
@@ -1667,7 +1838,14 @@ int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device,
     HIPCHK(s, s->arena.raw_alloc(&tmp, bytes));
     dst = tmp;
   }
-  hipError_t e = launch_reconstruct(V, s->Mk, dst, dtype, s->stream);
+  hipError_t e;
+  if (s->field3) {
+    // a 3D field state is the nodal tensor itself
+    e = dtype == CTD_DTYPE_F64 ? hipMemcpyAsync(dst, s->U3, bytes, hipMemcpyDeviceToDevice, s->stream)
+                               : launch_field_to_f32(s->U3, (float*)dst, (int64_t)total, s->stream);
+  } else {
+    e = launch_reconstruct(V, s->Mk, dst, dtype, s->stream);
+  }
   std::vector<unsigned char> host;
   if (e == hipSuccess && !contiguous && on_device)
     e = launch_scatter_strided(tmp, out, (int)esz, s->dim, n, strides, s->stream);
@@ -1700,6 +1878,31 @@ int ctd_reconstruct(ctd_solver* s, void* out, int32_t dtype, int32_t on_device,
 
 int ctd_get_modes(ctd_solver* s, int32_t* m, double* amp, double* const* out, int32_t cap) {
   if (!s || !m) return CTD_EINVAL;
+  if (s->field3) {
+    // a 3D field state in separated form: mode j n2 + k = U[:, j, k] (x) e_j (x) e_k
+    const int n0 = s->ax[0].n, n1 = s->ax[1].n, n2 = s->ax[2].n;
+    const int64_t mf = (int64_t)n1 * n2;
+    if (mf > INT32_MAX) return s->fail(CTD_EUNSUPPORTED, "field state too large for separated form");
+    *m = (int32_t)mf;
+    if (cap < mf) return (amp || out) ? s->fail(CTD_EINVAL, "cap smaller than mode count") : CTD_OK;
+    HIPCHK(s, sync_collect(s));
+    if (amp) std::fill(amp, amp + mf, 1.0);
+    if (out && out[0]) {
+      std::vector<double> U((size_t)n0 * mf);
+      HIPCHK(s, copy_sync(s, U.data(), s->U3, sizeof(double) * U.size(), hipMemcpyDeviceToHost));
+      for (int i = 0; i < n0; ++i)
+        for (int64_t jk = 0; jk < mf; ++jk) out[0][(size_t)jk * n0 + i] = U[(size_t)i * mf + jk];
+    }
+    if (out && out[1]) {
+      std::fill(out[1], out[1] + (size_t)n1 * mf, 0.0);
+      for (int64_t jk = 0; jk < mf; ++jk) out[1][(size_t)jk * n1 + jk / n2] = 1.0;
+    }
+    if (out && out[2]) {
+      std::fill(out[2], out[2] + (size_t)n2 * mf, 0.0);
+      for (int64_t jk = 0; jk < mf; ++jk) out[2][(size_t)jk * n2 + jk % n2] = 1.0;
+    }
+    return CTD_OK;
+  }
   *m = s->Mk;
   if (cap < s->Mk) return (amp || out) ? s->fail(CTD_EINVAL, "cap smaller than mode count") : CTD_OK;
   HIPCHK(s, sync_collect(s));
@@ -1822,6 +2025,7 @@ extern "C" int ctd_tuning_current(ctd_solver* s, int32_t* nsplit_g, int32_t* nsp
 
 extern "C" int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u, double* out) {
   if (!s || !u || !out || d < 0 || d >= s->dim) return CTD_EINVAL;
+  if (s->field3) return s->fail(CTD_EUNSUPPORTED, "the separated load needs a separated state");
   const int D = s->dim;
   update_view(s);
   for (int e = 0; e < D; ++e) {

@@ -40,27 +40,45 @@ def short_name(name: str) -> str:
 
 
 def trace(db: str, title: str, cmd: str) -> str:
+    """Kernel records grouped by name and grid.  Launches of a sweep that was
+    enqueued ahead of the host's decision and returned at once (its mode had
+    ended) are counted apart: within a group, a launch shorter than a quarter
+    of the group's median is such a launch, and `avg us (ran)` is the mean of
+    the others."""
     con = sqlite3.connect(db)
-    rows = list(con.execute(
-        "select name, grid_x, grid_y, workgroup_x, count(*), avg(duration)/1000.0, "
-        "min(duration)/1000.0, max(duration)/1000.0, sum(duration)/1e6, lds_size, "
-        "vgpr_count, accum_vgpr_count, scratch_size from kernels "
-        "group by name, grid_x, grid_y order by sum(duration) desc limit 16"))
-    total = sum(r[0] for r in con.execute("select sum(duration)/1e6 from kernels"))
+    groups = collections.defaultdict(list)
+    meta = {}
+    for r in con.execute("select name, grid_x, grid_y, workgroup_x, duration, lds_size, vgpr_count, "
+                         "accum_vgpr_count, scratch_size from kernels"):
+        k = (r[0], r[1], r[2])
+        groups[k].append(r[4] / 1000.0)
+        meta[k] = (r[3], r[5], r[6], r[7], r[8])
+    total = sum(sum(v) for v in groups.values()) / 1e3
+    rows = []
+    for k, d in groups.items():
+        d.sort()
+        med = d[len(d) // 2]
+        ran = [x for x in d if x >= 0.25 * med]
+        rows.append((k, len(d), len(d) - len(ran), sum(d) / len(d), sum(ran) / max(1, len(ran)),
+                     d[0], d[-1], sum(d) / 1e3))
+    rows.sort(key=lambda r: -r[7])
     out = [f"# {title}", "", "Command (run from the repository root on one MI355X):", "",
            "```", cmd, "```", "",
            "Summary of the rocpd database it wrote: kernel records grouped by name and grid "
-           "(grid in work-items, durations in microseconds).", "",
+           "(grid in work-items, durations in microseconds).  `returned` counts the launches of "
+           "speculatively enqueued sweeps that returned at once (shorter than a quarter of the "
+           "group's median); `avg us (ran)` averages the other launches.", "",
            f"Total kernel time in the trace: {total:.1f} ms", "",
-           "| kernel | grid (x, y) | wg | launches | avg us | min us | max us | total ms | LDS B | VGPR | AGPR | scratch |",
-           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
-    for r in rows:
-        out.append(f"| {short_name(r[0])} | ({r[1]}, {r[2]}) | {r[3]} | {r[4]} | {r[5]:.1f} | "
-                   f"{r[6]:.1f} | {r[7]:.1f} | {r[8]:.1f} | {r[9]} | {r[10]} | {r[11]} | {r[12]} |")
+           "| kernel | grid (x, y) | wg | launches | returned | avg us | avg us (ran) | min us | max us | total ms | LDS B | VGPR | AGPR | scratch |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k, n, nret, avg, avg_ran, mn, mx, tot in rows[:18]:
+        wg, lds, vg, ag, sc = meta[k]
+        out.append(f"| {short_name(k[0])} | ({k[1]}, {k[2]}) | {wg} | {n} | {nret} | {avg:.1f} | {avg_ran:.1f} | "
+                   f"{mn:.1f} | {mx:.1f} | {tot:.1f} | {lds} | {vg} | {ag} | {sc} |")
     by_name = collections.defaultdict(lambda: [0, 0.0])
-    for name, n, tot in con.execute("select name, count(*), sum(duration)/1e6 from kernels group by name, grid_x, grid_y"):
-        by_name[short_name(name)][0] += n
-        by_name[short_name(name)][1] += tot
+    for (name, _, _), d in groups.items():
+        by_name[short_name(name)][0] += len(d)
+        by_name[short_name(name)][1] += sum(d) / 1e3
     out += ["", "All grids of a kernel together:", "",
             "| kernel | launches | avg us | total ms |", "|---|---|---|---|"]
     for name, (n, tot) in sorted(by_name.items(), key=lambda kv: -kv[1][1])[:20]:

@@ -59,10 +59,10 @@ def test_binding_struct_layout_and_validation():
     bad = ctd.make_problem(patch_s=1, poly_p=2)
     rc = ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h))
     assert rc == -1
-    # the full-solve fallback of the adaptive algorithm is 2D only
-    bad = ctd.make_problem(dim=3, actd=True)
+    # the full-solve fallback in 3D works on the tensor Gauss grid: bounded
+    bad = ctd.make_problem(dim=3, actd=True, nodes=(256, 256, 256))
     rc = ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h))
-    assert rc == -6 and not h.value and b"2D" in ctd.LIB.ctd_last_error(None)
+    assert rc == -6 and not h.value and b"Gauss points" in ctd.LIB.ctd_last_error(None)
     bad = ctd.make_problem(actd=True, nodes=(4096, 64, 64))
     assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
 
@@ -82,6 +82,9 @@ def test_footprint_query_without_device():
     assert f(small) % 256 == 0
     # actd keeps one mode per node of axis 1 for field states
     assert f(small, actd=True) > f(small)
+    # 3D actd: the field, its right-hand-side tensor and two Gauss-grid buffers
+    nq = 5 * 20
+    assert f(three, actd=True) - f(three) >= 8 * (2 * 21 ** 3 + 2 * nq ** 3)
     bad = ctd.make_problem(dim=4)
     b = ctypes.c_uint64()
     assert ctd.LIB.ctd_footprint_bytes(ctypes.byref(bad), 1, ctypes.byref(b)) == -1

@@ -147,3 +147,94 @@ def test_actd_in_batch_equals_standalone(ctd):
             amp, fac = s.modes()
         assert np.array_equal(got[i][0], amp), f"instance {i}"
         assert all(np.array_equal(x, y) for x, y in zip(got[i][1], fac)), f"instance {i}"
+
+
+# ---------------------------------------------------------------- 3D
+# The 3D fallback: the full step in the eigenbases (FP64 MFMA mode
+# products), the field state held as the nodal tensor with its right-hand-
+# side tensor R = c M3 U - int N w(U) (Gauss-grid passes), and CTD steps
+# from it (the load of a directional solve = R contracted with the other two
+# factors).  The oracle holds the field state as n1 n2 fibres and uses the
+# counter-based guess for its modes (it has no modes to warm-start from).
+
+def _inst3(n=(13, 11, 9), cap=3, kmax=3):
+    return small_instance(dim=3, n=n, m0=2, kmax=kmax, eps=0.08, dt=1e-3, max_modes=cap)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_actd3d_replay_parity(ctd, prec):
+    """Schedule full / CTD from the field state / full / CTD in 3D: every
+    step's field against the oracle's."""
+    inst = _inst3()
+    pr = problem_from_instance(inst)
+    sched = ["full", [3, 2, 2], "full", [2, 3]]
+    _, logs, fields = actd_run(pr, state_from_instance(inst), len(sched), replay=sched)
+    print(f"actd 3D replay prec={prec}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", actd=True) as s:
+        s.set_decisions(sched)
+        dec = []
+        for k, sc in enumerate(sched):
+            info = s.step(1)[0]
+            dec += s.decisions()
+            assert info["full_solve"] == (1 if sc == "full" else 0)
+            assert info["modes"] == (0 if sc == "full" else len(sc))
+            err = rel(s.reconstruct(), fields[k])
+            print(f"  step {k} ({'full' if sc == 'full' else 'ctd'}): rel l2 = {err:.3e}", flush=True)
+            assert err < TOL[prec]
+        assert dec == sched
+
+
+def test_actd3d_adaptive_decisions_and_energy(ctd):
+    """Adaptive 3D run: the switches happen where the oracle's do, the fields
+    agree, and the energy of every state (field states on the Gauss grid)
+    equals the oracle's full-grid energy and does not increase."""
+    inst = _inst3(n=(12, 10, 9), cap=3)
+    pr = problem_from_instance(inst, init="warm")
+    _, logs, fields = actd_run(pr, state_from_instance(inst), 3)
+    print(f"actd 3D adaptive: oracle decisions {decisions(logs)}", flush=True)
+    assert "full" in decisions(logs)
+    with ctd.Solver(inst, precision="fp64", actd=True, energy=True) as s:
+        infos = s.step(3)
+        assert s.decisions() == decisions(logs)
+        assert rel(s.reconstruct(), fields[-1]) < 1e-10
+        for k in range(3):
+            assert infos[k]["energy"] == pytest.approx(energy_fullgrid(pr, fields[k]), rel=1e-12)
+        assert all(infos[k + 1]["energy"] <= infos[k]["energy"] for k in range(2))
+        # the field state in separated form: n1 n2 fibres of the field
+        if infos[-1]["full_solve"]:
+            amp, fac = s.modes()
+            U = np.einsum("m,im,jm,km->ijk", amp, *fac)
+            assert np.array_equal(U, s.reconstruct())
+
+
+def test_actd3d_full_solve_residual(ctd):
+    """Two full steps at 40 x 33 x 27 nodes (ragged MFMA tiles; beyond the
+    dense oracle solve): each field must satisfy the tensor system
+    (c M3 + lam (K0 (x) M1 (x) M2 + M0 (x) K1 (x) M2 + M0 (x) M1 (x) K2)) U
+      = c M3 U^k - F(U^k),
+    F the oracle's tensor-Gauss-grid nonlinear load; the second step starts
+    from the field state of the first (its right-hand-side tensor)."""
+    inst = _inst3(n=(40, 33, 27), cap=2, kmax=5)
+    pr = problem_from_instance(inst)
+    ax = pr.axes
+
+    def apply(mats, U):
+        for d in range(3):
+            U = np.moveaxis(np.tensordot(mats[d], U, axes=([1], [d])), 0, d)
+        return U
+
+    Ms = [a.M for a in ax]
+    Uk = full_field(state_from_instance(inst))
+    with ctd.Solver(inst, precision="fp64", schedule="replay", actd=True) as s:
+        s.set_decisions(["full", "full"])
+        for k in range(2):
+            s.step(1)
+            U = s.reconstruct()
+            lhs = pr.c * apply(Ms, U)
+            for d in range(3):
+                lhs = lhs + pr.lam * apply([ax[e].K if e == d else ax[e].M for e in range(3)], U)
+            Q = pr.c * apply(Ms, Uk) - nonlinear_load(pr, Uk)
+            err = rel(lhs, Q)
+            print(f"  full step {k}: residual {err:.2e}", flush=True)
+            assert err < 1e-12
+            Uk = U

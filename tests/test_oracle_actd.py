@@ -1,6 +1,6 @@
-"""Pins of the ACTD oracle (Sec. 3.3 adaptive algorithm, 2D): the separated
-form of a nodal field, the switch to the full CFE solve past the mode cap,
-and the scheme's energy law along a run that switches."""
+"""Pins of the ACTD oracle (Sec. 3.3 adaptive algorithm, 2D and 3D): the
+separated form of a nodal field, the switch to the full CFE solve past the
+mode cap, and the scheme's energy law along a run that switches."""
 import numpy as np
 import pytest
 
@@ -111,8 +111,80 @@ def test_planted_field_transpose_caught(monkeypatch):
     assert np.linalg.norm(a - b) / np.linalg.norm(a) > 1e-6
 
 
-def test_actd_rejects_3d():
-    inst = small_instance(dim=3, n=8, m0=2, kmax=2, max_modes=2)
+def _inst3(n=(8, 7, 6), cap=4, **kw):
+    return small_instance(dim=3, n=n, m0=2, kmax=3, eps=0.08, dt=1e-3, max_modes=cap, **kw)
+
+
+def test_field_state_3d_is_the_field():
+    rng = np.random.default_rng(1)
+    U = rng.standard_normal((6, 5, 4))
+    st = field_state(U)
+    assert st.modes == 20 and st.warm_modes == 0
+    assert np.array_equal(full_field(st), U)
+
+
+def test_ctd_step_from_3d_field_state_equals_step_from_modes():
+    """3D: the step's integrals depend on the field only, so the step from
+    the 2-mode state and from its 42-fibre field form agree to rounding
+    (counter-based guess on both sides)."""
+    inst = _inst3(cap=24)
+    pr = problem_from_instance(inst, init="hash")
+    st = state_from_instance(inst)
+    new_a, log_a = ctd_step(pr, st, 0)
+    assert log_a.stop == "tol"
+    new_b, _ = ctd_step(pr, field_state(full_field(st)), 0, replay=log_a.iters)
+    a, b = full_field(new_a), full_field(new_b)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-11
+
+
+def test_warm_guess_from_3d_field_state_is_the_counter_based_one():
+    """A 3D field state holds no modes to start from: the warm reading gives
+    the counter-based initial guess for every mode (bitwise the same step)."""
+    inst = _inst3(cap=24)
+    U = full_field(state_from_instance(inst))
+    a, la = ctd_step(problem_from_instance(inst, init="warm"), field_state(U), 3)
+    b, lb = ctd_step(problem_from_instance(inst, init="hash"), field_state(U), 3)
+    assert la.iters == lb.iters
+    assert np.array_equal(full_field(a), full_field(b))
+
+
+def test_switch_past_the_cap_gives_the_full_solve_3d():
+    inst = _inst3(cap=3)
     pr = problem_from_instance(inst)
-    with pytest.raises(ValueError):
-        actd_step(pr, state_from_instance(inst), 0)
+    st = state_from_instance(inst)
+    _, log_ctd = ctd_step(pr, st, 0)
+    assert log_ctd.stop == "cap"
+    new, log = actd_step(pr, st, 0)
+    assert log.stop == "full"
+    assert np.array_equal(full_field(new), full_step(pr, full_field(st)))
+    assert new.warm_modes == 0
+
+
+def test_actd_3d_replay_and_energy_law():
+    """3D run replaying full / CTD from the field / full: each CTD step from
+    the field state equals the same step from the field's original-mode
+    form, and the discrete energy does not increase (Sec. 2.5)."""
+    inst = _inst3(cap=3)
+    pr = problem_from_instance(inst, init="hash")
+    st0 = state_from_instance(inst)
+    sched = ["full", [3, 2, 2], "full"]
+    st, logs, fields = actd_run(pr, st0, 3, replay=sched)
+    assert actd.decisions(logs) == sched
+    E = [energy_fullgrid(pr, full_field(st0))] + [energy_fullgrid(pr, U) for U in fields]
+    assert all(E[i + 1] <= E[i] * (1 + 1e-12) for i in range(len(E) - 1))
+    # the full steps are the full CFE solve of the previous field
+    assert np.allclose(fields[0], full_step(pr, full_field(st0)), rtol=0, atol=1e-15)
+    assert np.allclose(fields[2], full_step(pr, fields[1]), rtol=0, atol=1e-15)
+
+
+def test_planted_3d_fibre_order_caught():
+    """A 3D field state whose fibres are taken with axes 1 and 2 swapped is a
+    different field: the step-from-field comparison above must catch it."""
+    inst = _inst3(n=(8, 7, 7), cap=24)
+    pr = problem_from_instance(inst, init="hash")
+    st = state_from_instance(inst)
+    new_a, log_a = ctd_step(pr, st, 0)
+    bad = field_state(full_field(st).transpose(0, 2, 1))
+    new_b, _ = ctd_step(pr, bad, 0, replay=log_a.iters)
+    a, b = full_field(new_a), full_field(new_b)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) > 1e-6
