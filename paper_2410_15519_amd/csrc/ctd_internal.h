@@ -279,7 +279,8 @@ struct LsArg {
   int flag;       // append pending / leading signature of a continued sweep
   int nlin;       // linear RHS column chunks for M
   int nld[2];     // load chunks of the RHS of direction 0, 1
-  int pad;
+  int boff[2];    // first workgroup of this entry in the RHS launch of direction 0, 1
+  int pad[2];
   int64_t step;   // time-step index (keys the counter-based guess)
 };
 enum { kLsReset = 0, kLsAppend, kLsInit, kLsFinalizeInit, kLsSignatureAll, kLsSignature,
@@ -289,6 +290,7 @@ struct LsGrid {
   int ndot = 0;      // signature dot blocks
   int nchunk = 0;    // RHS chunks (linear + load)
   int B = 0;         // band half-width shared by the group
+  int nblk = 0;      // workgroups of the RHS launch (sum over the entries)
   int mode = 0, threads = 0;   // BCR storage class and threads
   size_t shm = 0;
 };

@@ -2689,11 +2689,24 @@ __global__ void k_signature_m(const DevInst* __restrict__ insts, const LsArg* __
   signature_body(I, d, a.M, ndot, 0, blockIdx.x, blockIdx.y);
 }
 
-__global__ __launch_bounds__(256) void k_rhs_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args, int d) {
-  const LsArg& a = args[blockIdx.z];
+// One workgroup per (row block, column chunk) of every entry, packed: the
+// entries' workgroups follow each other (boff), so the grid holds no idle
+// workgroups however uneven the instances; a workgroup finds its entry by
+// binary search over the offsets.
+__global__ __launch_bounds__(256) void k_rhs_m(const DevInst* __restrict__ insts, const LsArg* __restrict__ args,
+                                               int count, int d) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (args[mid].boff[d] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const LsArg& a = args[lo];
   const DevInst& I = insts[a.inst];
-  if ((int)blockIdx.x * 64 >= I.ax[d].n || (int)blockIdx.y >= a.nlin + a.nld[d]) return;
-  rhs_body(I, d, a.M, 0, a.nlin, blockIdx.x, blockIdx.y);
+  const int rb = (I.ax[d].n + 63) / 64;
+  const int local = b - a.boff[d];
+  rhs_body(I, d, a.M, 0, a.nlin, local % rb, local / rb);
 }
 
 template <int B, int MODE>
@@ -2751,7 +2764,10 @@ hipError_t launch_multi(int kind, DevInst* insts, const LsArg* args, int count, 
       break;
     case kLsSignature: k_signature_m<<<dim3(g.ndot, 1, count), 256, 0, st>>>(insts, args, d, 0); break;
     case kLsSignatureFlag: k_signature_m<<<dim3(g.ndot, 1, count), 256, 0, st>>>(insts, args, d, 1); break;
-    case kLsRhs: k_rhs_m<<<dim3((g.nmax + 63) / 64, g.nchunk, count), 256, 0, st>>>(insts, args, d); break;
+    case kLsRhs:
+      if (g.nblk <= 0) return hipErrorInvalidValue;
+      k_rhs_m<<<g.nblk, 256, 0, st>>>(insts, args, count, d);
+      break;
     case kLsSolve: {
 #define SOLVE_M(BW)                                                                                   \
   (g.mode == 0 ? k_solve_bcr_m<BW, 0><<<dim3(1, 1, count), g.threads, g.shm, st>>>(insts, args, d)    \

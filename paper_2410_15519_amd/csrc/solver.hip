@@ -1251,7 +1251,9 @@ struct LockstepInst {
   std::chrono::steady_clock::time_point t0;
 };
 
-int lockstep_finish(LockstepInst& L, ctd_step_info* info, std::vector<int32_t>& log) {
+// sync = false (no energy to read back): the step-end launches stay in flight
+// on the instance's stream; the caller waits for them by an event.
+int lockstep_finish(LockstepInst& L, ctd_step_info* info, std::vector<int32_t>& log, bool sync = true) {
   ctd_solver* s = L.s;
   if (L.pending_append) {
     HIPCHK(s, launch_append(s->I, L.M - 1, s->stream));
@@ -1283,7 +1285,7 @@ int lockstep_finish(LockstepInst& L, ctd_step_info* info, std::vector<int32_t>& 
       info->energy_increase = std::isfinite(s->energy_prev) && E > s->energy_prev * (1.0 + 1e-12) + 1e-300;
     }
     s->energy_prev = E;
-  } else {
+  } else if (sync) {
     HIPCHK(s, sync_collect(s));
   }
   if (info) {
@@ -1327,10 +1329,20 @@ struct Lockstep::Impl {
   std::vector<int> remaining;        // steps still to run per slot
   std::vector<std::vector<int32_t>> logs;
   int live = 0;
+  // step-end work (append, swap, the next step's tables and M_xy) runs on
+  // side streams while the other instances go on; an instance rejoins the
+  // rounds once its event has completed
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  int next_side = 0;
+  std::vector<hipEvent_t> ev;        // per slot
+  std::vector<char> pending;         // per slot: step-end work in flight
 
   hipError_t sync() { return hipStreamSynchronize(st); }
   void release() {
     (void)sync();
+    for (hipStream_t h : side)
+      if (h) (void)hipStreamSynchronize(h);
     if (dI) (void)hipFree(dI);
     if (dA) (void)hipFree(dA);
     if (dS) (void)hipFree(dS);
@@ -1367,6 +1379,8 @@ struct Lockstep::Impl {
     L.resize(want);
     remaining.resize(want, 0);
     logs.resize(want);
+    ev.resize(want, nullptr);
+    pending.resize(want, 0);
     cap = want;
     for (int i = 0; i < cap; ++i)
       if (S[i] && (e = hipMemcpyAsync(dI + i, hI + i, sizeof(DevInst), hipMemcpyHostToDevice, st)) != hipSuccess)
@@ -1384,6 +1398,10 @@ Lockstep::Lockstep(hipStream_t st) : p(new Impl) { p->st = st; }
 
 Lockstep::~Lockstep() {
   p->release();
+  for (hipEvent_t e : p->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipStream_t h : p->side)
+    if (h) (void)hipStreamDestroy(h);
   delete p;
 }
 
@@ -1438,6 +1456,46 @@ int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vect
   hipStream_t st = E.st;
   const int B = E.B;
   const int N = E.cap;
+  // instances whose step-end work has completed rejoin (or leave, when all
+  // their steps are done); with every instance still busy, wait for one
+  {
+    int active = 0, first_busy = -1;
+    for (int i = 0; i < N; ++i) {
+      if (!E.S[i]) continue;
+      if (E.pending[i]) {
+        hipError_t q = hipEventQuery(E.ev[i]);
+        if (q == hipErrorNotReady) {
+          if (first_busy < 0) first_busy = i;
+          continue;
+        }
+        if (q != hipSuccess) {
+          err = std::string("HIP error in lockstep step end: ") + hipGetErrorString(q);
+          return CTD_EDEVICE;
+        }
+        E.pending[i] = 0;
+        solver_bind_stream(E.S[i], st);
+        if (E.remaining[i] == 0) {
+          E.S[i]->decisions_last.swap(E.logs[i]);
+          E.logs[i].clear();
+          E.S[i] = nullptr;
+          --E.live;
+          finished.push_back(i);
+          continue;
+        }
+      }
+      ++active;
+    }
+    if (active == 0) {
+      if (first_busy >= 0) {
+        hipError_t e = hipEventSynchronize(E.ev[first_busy]);
+        if (e != hipSuccess) {
+          err = std::string("HIP error in lockstep step end: ") + hipGetErrorString(e);
+          return CTD_EDEVICE;
+        }
+      }
+      return CTD_OK;
+    }
+  }
   auto hip = [&](hipError_t e, const char* where) {
     if (e == hipSuccess) return CTD_OK;
     err = std::string("HIP error in ") + where + ": " + hipGetErrorString(e);
@@ -1463,7 +1521,7 @@ int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vect
   // finalisation workgroup size (one launch per size)
   std::vector<int> gi, gs;
   for (int i = 0; i < N; ++i) {
-    if (!E.S[i]) continue;
+    if (!E.S[i] || E.pending[i]) continue;
     if (E.L[i].start) gi.push_back(i);
     gs.push_back(i);
   }
@@ -1474,6 +1532,13 @@ int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vect
   LsArg* hAs = E.hA + N;
   for (int k = 0; k < ni; ++k) { fill(hAi[k], gi[k]); hAi[k].flag = E.L[gi[k]].pending_append ? 1 : 0; }
   for (int k = 0; k < ns; ++k) { fill(hAs[k], gs[k]); hAs[k].flag = E.L[gs[k]].it > 1 ? 1 : 0; }
+  // the RHS launches' workgroups, packed entry after entry per direction
+  int nblk[2] = {0, 0};
+  for (int k = 0; k < ns; ++k)
+    for (int d = 0; d < 2; ++d) {
+      hAs[k].boff[d] = nblk[d];
+      nblk[d] += ((E.S[gs[k]]->ax[d].n + 63) / 64) * (hAs[k].nlin + hAs[k].nld[d]);
+    }
   // the solve launches: sweep entries regrouped per direction by BCR
   // storage class and thread count (blocks [2N, 3N) and [3N, 4N))
   struct SolveClass { int mode, threads, first, count; size_t shm; };
@@ -1544,7 +1609,8 @@ int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vect
     LsGrid G1 = grid_of(gs, hAs, 1);
     if ((rc = hip(launch_multi(kLsSignatureFlag, dI, dAs, ns, G1, st, 1), "signature"))) return rc;
     for (int d = 0; d < 2; ++d) {
-      const LsGrid G = grid_of(gs, hAs, d);
+      LsGrid G = grid_of(gs, hAs, d);
+      G.nblk = nblk[d];
       if ((rc = hip(launch_multi(kLsRhs, dI, dAs, ns, G, st, d), "rhs"))) return rc;
       // the solve: one launch per BCR storage class and thread count
       for (const SolveClass& c : scls[d]) {
@@ -1622,13 +1688,30 @@ int Lockstep::round(std::vector<std::pair<int, ctd_step_info>>& steps, std::vect
     }
     if (end_step) {
       ctd_step_info inf{};
-      rc = lockstep_finish(Li, &inf, E.logs[i]);
+      // without an energy to read back, the step-end launches go to a side
+      // stream and the instance sits out until they have completed
+      const bool async = !s->P.energy_each_step;
+      if (async) {
+        hipStream_t& h = E.side[E.next_side];
+        E.next_side = (E.next_side + 1) % Impl::kSide;
+        if (!h && (rc = hip(hipStreamCreateWithFlags(&h, hipStreamNonBlocking), "lockstep stream"))) return rc;
+        if (!E.ev[i] && (rc = hip(hipEventCreateWithFlags(&E.ev[i], hipEventDisableTiming), "lockstep event")))
+          return rc;
+        solver_bind_stream(s, h);
+      }
+      rc = lockstep_finish(Li, &inf, E.logs[i], !async);
+      if (rc == CTD_OK && async) rc = hip(hipEventRecord(E.ev[i], s->stream), "lockstep event");
       if (rc) {
+        if (async) solver_bind_stream(s, st);
         if ((rc = fail_inst(rc, s->err))) return rc;
         continue;
       }
       steps.push_back({i, inf});
-      if (--E.remaining[i] == 0) {
+      --E.remaining[i];
+      if (async) {
+        E.pending[i] = 1;
+        if (E.remaining[i] > 0 && (rc = hip(E.upload(i), "lockstep upload"))) return rc;
+      } else if (E.remaining[i] == 0) {
         s->decisions_last.swap(E.logs[i]);
         E.logs[i].clear();
         E.S[i] = nullptr;
