@@ -1398,6 +1398,10 @@ Lockstep::Lockstep(hipStream_t st) : p(new Impl) { p->st = st; }
 
 Lockstep::~Lockstep() {
   p->release();
+  // instances still in their step-end work go back to the engine's stream
+  // (the side streams end here)
+  for (int i = 0; i < p->cap; ++i)
+    if (p->S[i] && p->pending[i]) solver_bind_stream(p->S[i], p->st);
   for (hipEvent_t e : p->ev)
     if (e) (void)hipEventDestroy(e);
   for (hipStream_t h : p->side)
