@@ -161,16 +161,19 @@ def _inst3(n=(13, 11, 9), cap=3, kmax=3):
     return small_instance(dim=3, n=n, m0=2, kmax=kmax, eps=0.08, dt=1e-3, max_modes=cap)
 
 
+@pytest.mark.parametrize("solve", ["auto", "bcr"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_actd3d_replay_parity(ctd, prec):
+def test_actd3d_replay_parity(ctd, prec, solve):
     """Schedule full / CTD from the field state / full / CTD in 3D: every
-    step's field against the oracle's."""
+    step's field against the oracle's (directional solves by fast
+    diagonalisation or by cyclic reduction: both add the field state's load
+    chunks)."""
     inst = _inst3()
     pr = problem_from_instance(inst)
     sched = ["full", [3, 2, 2], "full", [2, 3]]
     _, logs, fields = actd_run(pr, state_from_instance(inst), len(sched), replay=sched)
-    print(f"actd 3D replay prec={prec}", flush=True)
-    with ctd.Solver(inst, precision=prec, schedule="replay", actd=True) as s:
+    print(f"actd 3D replay prec={prec} solve={solve}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", actd=True, solve=solve) as s:
         s.set_decisions(sched)
         dec = []
         for k, sc in enumerate(sched):
@@ -238,3 +241,24 @@ def test_actd3d_full_solve_residual(ctd):
             print(f"  full step {k}: residual {err:.2e}", flush=True)
             assert err < 1e-12
             Uk = U
+
+
+def test_actd3d_in_batch_equals_standalone(ctd):
+    """3D instances that switch to the full solve and step from the field
+    state, on worker streams, end bitwise where each alone does (the field
+    state read back as its fibres)."""
+    insts = [_inst3(n=(12 + 2 * k, 10 + k, 9), cap=3) for k in range(3)]
+    b = ctd.Batch(insts, precision="mixed", actd=True)
+    try:
+        b.set_workers(3)
+        infos = b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    assert any(r["full_solve"] for inf in infos for r in inf)
+    for i, inst in enumerate(insts):
+        with ctd.Solver(inst, precision="mixed", actd=True) as s:
+            s.step(2)
+            amp, fac = s.modes()
+        assert np.array_equal(got[i][0], amp), f"instance {i}"
+        assert all(np.array_equal(x, y) for x, y in zip(got[i][1], fac)), f"instance {i}"
