@@ -91,6 +91,8 @@ struct DevScalars {
 };
 
 // Everything a kernel may need about one instance, passed by value.
+constexpr int kHsbMax = 64;   // h splits with balanced ranges (more: equal counts)
+
 struct DevInst {
   int dim;
   int Mk;            // modes of u^k
@@ -139,6 +141,12 @@ struct DevInst {
                      // class: [rank][split][4096] distinct, then [rank][split][2304]
   void* S;           // ntri x 4096 (T), weighted g_e * g_f
   double* hpart;     // nsplit_h x nqmax
+  // h splits of about equal MFMA work (a triple whose pair tiles coincide
+  // runs 40 of the 64 k-steps): when hsb_n == nsplit_h, split s takes the
+  // positions [hsb[s], hsb[s + 1]) of the h order, else ranges of equal
+  // triple counts
+  int hsb_n;
+  int16_t hsb[kHsbMax + 1];
   double* bcr_ws;    // cyclic-reduction block data in HBM for axes too large for LDS (else null)
   int nsplit_g, nsplit_h;
   // 2D route

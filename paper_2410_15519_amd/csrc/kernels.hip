@@ -623,14 +623,16 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
     double* phl = hl + qcount;    // qcount x SW
     for (int idx = tid; idx < qcount; idx += blockDim.x) {
       const int q = q_lo + idx;
-      double hp[16];
+      // the h splits in order, sixteen loads in flight at a time
       const int ns = I.nsplit_h;
-#pragma unroll
-      for (int sp = 0; sp < 16; ++sp) hp[sp] = sp < ns ? I.hpart[(size_t)sp * A.nq + q] : 0.0;
       double h = 0.0;
+      for (int s0 = 0; s0 < ns; s0 += 16) {
+        double hp[16];
 #pragma unroll
-      for (int sp = 0; sp < 16; ++sp) h += hp[sp];
-      for (int sp = 16; sp < ns; ++sp) h += I.hpart[(size_t)sp * A.nq + q];
+        for (int k = 0; k < 16; ++k) hp[k] = s0 + k < ns ? I.hpart[(size_t)(s0 + k) * A.nq + q] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) h += hp[k];
+      }
       hl[idx] = h * A.w[q];
     }
     for (int idx = tid; idx < qcount * SW; idx += blockDim.x)
@@ -1756,6 +1758,22 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
   }
 }
 
+// The 40 k-steps ks = 4 j + u (u >= j / 4) of a repeated-tile triple in
+// packed order: blocks J = j / 4 of 4 (4 - J) k-steps, j-major inside.
+__host__ __device__ constexpr int packed_ks_base(int J) { return 4 * (4 * J - J * (J - 1) / 2); }
+__host__ __device__ constexpr int packed_ks_block(int p) {
+  return p < packed_ks_base(1) ? 0 : p < packed_ks_base(2) ? 1 : p < packed_ks_base(3) ? 2 : 3;
+}
+__host__ __device__ constexpr int packed_ks_j(int p) {
+  return 4 * packed_ks_block(p) + (p - packed_ks_base(packed_ks_block(p))) / (4 - packed_ks_block(p));
+}
+__host__ __device__ constexpr int packed_ks_u(int p) {
+  return packed_ks_block(p) + (p - packed_ks_base(packed_ks_block(p))) % (4 - packed_ks_block(p));
+}
+static_assert(packed_ks_j(39) == 15 && packed_ks_u(39) == 3 && packed_ks_j(16) == 4 &&
+                  packed_ks_u(16) == 1 && packed_ks_j(15) == 3 && packed_ks_u(15) == 3,
+              "packed k-step order");
+
 // Split-K reduction of the FP32 g by class (fixed split order), and S = w g_d
 // g_other in the h kernel's order and layout.  One thread per element of an
 // h tile (first mode, second mode, column mode); for a repeated-tile triple
@@ -1812,9 +1830,19 @@ __global__ __launch_bounds__(256) void k_cubic_gred32(DevInst I, int d, int e_ot
     const float* go = (const float*)I.ax[e_other].g;
     const float val = pw == 0.0 ? 0.0f : (float)((double)I.tri[t].w * pw * s * (double)go[goff + el]);
     // element eh = 64 ks + l of the tile (k-step ks, lane l) goes where lane
-    // l finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4)
+    // l finds k-steps 4j..4j+3 in one 16-byte word: ((j 64 + l) 4 + ks % 4).
+    // A repeated-tile triple keeps only the k-steps ks = 4 j + u with
+    // u >= j / 4 (the others pair a first mode j above all four second modes
+    // 4u..4u+3), packed in (j, u) order: position 4 (4J - J(J-1)/2) +
+    // (j % 4)(4 - J) + u - J for J = j / 4.
     const int ks = eh >> 6, l = eh & 63;
-    ((float*)I.S)[(size_t)p * TS + ((((ks >> 2) << 6) + l) << 2) + (ks & 3)] = val;
+    int pk = ks;
+    if (cr.x != 0) {
+      const int j = ks >> 2, u = ks & 3, J = j >> 2;
+      if (u < J) return;
+      pk = packed_ks_base(J) + (j & 3) * (4 - J) + (u - J);
+    }
+    ((float*)I.S)[(size_t)p * TS + ((((pk >> 2) << 6) + l) << 2) + (pk & 3)] = val;
   }
 }
 
@@ -1873,149 +1901,170 @@ __global__ __launch_bounds__(256) void k_cubic_gred(DevInst I, int d, int e_othe
 }
 
 
-// h for the FP32 path.  A workgroup of 4 waves owns 64 Gauss points (a
-// 16-point MFMA block per wave) and walks its share of the tile triples.
-// Only the S tiles are staged in LDS (32 KB, double-buffered; in the order
-// k_cubic_gred<float> writes them: lane l finds k-steps 4j..4j+3 in one
-// 16-byte word), so several workgroups share a CU.  The factor values of a
-// lane's Gauss point come from L2 straight into VGPRs (the tile-major table
-// makes the 16 points of a wave one contiguous kilobyte per tile, and puts a
-// lane group's four B-operand modes in one 16-byte word); the factor values
-// of the next triple are fetched while the MFMAs of the current one run, the
-// S tile of the next triple is loaded and stored to the other buffer after
-// them (one barrier per triple).
-constexpr int kHRows = 1;              // 16-point MFMA blocks per wave (2 measured slower: occupancy)
-constexpr int kHQ = 64 * kHRows;       // Gauss points per workgroup
+// h for the FP32 path.  A workgroup of 8 waves owns 128 Gauss points (16 per
+// wave, the MFMA columns) and walks its share of the tile triples; every
+// MFMA takes the S tile as its A operand (rows: the 16 column modes c;
+// k-steps: mode pairs) and the pair products X_a X_b of the wave's points
+// as its B operand, so that the output holds the lane's own point in its
+// column and the closing sum over c with X_c is lane-local except for the
+// four lane groups' rows.
+// Per triple the workgroup stages the S tile and the first tile's factor
+// rows at its 128 points in LDS (double-buffered, 24 KB each; S in the
+// order k_cubic_gred32 writes it: lane l finds four k-steps in one 16-byte
+// word), so the 16 waves of two workgroups share one copy per CU of what
+// the MFMAs read most; each lane loads the second tile's four B modes of
+// its point (one 16-byte word of the tile-major table) itself, and the
+// column tile's values only where a column closes.  The next triple's data
+// are fetched while the MFMAs of the current one run and stored to the
+// other buffer after them (one barrier per triple).
+constexpr int kHWaves = 8;                 // waves per workgroup
+constexpr int kHQ = 16 * kHWaves;          // Gauss points per workgroup
+constexpr int kHThreads = 64 * kHWaves;
+constexpr int kHBufWords = kTileSq * kTile / 4 + kHQ * kTile / 4;   // S tile + first-tile rows
 
-template <int HR>
-__global__ __launch_bounds__(256) void k_cubic_h32(DevInst I, int d) {
+__global__ __launch_bounds__(kHThreads) void k_cubic_h32(DevInst I, int d) {
   if (spec_skip(I)) return;
   extern __shared__ unsigned char smraw[];
   constexpr int TW = kTileSq * kTile / 4;   // 16-byte words per S tile
+  static_assert(TW == 2 * kHThreads && kHQ * kTile / 4 == kHThreads, "three staged words per thread");
   const DevAxis& A = I.ax[d];
   const float* X = (const float*)A.Xhf;
-  const int ldh = I.Mkp;
   const int nq = A.nq;
-  float4* sb = (float4*)smraw;           // 2 x TW words
+  float4* sb = (float4*)smraw;           // 2 x (S tile, first-tile rows)
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int q0 = blockIdx.x * (64 * HR);
-  const int qw = q0 + w * 16 * HR;       // first Gauss point of this wave
+  const int g = l >> 4;                  // lane group: k index of the operands
+  const int q0 = blockIdx.x * kHQ;
+  const int qw = q0 + w * 16;            // first Gauss point of this wave
   const int split = blockIdx.y;
-  const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
-  const int t0 = split * per;
-  const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
-  // A-operand rows of this lane; rows past the end read the last point (their
-  // MFMA output rows are never stored).  The table is tile-major over the
-  // 64-padded point count, mode i of a tile in slot 4 (i % 4) + i / 4.
+  int t0, t1;
+  if (I.hsb_n == I.nsplit_h) {
+    t0 = I.hsb[split];
+    t1 = I.hsb[split + 1];
+  } else {
+    const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
+    t0 = split * per;
+    t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
+  }
+  // Points past the end read the last point (their sums are never stored).
+  // The table is tile-major over the 64-padded point count, mode i of a tile
+  // in slot 4 (i % 4) + i / 4 (16-byte word i % 4).
   const size_t nqp = (size_t)(nq + 63) / 64 * 64;
-  int qa[HR];
-#pragma unroll
-  for (int rb = 0; rb < HR; ++rb) {
-    const int q = qw + rb * 16 + (l & 15);
-    qa[rb] = q < nq ? q : nq - 1;
-  }
-  const int es = (((l & 15) & 3) << 2) + ((l & 15) >> 2);   // slot of mode l % 16
-  // prefetch registers; loads use a clamped triple index so they are
-  // unconditional (the surplus S words land in the idle buffer)
+  const int qa = qw + (l & 15) < nq ? qw + (l & 15) : nq - 1;        // the lane's point
+  const int qs = q0 + (tid >> 2) < nq ? q0 + (tid >> 2) : nq - 1;    // the staging row of this thread
+  const int xrow = (w * 16 + (l & 15)) * 4;                          // the lane's row in the staged rows
+  // loads use a clamped triple index so they are unconditional (the surplus
+  // lands in the idle buffer)
   const int tlast = t1 > t0 ? t1 - 1 : 0;
+  auto tcl = [&](int t) { return t < tlast ? t : tlast; };
   const float4* Sp = (const float4*)I.S;
-  float4 pre[TW / 256];
-  float4 xa4[HR][4], xan[HR][4];
-  float xb[HR][4], xbn[HR][4];
-#define H32_FETCH(tt, XA, XB)                                                    \
-  do {                                                                          \
-    const int4 tr_ = I.trih[tt];                                                \
-    const size_t base_ = (size_t)(tt) * TW + tid;                               \
-    _Pragma("unroll") for (int v = 0; v < TW / 256; ++v) pre[v] = Sp[base_ + v * 256]; \
-    _Pragma("unroll") for (int rb = 0; rb < HR; ++rb) {                         \
-      const float4* ar_ = (const float4*)(X + ((size_t)tr_.x * nqp + qa[rb]) * kTile); \
-      _Pragma("unroll") for (int v = 0; v < 4; ++v) XA[rb][v] = ar_[v];         \
-      const float4 b_ = *(const float4*)(X + ((size_t)tr_.y * nqp + qa[rb]) * kTile + 4 * (l >> 4)); \
-      XB[rb][0] = b_.x; XB[rb][1] = b_.y; XB[rb][2] = b_.z; XB[rb][3] = b_.w;    \
-    }                                                                           \
-  } while (0)
-  H32_FETCH(t0 < tlast ? t0 : tlast, xa4, xb);
+  float4 pre0, pre1, pre2;
+  float xb[4], xbn[4], xc[4];
+  auto fetch = [&](int tt, int4 tr) __attribute__((always_inline)) {
+    const float4* src = Sp + (size_t)tt * TW + tid;
+    pre0 = src[0];
+    pre1 = src[kHThreads];
+    pre2 = *(const float4*)(X + ((size_t)tr.x * nqp + qs) * kTile + 4 * (tid & 3));
+    const float4 bq = *(const float4*)(X + ((size_t)tr.y * nqp + qa) * kTile + 4 * g);
+    xbn[0] = bq.x; xbn[1] = bq.y; xbn[2] = bq.z; xbn[3] = bq.w;
+  };
+  auto stage = [&](float4* dst) __attribute__((always_inline)) {
+    dst[tid] = pre0;
+    dst[kHThreads + tid] = pre1;
+    dst[TW + tid] = pre2;
+  };
+  // the triple table two ahead (scalar loads consumed an iteration later)
+  int4 thc = I.trih[tcl(t0)], thn = I.trih[tcl(t0 + 1)];
+  fetch(tcl(t0), thc);
+  stage(sb);
 #pragma unroll
-  for (int v = 0; v < TW / 256; ++v) sb[v * 256 + tid] = pre[v];
+  for (int v = 0; v < 4; ++v) xb[v] = xbn[v];
   __syncthreads();
-  double hq[HR][4];
-  f4 acc[HR][2];
-#pragma unroll
-  for (int rb = 0; rb < HR; ++rb) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) hq[rb][r] = 0.0;
-    acc[rb][0] = f4{0, 0, 0, 0};
-    acc[rb][1] = f4{0, 0, 0, 0};
-  }
+  double hq = 0.0;
+  f4 acc = f4{0, 0, 0, 0};
   int curC = -1;
-  auto close_c = [&]() {
+  // h[q] += sum over the lane's column modes c = 4 g + r of X_c[q] acc[c, q],
+  // then over the four lane groups
+  auto close_c = [&]() __attribute__((always_inline)) {
+    double v = 0.0;
 #pragma unroll
-    for (int rb = 0; rb < HR; ++rb) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        int q = qw + rb * 16 + mfma_row<float>(l, r);
-        q = q < nq ? q : nq - 1;
-        double v = ((double)acc[rb][0][r] + (double)acc[rb][1][r]) *
-                   (double)X[((size_t)curC * nqp + q) * kTile + es];
-        v += __shfl_xor(v, 8, 64);
-        v += __shfl_xor(v, 4, 64);
-        v += __shfl_xor(v, 2, 64);
-        v += __shfl_xor(v, 1, 64);
-        hq[rb][r] += v;
-      }
-      acc[rb][0] = f4{0, 0, 0, 0};
-      acc[rb][1] = f4{0, 0, 0, 0};
-    }
+    for (int r = 0; r < 4; ++r) v += (double)acc[r] * (double)xc[r];
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    hq += v;
+    acc = f4{0, 0, 0, 0};
   };
   for (int t = t0; t < t1; ++t) {
-    const int4 th = I.trih[t];
-    const int cz = th.z;
-    H32_FETCH(t + 1 < tlast ? t + 1 : tlast, xan, xbn);
-    if (cz != curC) {
+    const int4 th = thc;
+    // the previous column closes before the prefetch is issued, so that the
+    // prefetch's loads stay in flight across the MFMAs
+    if (th.z != curC) {
       if (curC >= 0) close_c();
-      curC = cz;
+      curC = th.z;
     }
-    const float4* sq = sb + ((t - t0) & 1) * TW;
-    // k-step ks = 4 j + u pairs mode a = j of the first tile with b = 4 u + g
-    // of the second; when the pairs are taken once (first tile = second
+    const int4 thnn = I.trih[tcl(t + 2)];
+    fetch(tcl(t + 1), thn);
+    if (t + 1 >= t1 || thn.z != th.z) {
+      // this triple closes its column: X_c of the lane's modes c = 4 g + r
+      // (slot 4 r + g of the point's row)
+      const float* xr = X + ((size_t)th.z * nqp + qa) * kTile + g;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xc[r] = xr[4 * r];
+    }
+    const float4* sq = sb + ((t - t0) & 1) * kHBufWords;
+    float4 xa4[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xa4[v] = sq[TW + xrow + v];
+    // k-step ks = 4 j + u: first mode a = j (word j % 4, slot j / 4 of the
+    // point's row), second modes b = 4 u + k over the operands' k index (the
+    // lane group).  When the pairs are taken once (first tile = second
     // tile), the k-steps whose four b all lie below a (u < j / 4) meet only
-    // zero weights in S and are skipped
-    const bool full = th.w == 0;
+    // zero weights; S holds the other 40 k-steps packed in order, so both
+    // forms read whole 16-byte words and branch once per triple.  The
+    // schedule is pinned (sched_group_barrier; 0x100 LDS read, 0x002 VALU,
+    // 0x008 MFMA): S words read three ahead, each product issued just before
+    // its MFMA.
+    if (th.w == 0) {
 #pragma unroll
-    for (int j = 0; j < kTileSq / 16; ++j) {
-      const float4 b4 = sq[j * 64 + l];
+      for (int j = 0; j < kTileSq / 16; ++j) {
+        const float4 b4 = sq[j * 64 + l];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (u < (j >> 2) && !full) continue;
-        const int ks = 4 * j + u;
+        for (int u = 0; u < 4; ++u) acc = mfma16(b4[u], xa4[j & 3][j >> 2] * xb[u], acc);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
 #pragma unroll
-        for (int rb = 0; rb < HR; ++rb)
-          // mode a = ks / 4 of the first tile: word a % 4, slot a / 4
-          acc[rb][u & 1] = mfma16(xa4[rb][(ks >> 2) & 3][ks >> 4] * xb[rb][ks & 3], b4[u], acc[rb][u & 1]);
+      for (int j = 0; j < kTileSq / 16; ++j) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        }
+        if (j + 3 < kTileSq / 16) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+    } else {
+      float4 b4;
+#pragma unroll
+      for (int p = 0; p < 40; ++p) {
+        const int j = packed_ks_j(p), u = packed_ks_u(p);
+        if ((p & 3) == 0) b4 = sq[(p >> 2) * 64 + l];
+        acc = mfma16(b4[p & 3], xa4[j & 3][j >> 2] * xb[u], acc);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x100, 3, 0);
+#pragma unroll
+      for (int p = 0; p < 40; ++p) {
+        __builtin_amdgcn_sched_group_barrier(0x002, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        if ((p & 3) == 3 && (p >> 2) + 3 < 10) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
       }
     }
-    {
-      float4* dst = sb + ((t + 1 - t0) & 1) * TW;
+    stage(sb + ((t + 1 - t0) & 1) * kHBufWords);
 #pragma unroll
-      for (int v = 0; v < TW / 256; ++v) dst[v * 256 + tid] = pre[v];
-    }
-#pragma unroll
-    for (int rb = 0; rb < HR; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) { xa4[rb][v] = xan[rb][v]; xb[rb][v] = xbn[rb][v]; }
+    for (int v = 0; v < 4; ++v) xb[v] = xbn[v];
     __syncthreads();
+    thc = thn;
+    thn = thnn;
   }
   if (curC >= 0) close_c();
-  if ((l & 15) == 0) {
-#pragma unroll
-    for (int rb = 0; rb < HR; ++rb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = qw + rb * 16 + mfma_row<float>(l, r);
-        if (q < nq) I.hpart[(size_t)split * nq + q] = hq[rb][r];
-      }
-  }
-#undef H32_FETCH
+  if (g == 0 && qw + (l & 15) < nq) I.hpart[(size_t)split * nq + qw + (l & 15)] = hq;
 }
 
 // Row stride of the LDS copy of the Gauss-point factor rows in k_cubic_h:
@@ -2041,9 +2090,15 @@ __global__ __launch_bounds__(256) void k_cubic_h(DevInst I, int d) {
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int q0 = blockIdx.x * 64;
   const int split = blockIdx.y;
-  const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
-  const int t0 = split * per;
-  const int t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
+  int t0, t1;
+  if (I.hsb_n == I.nsplit_h) {
+    t0 = I.hsb[split];
+    t1 = I.hsb[split + 1];
+  } else {
+    const int per = (I.ntri + I.nsplit_h - 1) / I.nsplit_h;
+    t0 = split * per;
+    t1 = t0 + per < I.ntri ? t0 + per : I.ntri;
+  }
   for (int idx = tid; idx < 64 * ldh; idx += 256) {
     const int qq = idx / ldh, c = idx % ldh, q = q0 + qq;
     xs[qq * ldx + c] = q < nq ? X[(size_t)q * ldh + c] : (T)0;
@@ -2153,11 +2208,13 @@ hipError_t launch_cubic_gred(const DevInst& I, int d, int e_other, hipStream_t s
 }
 
 size_t cubic_h_lds(const DevInst& I) {
-  if (I.mixed) return sizeof(float) * 2 * kTileSq * kTile;
+  if (I.mixed) return sizeof(float4) * 2 * kHBufWords;
   return sizeof(double) * (64 * (size_t)h_lds_stride<double>(I.Mkp) + 2 * kTileSq * kTile);
 }
 
 int cubic_h_rows(const DevInst& I) { return I.mixed ? kHQ : 64; }
+
+int cubic_h_threads(const DevInst& I) { return I.mixed ? kHThreads : 256; }
 
 size_t cubic_h_lds_total(const DevInst& I) { return cubic_h_lds(I); }
 
@@ -2170,8 +2227,8 @@ int cubic_h_blocks_per_cu(const DevInst& I) {
   const size_t shm = cubic_h_lds(I);
   if (last_nb[k] == 0 || last_shm[k] != shm) {
     int nb = 0;
-    const void* f = I.mixed ? (const void*)k_cubic_h32<kHRows> : (const void*)k_cubic_h<double>;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 256, shm) != hipSuccess || nb < 1) {
+    const void* f = I.mixed ? (const void*)k_cubic_h32 : (const void*)k_cubic_h<double>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, cubic_h_threads(I), shm) != hipSuccess || nb < 1) {
       (void)hipGetLastError();
       nb = std::max(1, (int)((size_t)max_lds_bytes() / shm));
     }
@@ -2186,7 +2243,7 @@ hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
   const int rows = cubic_h_rows(I);
   dim3 grid((nq + rows - 1) / rows, I.nsplit_h);
   if (I.mixed) {
-    k_cubic_h32<kHRows><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
+    k_cubic_h32<<<grid, kHThreads, cubic_h_lds(I), st>>>(I, d);
   } else {
     k_cubic_h<double><<<grid, 256, cubic_h_lds(I), st>>>(I, d);
   }
@@ -2855,7 +2912,7 @@ hipError_t configure_kernels() {
                       (const void*)k_solve_bcr<7, 2>, (const void*)k_band_solve_bcr<3, 2>,
                       (const void*)k_band_solve_bcr<5, 2>, (const void*)k_band_solve_bcr<7, 2>,
                       (const void*)k_cubic_h<double>,
-                      (const void*)k_cubic_h32<kHRows>, (const void*)k_reconstruct_tile<float>,
+                      (const void*)k_cubic_h32, (const void*)k_reconstruct_tile<float>,
                       (const void*)k_reconstruct_tile<double>, (const void*)k_reconstruct_mfma<float>,
                       (const void*)k_reconstruct_mfma<double>,
                       (const void*)k_solve_bcr_m<3, 0>, (const void*)k_solve_bcr_m<5, 0>,

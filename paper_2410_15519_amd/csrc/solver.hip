@@ -171,6 +171,8 @@ struct ctd_solver {
   double* fsQ = nullptr;           // n0 x n1 temporaries of the full solve
   double* fsT = nullptr;
   int nsplit_g_cap = 0;
+  // MFMA k-steps of the first t triples of the h order (t = 0 .. ntri_max)
+  std::vector<int> hcost;
   int64_t step_index = 0;
   std::vector<int32_t> decisions_last, decisions_next;
   std::string err = "no error";
@@ -413,8 +415,12 @@ void fp32_g_splits(ctd_solver* s, int nq, int forced) {
     pp = std::min(nchunk * 64, ((pd * 16 + 8) / 9 + 63) / 64 * 64);
     nsp = (nq + pp - 1) / pp;
   };
-  int best = 1;
-  double best_cost = 1e300;
+  // Split counts that are multiples of 8 keep each XCD's L2 on one eighth of
+  // the tables (kernel placement); measured on the 1024^3 workload that is
+  // worth about a fifth of the launch length, so such a count is taken when
+  // its modelled length is within 25 % of the best.
+  int best = 1, best8 = 0;
+  double best_cost = 1e300, best8_cost = 1e300;
   for (int nsd = 1; nsd <= nchunk; ++nsd) {
     int pd, pp, nsp;
     plan(nsd, pd, pp, nsp);
@@ -429,7 +435,12 @@ void fp32_g_splits(ctd_solver* s, int nq, int forced) {
       best_cost = cost;
       if (forced > 0) break;
     }
+    if (nsd_eff == nsd && nsd % 8 == 0 && cost < best8_cost * 0.999) {
+      best8 = nsd;
+      best8_cost = cost;
+    }
   }
+  if (forced <= 0 && best8 > 0 && best % 8 != 0 && best8_cost <= 1.25 * best_cost) best = best8;
   int pd, pp, nsp;
   plan(best, pd, pp, nsp);
   // the kernel spreads each axis' Gauss points over these split counts
@@ -444,6 +455,29 @@ void fp32_g_splits(ctd_solver* s, int nq, int forced) {
     const double floats = (double)nd * I.nsplit_g * 4096.0 + (double)I.ntri_p * I.nsplit_g * 2304.0;
     if (wgs <= slots && floats <= (double)s->nsplit_g_cap * 4096.0) I.nsplit_p = I.nsplit_g;
   }
+}
+
+// Split boundaries of the h contraction with about equal MFMA work per
+// split: boundary s is the position whose k-step prefix is nearest to s/n of
+// the total (ranges may be empty; the kernels then write zero partials).
+void h_split_ranges(ctd_solver* s) {
+  DevInst& I = s->I;
+  const int ns = I.nsplit_h, nt = I.ntri;
+  I.hsb_n = 0;
+  if (ns > kHsbMax || (int)s->hcost.size() < nt + 1) return;
+  const double total = (double)s->hcost[nt];
+  int t = 0;
+  I.hsb[0] = 0;
+  for (int k = 1; k < ns; ++k) {
+    const double target = total * k / ns;
+    while (t < nt && s->hcost[t + 1] <= target) ++t;
+    // s->hcost[t] <= target < s->hcost[t + 1] (or t == nt)
+    int b = t;
+    if (t < nt && s->hcost[t + 1] - target < target - s->hcost[t]) b = t + 1;
+    I.hsb[k] = (int16_t)std::max<int>(b, I.hsb[k - 1]);
+  }
+  I.hsb[ns] = (int16_t)nt;
+  I.hsb_n = ns;
 }
 
 void update_view(ctd_solver* s) {
@@ -461,11 +495,12 @@ void update_view(ctd_solver* s) {
     // when there are at least 8 (XCD-aware split mapping in the kernel)
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
     if (ng >= 8) ng = ng / 8 * 8;
-    // h: one round of resident workgroups, triples split evenly
+    // h: two rounds of resident workgroups (the second round evens out the
+    // workgroups' unequal lengths), triples split by MFMA work
     const int nqt = (nqmin + cubic_h_rows(I) - 1) / cubic_h_rows(I);
     const int per_cu = std::max(1, std::min(8, cubic_h_blocks_per_cu(I)));
     const int slots = num_cus() * per_cu;
-    int nh = slots / nqt;
+    int nh = 2 * slots / nqt;
     // a measured table entry for this shape replaces the heuristic
     int tg = 0, th = 0;
     if (tuning_lookup(I.nb, nqmin, tg, th)) {
@@ -478,6 +513,7 @@ void update_view(ctd_solver* s) {
     ng = std::min(ng, s->nsplit_g_cap / I.ntri);
     I.nsplit_g = std::max(1, ng);
     I.nsplit_h = std::max(1, std::min(I.ntri, nh));
+    h_split_ranges(s);
     if (I.mixed) fp32_g_splits(s, nqmin, tg > 0 ? tg : 0);
   }
 }
@@ -597,6 +633,8 @@ int alloc_instance(ctd_solver* s, int m0) {
     std::vector<int4> trih;
     std::vector<int2> map;
     make_h_order(tri, trih, map);
+    s->hcost.assign(trih.size() + 1, 0);
+    for (size_t t = 0; t < trih.size(); ++t) s->hcost[t + 1] = s->hcost[t] + (trih[t].w ? 40 : 64);
     std::vector<int> inv(map.size());
     for (size_t t = 0; t < map.size(); ++t) inv[map[t].x] = (int)t;
     int4* thd;

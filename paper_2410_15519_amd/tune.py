@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 G_CANDIDATES = (4, 8, 16, 24, 32)
-H_CANDIDATES = (4, 6, 8, 12, 16, 24, 32)
+H_CANDIDATES = (4, 8, 12, 16, 24, 32, 48)
 
 
 def time_load(s, u, dims, reps):
