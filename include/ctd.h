@@ -434,7 +434,8 @@ int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u,
                        double* out);
 
 /* Tuning table of the 3D cubic contraction (process-wide, thread-safe).
- * An entry gives the split counts for one (nb, nq): nb = ceil(M_k / 16)
+ * An entry gives the split counts for one (precision, nb, nq): precision
+ * CTD_PREC_MIXED or CTD_PREC_FP64 (the kernels differ), nb = ceil(M_k / 16)
  * mode tiles, nq = Gauss points of the instance's smallest axis.
  * nsplit_g: Gauss-point splits of the g contraction (workgroups = tile
  * triples x nsplit_g); nsplit_h: tile-triple splits of the h contraction.
@@ -442,8 +443,13 @@ int ctd_nonlinear_load(ctd_solver* s, int32_t d, const double* const* u,
  * next call); without one they use the built-in heuristic.  The split counts
  * change the summation order, so results are reproducible for a fixed table.
  * Values are clamped to what the handle allocated.  Set replaces an entry of
- * the same key; returns CTD_EINVAL for non-positive arguments.  The table is
- * measured offline (paper_2410_15519_amd/tune.py) and loaded by the binding. */
+ * the same key; returns CTD_EINVAL for non-positive counts or an unknown
+ * precision.  The table is measured offline (paper_2410_15519_amd/tune.py)
+ * and loaded by the binding. */
+int ctd_tuning_set_prec(int32_t precision, int32_t nb, int32_t nq, int32_t nsplit_g,
+                        int32_t nsplit_h);
+/* The entry of the mixed-precision path (ctd_tuning_set_prec with
+ * CTD_PREC_MIXED). */
 int ctd_tuning_set(int32_t nb, int32_t nq, int32_t nsplit_g, int32_t nsplit_h);
 /* Removes every entry. */
 int ctd_tuning_clear(void);

@@ -48,7 +48,8 @@ struct DevAxis {
   double* Xk;       // n x Mcap, factors of u^k
   double* MXk;      // n x Mcap, M X^k
   double* Xh;       // nq x ldh, Phi X^k sigma^(1/D) (row-major)
-  float* Xhf;
+  float* Xhf;       // FP32 copy, tile-major: [a / 16][q][slot] (3D h contraction)
+  float* Xhg;       // FP32 copy for the 3D g contraction: [a / 16][q / 4][a % 16][q % 4]
   double* X;        // n x Mcap, factors of u^{k+1}
   double* MX;
   double* KX;

@@ -118,6 +118,10 @@ __global__ void k_quad_eval(DevAxis A, int Mk, int ldh, const double* sk,
       const size_t nqp = (size_t)(A.nq + 63) / 64 * 64;
       const int i = a & 15;
       dst = ((size_t)(a >> 4) * nqp + q) * kTile + ((i & 3) << 2) + (i >> 2);
+      // the g contraction's copy groups four consecutive points per mode:
+      // [a / 16][q / 4][a % 16][q % 4], a 16-byte word holding one mode at
+      // four points
+      A.Xhg[((size_t)(a >> 4) * (nqp >> 2) + (q >> 2)) * 64 + i * 4 + (q & 3)] = (float)val;
     }
     A.Xhf[dst] = (float)val;
   }
@@ -1607,7 +1611,7 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
   constexpr int VW = kGChunk * 4 / 16;              // words of v per chunk
   constexpr int SS = kGChunk * kTile;               // segment stride (floats)
   const DevAxis& A = I.ax[d];
-  const float* Y = A.Xhf;
+  const float* Y = A.Xhg;
   const float* vq = A.vf;
   const int nd = I.ntri_d, np = I.ntri_p;
   const int b = blockIdx.x;
@@ -1652,23 +1656,21 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
   const int tid = threadIdx.x, l = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const size_t nqp = (size_t)(nq + 63) / 64 * 64;
-  // word f = tid + 256 k of a chunk: segment f / 256 (= k), point
-  // (f % 256) / 4, part f % 4 (the tile-major table: a wave reads 1 KB of
-  // consecutive memory)
+  // word f = tid + 256 k of a chunk: segment f / 256 (= k), point group
+  // (f % 256) / 16, mode f % 16 (four consecutive points of one mode per
+  // word; a wave reads 1 KB of consecutive memory)
   auto load_chunk = [&](int q0, uint4* ys, uint4* vs) {
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
       const int f = tid + 256 * k;
-      const int arr = f >> 8, row = (f & 255) >> 2, part = f & 3;
-      const float* src = Y + ((size_t)(col0[arr] >> 4) * nqp + q0 + row) * kTile + part * 4;
+      const int arr = f >> 8, wi = f & 255;
+      const float* src = Y + (((size_t)(col0[arr] >> 4) * (nqp >> 2) + (q0 >> 2)) * 16 + wi) * 4;
       __builtin_amdgcn_global_load_lds((const void*)src, CTD_LDS(ys + 256 * k + 64 * w), 16, 0, 0);
     }
     if (w == 0 && l < VW)
       __builtin_amdgcn_global_load_lds((const void*)((const uint4*)(vq + q0) + l), CTD_LDS(vs), 16, 0, 0);
   };
-  const int e = l & 15;
-  auto slot = [](int m) { return ((m & 3) << 2) + (m >> 2); };   // mode m of a tile row
-  const int es = slot(e);
+  const int e = l & 15, kk = l >> 4;   // A row / B column mode e; MFMA k index kk
   auto chunk_loop = [&](auto compute) {
     auto step = [&](int ci, const uint4* ys, const uint4* vs, uint4* ysn, uint4* vsn) {
       if (ci + 1 < nchunk) load_chunk(qbeg + (ci + 1) * kGChunk, ysn, vsn);
@@ -1688,17 +1690,27 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
     f4 acc[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[r] = f4{0, 0, 0, 0};
+    // lane group kk takes the chunk's points 16 kk .. 16 kk + 15, four per
+    // 16-byte word: per word group the B-row, C-column, v and the wave's
+    // four A-mode values are one LDS read each, for four k-steps
     chunk_loop([&](const float* ys, const float* vs) {
+      const float4* yw = (const float4*)ys;
+      const float4* vw = (const float4*)vs;
 #pragma unroll
-      for (int ks = 0; ks < kGChunk / 4; ++ks) {
-        const int qq = ks * 4 + (l >> 4);
-        const float* yr = ys + qq * kTile;
-        const float bval = yr[2 * SS + es];
-        const float ybv = yr[SS + es] * vs[qq];
+      for (int G = 0; G < 4; ++G) {
+        const int grp = 4 * kk + G;
+        const float4 yb = yw[256 + grp * 16 + e];
+        const float4 yc = yw[512 + grp * 16 + e];
+        const float4 vv = vw[grp];
+        float4 ya[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          // chain r: mode w + 4 r of A, slot 4 w + r (the wave's four values are one word)
-          acc[r] = mfma16(yr[w * 4 + r] * ybv, bval, acc[r]);
+        for (int r = 0; r < 4; ++r) ya[r] = yw[grp * 16 + w + 4 * r];   // chain r: mode w + 4 r of A
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const float ybv = yb[p] * vv[p];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[r] = mfma16(ya[r][p] * ybv, yc[p], acc[r]);
+        }
       }
     });
     float* out = gp + ((size_t)rank * I.nsplit_g + split) * TS;
@@ -1712,21 +1724,26 @@ __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
   // repeated tile: pair tile and column tile (segments of the chunk)
   const bool p2 = tr.x < tr.y;                        // A < B = C: pairs of B, columns A
   const int pa = p2 ? 1 : 0, pc = p2 ? 0 : 2;
-  int off[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) off[k] = pa * SS + slot((e + k) & 15);
   f4 acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = f4{0, 0, 0, 0};
+  // wave w takes the chunk's points 16 w .. 16 w + 15, lane group kk four
+  // of them (one word group); the pair tile's modes e .. e + 8 (mod 16),
+  // the column mode e and v are one LDS read each for four k-steps
   chunk_loop([&](const float* ys, const float* vs) {
-#pragma unroll 1
-    for (int ks = 0; ks < 4; ++ks) {
-      const int qq = w * 16 + ks * 4 + (l >> 4);      // this lane's point of the chunk
-      const float* yr = ys + qq * kTile;
-      const float own = yr[off[0]] * vs[qq];
-      const float bval = yr[pc * SS + es];
+    const float4* yw = (const float4*)ys;
+    const float4* vw = (const float4*)vs;
+    const int grp = 4 * w + kk;
+    float4 yp[9];
 #pragma unroll
-      for (int k = 0; k < 9; ++k) acc[k] = mfma16(own * yr[off[k]], bval, acc[k]);
+    for (int k = 0; k < 9; ++k) yp[k] = yw[pa * 256 + grp * 16 + ((e + k) & 15)];
+    const float4 yc = yw[pc * 256 + grp * 16 + e];
+    const float4 vv = vw[grp];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const float own = yp[0][p] * vv[p];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) acc[k] = mfma16(own * yp[k][p], yc[p], acc[k]);
     }
   });
   // add the four waves' sums (wave order), three blocks at a time

@@ -380,12 +380,13 @@ void make_h_order(const std::vector<int4>& tri, std::vector<int4>& trih, std::ve
 // ---- tuning table of the 3D cubic contraction (see ctd_tuning_set)
 namespace {
 std::mutex g_tune_mu;
-std::map<std::pair<int, int>, std::pair<int, int>> g_tune;   // (nb, nq) -> (nsplit_g, nsplit_h)
+// (precision, nb, nq) -> (nsplit_g, nsplit_h)
+std::map<std::tuple<int, int, int>, std::pair<int, int>> g_tune;
 }  // namespace
 
-bool tuning_lookup(int nb, int nq, int& ng, int& nh) {
+bool tuning_lookup(int prec, int nb, int nq, int& ng, int& nh) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find({nb, nq});
+  auto it = g_tune.find({prec, nb, nq});
   if (it == g_tune.end()) return false;
   ng = it->second.first;
   nh = it->second.second;
@@ -495,15 +496,16 @@ void update_view(ctd_solver* s) {
     // when there are at least 8 (XCD-aware split mapping in the kernel)
     int ng = std::max(1, std::min((1024 + I.ntri - 1) / I.ntri, (nqmin + 63) / 64));
     if (ng >= 8) ng = ng / 8 * 8;
-    // h: two rounds of resident workgroups (the second round evens out the
-    // workgroups' unequal lengths), triples split by MFMA work
+    // h, triples split by MFMA work: FP32 two rounds of resident workgroups
+    // (the second round evens out the workgroups' unequal lengths); FP64
+    // one round (measured at 1024^3: 3 splits 175 us, 12 splits 194 us)
     const int nqt = (nqmin + cubic_h_rows(I) - 1) / cubic_h_rows(I);
     const int per_cu = std::max(1, std::min(8, cubic_h_blocks_per_cu(I)));
     const int slots = num_cus() * per_cu;
-    int nh = 2 * slots / nqt;
-    // a measured table entry for this shape replaces the heuristic
+    int nh = (I.mixed ? 2 : 1) * slots / nqt;
+    // a measured table entry for this precision and shape replaces the heuristic
     int tg = 0, th = 0;
-    if (tuning_lookup(I.nb, nqmin, tg, th)) {
+    if (tuning_lookup(I.mixed ? CTD_PREC_MIXED : CTD_PREC_FP64, I.nb, nqmin, tg, th)) {
       ng = tg;
       nh = th;
     } else {
@@ -599,6 +601,7 @@ int alloc_instance(ctd_solver* s, int m0) {
     const size_t nqp = (nq + 63) / 64 * 64;
     AL(X.Xh, sizeof(double) * nqp * s->Mkp_max);
     if (mixed) AL(X.Xhf, sizeof(float) * nqp * s->Mkp_max);
+    if (mixed && s->dim == 3) AL(X.Xhg, sizeof(float) * nqp * s->Mkp_max);
     AL(X.X, sizeof(double) * n * M);
     AL(X.MX, sizeof(double) * n * M);
     AL(X.KX, sizeof(double) * n * M);
@@ -2128,11 +2131,18 @@ void solver_bind_stream(ctd_solver* s, hipStream_t st) {
 size_t solver_device_bytes(const ctd_solver* s) { return s->arena.bytes; }
 }  // namespace ctd
 
-extern "C" int ctd_tuning_set(int32_t nb, int32_t nq, int32_t nsplit_g, int32_t nsplit_h) {
-  if (nb < 1 || nq < 1 || nsplit_g < 1 || nsplit_h < 1) return CTD_EINVAL;
+extern "C" int ctd_tuning_set_prec(int32_t precision, int32_t nb, int32_t nq, int32_t nsplit_g,
+                                   int32_t nsplit_h) {
+  if ((precision != CTD_PREC_FP64 && precision != CTD_PREC_MIXED) || nb < 1 || nq < 1 || nsplit_g < 1 ||
+      nsplit_h < 1)
+    return CTD_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  g_tune[{nb, nq}] = {nsplit_g, nsplit_h};
+  g_tune[{precision, nb, nq}] = {nsplit_g, nsplit_h};
   return CTD_OK;
+}
+
+extern "C" int ctd_tuning_set(int32_t nb, int32_t nq, int32_t nsplit_g, int32_t nsplit_h) {
+  return ctd_tuning_set_prec(CTD_PREC_MIXED, nb, nq, nsplit_g, nsplit_h);
 }
 
 extern "C" int ctd_tuning_clear(void) {

@@ -142,6 +142,7 @@ def _load():
         "ctd_profile_enable": (C.c_int, [vp, C.c_int32]),
         "ctd_profile_select": (C.c_int, [vp, C.c_uint32]),
         "ctd_tuning_set": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+        "ctd_tuning_set_prec": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "ctd_tuning_clear": (C.c_int, []),
         "ctd_tuning_current": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
         "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
@@ -159,9 +160,10 @@ LIB = _load()
 TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 
-def tuning_set(nb, nq, nsplit_g, nsplit_h):
-    """ctd_tuning_set: split counts of the 3D cubic contraction for (nb, nq)."""
-    rc = LIB.ctd_tuning_set(int(nb), int(nq), int(nsplit_g), int(nsplit_h))
+def tuning_set(nb, nq, nsplit_g, nsplit_h, precision="mixed"):
+    """ctd_tuning_set_prec: split counts of the 3D cubic contraction for
+    (precision, nb, nq)."""
+    rc = LIB.ctd_tuning_set_prec(PREC[precision], int(nb), int(nq), int(nsplit_g), int(nsplit_h))
     if rc != CTD_OK:
         raise CtdError(rc, "ctd_tuning_set")
 
@@ -179,7 +181,7 @@ def tuning_load(path=TUNING_PATH):
     with open(path) as f:
         table = json.load(f)
     for e in table.get("entries", []):
-        tuning_set(e["nb"], e["nq"], e["nsplit_g"], e["nsplit_h"])
+        tuning_set(e["nb"], e["nq"], e["nsplit_g"], e["nsplit_h"], e.get("precision", "mixed"))
     return len(table.get("entries", []))
 
 

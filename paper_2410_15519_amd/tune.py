@@ -1,7 +1,7 @@
 """Offline tuning of the split counts of the 3D cubic contraction.
 
-For each mode-tile count nb = 1..ceil(max_modes / 16) of a workload's shape,
-times ctd_nonlinear_load (signature, the two g contractions with their split
+For each precision and mode-tile count nb = 1..ceil(max_modes / 16) of a
+workload's shape, times ctd_nonlinear_load (signature, the two g contractions with their split
 reductions, h and the projected load: the sequence a directional solve runs
 before its right-hand side) for candidate (nsplit_g, nsplit_h) pairs, and
 writes the fastest pair per (nb, nq) to a JSON table that the binding loads
@@ -47,6 +47,7 @@ def main():
     ap.add_argument("--out", default=os.path.join(HERE, "tuning.json"))
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--max-nb", type=int, default=0, help="largest tile count (default: from max_modes)")
+    ap.add_argument("--precisions", default="mixed,fp64")
     args = ap.parse_args()
 
     import numpy as np
@@ -63,40 +64,41 @@ def main():
     u = [rng.uniform(-1.0, 1.0, int(n)) for n in base.nodes]
     ctd.tuning_clear()
     entries = []
-    for nb in range(1, nbmax + 1):
-        inst = make_instance(args.workload, m0=16 * nb)
-        with ctd.Solver(inst, precision="mixed") as s:
-            default = s.tuning_current()
-            t_def = time_load(s, u, 3, args.reps)
-            best = (t_def, default[0], default[1])
-            for g in G_CANDIDATES:
-                for h in H_CANDIDATES:
-                    ctd.tuning_set(nb, nq, g, h)
-                    s.nonlinear_load(0, u)          # picks up the entry
-                    used = s.tuning_current()
-                    if used != (g, h):              # clamped: same as another candidate
-                        continue
-                    t = time_load(s, u, 3, args.reps)
-                    if t < best[0]:
-                        best = (t, g, h)
-            # confirm against the heuristic, measured alternately (run-to-run
-            # noise is a few per cent); keep the heuristic unless the
-            # candidate wins by more than 3 %
-            tb, td = [], []
-            for _ in range(3):
-                ctd.tuning_set(nb, nq, best[1], best[2])
-                s.nonlinear_load(0, u)
-                tb.append(time_load(s, u, 3, args.reps))
-                ctd.tuning_clear()
-                s.nonlinear_load(0, u)
-                td.append(time_load(s, u, 3, args.reps))
-            t_def = min(td)
-            best = (min(tb), best[1], best[2]) if min(tb) < 0.97 * t_def else (t_def, default[0], default[1])
-        print(f"nb={nb} (M_k={16 * nb}): default {default} {t_def * 1e6:.1f} us, "
-              f"best ({best[1]}, {best[2]}) {best[0] * 1e6:.1f} us", flush=True)
-        entries.append({"nb": nb, "nq": nq, "nsplit_g": best[1], "nsplit_h": best[2],
-                        "us": round(best[0] * 1e6, 1), "default": list(default),
-                        "default_us": round(t_def * 1e6, 1)})
+    for prec in args.precisions.split(","):
+        for nb in range(1, nbmax + 1):
+            inst = make_instance(args.workload, m0=16 * nb)
+            with ctd.Solver(inst, precision=prec) as s:
+                default = s.tuning_current()
+                t_def = time_load(s, u, 3, args.reps)
+                best = (t_def, default[0], default[1])
+                for g in G_CANDIDATES:
+                    for h in H_CANDIDATES:
+                        ctd.tuning_set(nb, nq, g, h, precision=prec)
+                        s.nonlinear_load(0, u)          # picks up the entry
+                        used = s.tuning_current()
+                        if used != (g, h):              # clamped: same as another candidate
+                            continue
+                        t = time_load(s, u, 3, args.reps)
+                        if t < best[0]:
+                            best = (t, g, h)
+                # confirm against the heuristic, measured alternately (run-to-run
+                # noise is a few per cent); keep the heuristic unless the
+                # candidate wins by more than 3 %
+                tb, td = [], []
+                for _ in range(3):
+                    ctd.tuning_set(nb, nq, best[1], best[2], precision=prec)
+                    s.nonlinear_load(0, u)
+                    tb.append(time_load(s, u, 3, args.reps))
+                    ctd.tuning_clear()
+                    s.nonlinear_load(0, u)
+                    td.append(time_load(s, u, 3, args.reps))
+                t_def = min(td)
+                best = (min(tb), best[1], best[2]) if min(tb) < 0.97 * t_def else (t_def, default[0], default[1])
+            print(f"{prec} nb={nb} (M_k={16 * nb}): default {default} {t_def * 1e6:.1f} us, "
+                  f"best ({best[1]}, {best[2]}) {best[0] * 1e6:.1f} us", flush=True)
+            entries.append({"precision": prec, "nb": nb, "nq": nq, "nsplit_g": best[1],
+                            "nsplit_h": best[2], "us": round(best[0] * 1e6, 1), "default": list(default),
+                            "default_us": round(t_def * 1e6, 1)})
     table = {"workload": args.workload, "device": torch.cuda.get_device_properties(0).name,
              "timed": "ctd_nonlinear_load per direction, median of reps (us)",
              "entries": entries}

@@ -111,15 +111,22 @@ def test_tuning_table_arguments_and_file():
     assert ctd.LIB.ctd_tuning_set(1, 100, 0, 8) == -1
     assert ctd.LIB.ctd_tuning_set(1, 100, 8, -1) == -1
     assert ctd.LIB.ctd_tuning_set(1, 100, 8, 8) == 0
+    assert ctd.LIB.ctd_tuning_set_prec(2, 1, 100, 8, 8) == -1
+    assert ctd.LIB.ctd_tuning_set_prec(0, 1, 100, 8, 8) == 0
     assert ctd.LIB.ctd_tuning_current(None, None, None) == -1
     assert ctd.LIB.ctd_tuning_clear() == 0
     if os.path.exists(ctd.TUNING_PATH):
         with open(ctd.TUNING_PATH) as f:
             table = json.load(f)
-        nbs = [e["nb"] for e in table["entries"]]
-        assert nbs == sorted(set(nbs))
+        # one entry per (precision, mode-tile count), tile counts ascending
+        keys = [(e.get("precision", "mixed"), e["nb"]) for e in table["entries"]]
+        assert len(keys) == len(set(keys))
+        for prec in {k[0] for k in keys}:
+            assert prec in ("mixed", "fp64")
+            nbs = [k[1] for k in keys if k[0] == prec]
+            assert nbs == sorted(nbs)
         assert all(e["nsplit_g"] >= 1 and e["nsplit_h"] >= 1 and e["nq"] >= 1 for e in table["entries"])
-        assert ctd.tuning_load() == len(nbs)
+        assert ctd.tuning_load() == len(keys)
         ctd.tuning_clear()
         ctd.tuning_load()
 

@@ -31,7 +31,7 @@ def test_tuned_splits_keep_the_load(ctd, prec, tol, splits):
     nq = min((n - 1) * 5 for n in inst.nodes)
     nb = (40 + 15) // 16
     try:
-        ctd.tuning_set(nb, nq, *splits)
+        ctd.tuning_set(nb, nq, *splits, precision=prec)
         with ctd.Solver(inst, precision=prec) as s:
             for d in range(3):
                 got = s.nonlinear_load(d, u)
