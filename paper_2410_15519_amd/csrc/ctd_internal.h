@@ -171,6 +171,9 @@ hipError_t launch_finalize(const DevInst& I, int d, int sweep, int from_init,
 // (one workgroup per direction; all axes share the band width)
 hipError_t launch_finalize_init(const DevInst& I, hipStream_t st);
 hipError_t launch_signature(const DevInst& I, int d, int M, hipStream_t st);
+// launch_finalize (sweep, fast-diagonalisation partials) and launch_signature
+// of the same direction in one launch, with the same results
+hipError_t launch_finalize_sig(const DevInst& I, int d, int sweep, int M, hipStream_t st, int nparts);
 hipError_t launch_signature_all(const DevInst& I, int M, hipStream_t st);   // every direction, one launch
 hipError_t launch_rhs(const DevInst& I, int d, int M, hipStream_t st, int load_only = 0);
 hipError_t launch_rhs_sum(const DevInst& I, int d, int M, int load_only, hipStream_t st);

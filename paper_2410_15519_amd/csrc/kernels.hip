@@ -278,9 +278,12 @@ __device__ __forceinline__ double band_row_apply(const BandRow<B>& r, int n, con
 // M u, K u, and the Gram scalars of the fixed-point test.  One fused pass:
 // the sums of the unnormalised u are rescaled by 1/sigma afterwards.
 // red: >= 96 doubles of LDS; ul: 3n doubles of scratch (LDS) for u, M u, K u.
+// writer = false (the fused normalisation + Grams launch): the same sums,
+// but no stores to the instance; the normalised factor is left in ul for the
+// caller (the previous factor is not read: only the writer needs it).
 template <int B>
 __device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep, int from_init, double* red, double* ul,
-                              int nparts = 0) {
+                              int nparts = 0, bool writer = true) {
   const DevAxis& A = I.ax[d];
   DevScalars* sc = I.sc;
   const int n = A.n;
@@ -289,7 +292,7 @@ __device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep
   // the other directions' Gram scalars of the fixed-point test, requested
   // at the start (they were written by earlier launches)
   double puu_o = 1.0, pupup_o = 1.0, puup_o = 1.0, sigma_prev = 0.0;
-  if (threadIdx.x == 0 && !from_init && d == I.dim - 1) {
+  if (writer && threadIdx.x == 0 && !from_init && d == I.dim - 1) {
     double a0[kMaxDim], a1[kMaxDim], a2[kMaxDim];
 #pragma unroll
     for (int e = 0; e < kMaxDim; ++e) {
@@ -316,7 +319,7 @@ __device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep
   if (one) {
     band_row_load<B>(A.Mb, n, i1, rm);
     band_row_load<B>(A.Kb, n, i1, rk);
-    up1 = A.up[i1];
+    up1 = writer ? A.up[i1] : 0.0;
   }
   // the solved factor: u, or the sum of the back-projection partials (fixed order)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -341,7 +344,7 @@ __device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep
     const double ku = one ? band_row_apply<B>(rk, n, ul, i) : band_row_lds<B>(A.Kb, n, ul, i);
     ml[i] = mu;
     kl[i] = ku;
-    const double u = ul[i], up = one ? up1 : A.up[i];
+    const double u = ul[i], up = one ? up1 : (writer ? A.up[i] : 0.0);
     acc[0] += u * mu;
     acc[1] += u * ku;
     acc[2] += u * u;
@@ -360,10 +363,18 @@ __device__ __forceinline__ void finalize_body(const DevInst& I, int d, int sweep
   um *= inv;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     double u = ul[i] * inv;
+    if (!writer) {
+      ul[i] = u;
+      continue;
+    }
     A.u[i] = u;
     A.up[i] = u;
     A.Mu[i] = ml[i] * inv;
     A.Ku[i] = kl[i] * inv;
+  }
+  if (!writer) {
+    __syncthreads();
+    return;
   }
   if (threadIdx.x == 0) {
     sc->m[d] = m;
@@ -501,6 +512,76 @@ hipError_t launch_signature_all(const DevInst& I, int M, hipStream_t st) {
   for (int e = 0; want_v && e < I.dim; ++e) nv = nv > (I.ax[e].nq + 255) / 256 ? nv : (I.ax[e].nq + 255) / 256;
   if (ndot + nv == 0) return hipSuccess;
   k_signature<<<dim3(ndot + nv, I.dim), 256, 0, st>>>(I, -1, M, ndot, want_v);
+  return hipGetLastError();
+}
+
+// Normalisation and Grams in one launch (fast-diagonalisation solves: the
+// raw factor is the sum of the back-projection partials, which nothing in
+// the launch writes).  Workgroup 0 is k_finalize's (stores the factor, M u,
+// K u, the previous-sweep copy and the scalars); every other workgroup
+// forms the same normalised factor in LDS with the same sums in the same
+// order (so its values are those workgroup 0 stores) and then does one
+// block of k_signature's work: one stored column's Gram per wave, or the
+// Gauss-point values of nt points.  Saves a launch and its dependent
+// round trip per directional solve; the results equal the two-launch
+// sequence bitwise.
+template <int B>
+__global__ __launch_bounds__(1024) void k_finalize_sig(DevInst I, int d, int sweep, int M, int ndot_blocks,
+                                                       int want_v, int nparts) {
+  if (spec_skip(I)) return;
+  __shared__ double red[96];
+  extern __shared__ double ul[];
+  const int b = blockIdx.x;
+  finalize_body<B>(I, d, sweep, 0, red, ul, nparts, b == 0);
+  if (b == 0) return;
+  const DevAxis& A = I.ax[d];
+  const int n = A.n;
+  const int nw = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (b - 1 < ndot_blocks) {
+    const int idx = (b - 1) * nw + w;
+    const int total = 2 * M + I.Mk;
+    if (idx >= total) return;
+    const double* col;
+    double* out;
+    if (idx < M) { col = A.MX + (size_t)idx * n; out = A.gm + idx; }
+    else if (idx < 2 * M) { col = A.KX + (size_t)(idx - M) * n; out = A.gk + (idx - M); }
+    else { col = A.MXk + (size_t)(idx - 2 * M) * n; out = A.gmk + (idx - 2 * M); }
+    double sum = 0.0;
+#pragma unroll 16
+    for (int i = l; i < n; i += 64) sum += col[i] * ul[i];
+    sum = wave_sum(sum);
+    if (l == 0) *out = sum;
+    return;
+  }
+  if (!want_v) return;
+  const int q = (b - 1 - ndot_blocks) * blockDim.x + threadIdx.x;
+  if (q >= A.nq) return;
+  const int st = elem_start(q / A.ng, A.s, n, A.SW);
+  const double* ph = A.phi + (size_t)q * A.SW;
+  double val = 0.0;
+  for (int j = 0; j < A.SW; ++j) val += ph[j] * ul[st + j];
+  val *= A.w[q];
+  A.v[q] = val;
+  if (I.mixed) A.vf[q] = (float)val;
+}
+
+hipError_t launch_finalize_sig(const DevInst& I, int d, int sweep, int M, hipStream_t st, int nparts) {
+  if (nparts <= 0) return hipErrorInvalidValue;   // the raw factor must not be the one workgroup 0 stores
+  const int n = I.ax[d].n;
+  const size_t shm = sizeof(double) * 3 * (size_t)n;
+  const int nt = n >= 1024 ? 1024 : (n + 63) / 64 * 64;
+  const int total = 2 * M + I.Mk;
+  const int ndot = (total + nt / 64 - 1) / (nt / 64);
+  const int want_v = I.dim == 3;
+  const int nv = want_v ? (I.ax[d].nq + nt - 1) / nt : 0;
+  const dim3 grid(1 + ndot + nv);
+  switch (I.ax[d].B) {
+    case 3: k_finalize_sig<3><<<grid, nt, shm, st>>>(I, d, sweep, M, ndot, want_v, nparts); break;
+    case 5: k_finalize_sig<5><<<grid, nt, shm, st>>>(I, d, sweep, M, ndot, want_v, nparts); break;
+    case 7: k_finalize_sig<7><<<grid, nt, shm, st>>>(I, d, sweep, M, ndot, want_v, nparts); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -2937,7 +3018,9 @@ hipError_t configure_kernels() {
                       (const void*)k_solve_bcr_m<5, 2>, (const void*)k_solve_bcr_m<7, 2>,
                       (const void*)k_finalize_init_m<3>, (const void*)k_finalize_init_m<5>,
                       (const void*)k_finalize_init_m<7>, (const void*)k_finalize<3>,
-                      (const void*)k_finalize<5>, (const void*)k_finalize<7>};
+                      (const void*)k_finalize<5>, (const void*)k_finalize<7>,
+                      (const void*)k_finalize_sig<3>, (const void*)k_finalize_sig<5>,
+                      (const void*)k_finalize_sig<7>};
   for (const void* k : ks)
     (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipGetLastError();

@@ -1120,25 +1120,32 @@ int one_step(ctd_solver* s, const int32_t* replay, int replay_len, ctd_step_info
           LAUNCH(s, CTD_K_RHS, w.flops, w.bytes, launch_rhs(s->I, d, M, s->stream));
           Work ws = w_solve(s, d);
           if (s->use_fd[d]) {
+            // the normalisation and the fresh factor's Grams in one launch
             LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_fd(s->I, d, M, s->stream));
-            LAUNCH(s, CTD_K_FINALIZE, 0.0, 0.0, launch_finalize(s->I, d, it, 0, s->stream, kFdKb));
+            Work wg = w_sig(s, d, M);
+            LAUNCH(s, CTD_K_FINALIZE, wg.flops, wg.bytes, launch_finalize_sig(s->I, d, it, M, s->stream, kFdKb));
           } else {
             LAUNCH(s, CTD_K_SOLVE, ws.flops, ws.bytes, launch_solve_bcr(s->I, d, it, M, s->stream));
           }
         }
         if (d < D - 1) {
-          Work w = w_sig(s, d, M);
-          LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
+          if (!s->use_fd[d]) {
+            Work w = w_sig(s, d, M);
+            LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, d, M, s->stream));
+          }
           int rc = cubic_after(s, d, d + 1);
           if (rc) return rc;
         }
       }
       return CTD_OK;
     };
-    // the start of a further sweep: the last direction's Grams
+    // the start of a further sweep: the last direction's Grams (unless its
+    // normalisation launch made them) and the cubic Grams
     auto carry = [&]() -> int {
-      Work w = w_sig(s, D - 1, M);
-      LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
+      if (!s->use_fd[D - 1]) {
+        Work w = w_sig(s, D - 1, M);
+        LAUNCH(s, CTD_K_SIGNATURE, w.flops, w.bytes, launch_signature(s->I, D - 1, M, s->stream));
+      }
       return cubic_after(s, D - 1, 0);
     };
     // Adaptive: sweep it + 1 is enqueued before the host waits for the
