@@ -62,7 +62,7 @@ PEAK = {"fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "hbm": 8.0e12}
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "ctd_step_ac3d_n1024_mixed_hbm_traffic.md")
 # kernel [grid work-items] of each class at the timed shape (M_k = 128)
 KERNEL_NAMES = {"cubic_g": "k_cubic_g32 [245760]", "cubic_h": "k_cubic_h32 [512000]",
-                "cubic_gred": "k_cubic_gred32 [491520]", "finalize": "k_finalize<5> [1024]"}
+                "cubic_gred": "k_cubic_gred32 [491520]"}
 
 
 def log(*a):
