@@ -46,3 +46,31 @@ def test_tuned_splits_keep_the_load(ctd, prec, tol, splits):
     finally:
         ctd.tuning_clear()
         ctd.tuning_load()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 1e-6)])
+def test_many_h_splits_keep_the_load(ctd, prec, tol):
+    """More h splits than the balanced split table holds (84 triples at 112
+    modes, 80 splits): the equal-count triple ranges, against the oracle."""
+    from oracle.ctd import SeparatedNonlinear, state_from_instance
+    from oracle.scheme import problem_from_instance
+    inst = small_instance(3, (21, 19, 17), m0=112, kmax=7, max_modes=112)
+    ref_of = SeparatedNonlinear(problem_from_instance(inst), state_from_instance(inst))
+    rng = np.random.default_rng(11)
+    u = [rng.uniform(-1, 1, n) for n in inst.nodes]
+    nq = min((n - 1) * 5 for n in inst.nodes)
+    nb = (112 + 15) // 16
+    try:
+        ctd.tuning_set(nb, nq, 2, 80, precision=prec)
+        with ctd.Solver(inst, precision=prec) as s:
+            for d in range(3):
+                got = s.nonlinear_load(d, u)
+                g, h = s.tuning_current()
+                assert h == 80
+                ref = ref_of(d, u)
+                err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+                print(f"80 h splits {prec} d={d}: {err:.2e}", flush=True)
+                assert err < tol
+    finally:
+        ctd.tuning_clear()
+        ctd.tuning_load()
