@@ -274,6 +274,7 @@ hipError_t launch_field_contract(const double* R, const int* dims, int d, const 
 hipError_t launch_field_eig(const double* X, double* Y, const int* dims, int a, const double* V, int forward,
                             hipStream_t st);
 hipError_t launch_field_to_f32(const double* X, float* Y, int64_t total, hipStream_t st);
+constexpr int kLoadSub = 4;      // 3D cubic load: RHS chunks of 16-row sub-blocks of a 64-row block
 constexpr int kFieldParts = 8;   // load chunks of a directional solve from a 3D field state
 hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
 hipError_t configure_kernels();

@@ -591,7 +591,7 @@ hipError_t launch_finalize_sig(const DevInst& I, int d, int sweep, int M, hipStr
 // ck = c with the 2D M_xy load (which contains the full w), ck = c + omega
 // with the 3D cubic load F_d = omega Phi^T W h.
 // Grid: row blocks of 64 x (column chunks of 64 over [MXk | MX | KX], plus
-// the load chunks: 3D one chunk for -F_d; 2D the columns of the M_xy
+// the load chunks: 3D four chunks for -F_d (16 rows each); 2D the columns of the M_xy
 // product F_d = M_xy u_e (d = 0) or M_xy^T u_e (d = 1), 64 per chunk, each
 // column stored contiguously over the rows of d (a row of M_xy^T or M_xy)).
 // Each block writes its partial sums to rpart[chunk][row]; the solve kernel
@@ -694,16 +694,20 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
     if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = part[l] + part[64 + l] + part[128 + l] + part[192 + l];
     return;
   }
-  // chunk nchunk: the projected nonlinear load F_i = omega sum_q Phi[q, i] W_q h_q
-  // over the elements around the 64 rows; h and the Phi rows of those
+  // chunks nchunk + s, s < kLoadSub: the projected nonlinear load
+  // F_i = omega sum_q Phi[q, i] W_q h_q of rows r0 + 16 s .. r0 + 16 s + 15
+  // (zero in the block's other rows), so that a workgroup sums the h splits
+  // of only the Gauss points around 16 rows; h and the Phi rows of those
   // elements are staged in LDS, and the elements of a row are split over the
-  // four waves (summed in wave order).
+  // four waves (summed in wave order).  A row's sum is the same whichever
+  // sub-chunk computes it, and the solve adds the zeros exactly.
   double F = 0.0;
   {
     const int ne = n - 1;
     const int SW = A.SW;
-    const int e_lo = r0 - SW > 0 ? r0 - SW : 0;
-    const int e_hi = r0 + 63 + SW < ne - 1 ? r0 + 63 + SW : ne - 1;
+    const int ra = r0 + 16 * (y - nchunk), rb = ra + 16;
+    const int e_lo = ra - SW > 0 ? ra - SW : 0;
+    const int e_hi = rb - 1 + SW < ne - 1 ? rb - 1 + SW : ne - 1;
     const int q_lo = e_lo * A.ng, qcount = (e_hi - e_lo + 1) * A.ng;
     double* phl = hl + qcount;    // qcount x SW
     for (int idx = tid; idx < qcount; idx += blockDim.x) {
@@ -724,7 +728,7 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
       phl[idx] = A.phi[(size_t)q_lo * SW + idx];
     __syncthreads();
     double Fw = 0.0;
-    if (i < n) {
+    if (i < n && i >= ra && i < rb) {
       int e0 = i - SW;
       e0 = e0 < e_lo ? e_lo : e0;
       int e1 = i + SW;
@@ -743,7 +747,7 @@ __device__ __forceinline__ void rhs_body(const DevInst& I, int d, int M, int loa
     __syncthreads();
     if (w == 0) F = I.omega * (part[l] + part[64 + l] + part[128 + l] + part[192 + l]);
   }
-  if (w == 0 && i < n) A.rpart[(size_t)nchunk * n + i] = load_only ? F : -F;
+  if (w == 0 && i < n) A.rpart[(size_t)y * n + i] = load_only ? F : -F;
 }
 
 __global__ __launch_bounds__(256) void k_rhs(DevInst I, int d, int M, int load_only, int nchunk) {
@@ -758,7 +762,7 @@ static int rhs_linear_chunks(const DevInst& I, int M, int load_only) {
 
 int rhs_load_chunks(const DevInst& I, int d) {
   if (I.dim == 2) return (I.ax[1 - d].n + 63) / 64;
-  return I.fparts > 0 ? I.fparts : 1;
+  return I.fparts > 0 ? I.fparts : kLoadSub;
 }
 
 int rhs_chunks(const DevInst& I, int d, int M, int load_only) {

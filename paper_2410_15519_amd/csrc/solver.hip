@@ -612,7 +612,8 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(X.rhs, sizeof(double) * n);
     // RHS partials: linear column chunks, then the load chunks (2D: the
     // columns of the M_xy product, 64 per chunk)
-    const size_t nload = s->dim == 2 ? (size_t)(s->ax[1 - d].n + 63) / 64 : (s->actd ? kFieldParts : 1);
+    const size_t nload = s->dim == 2 ? (size_t)(s->ax[1 - d].n + 63) / 64
+                                     : (size_t)std::max(kLoadSub, s->actd ? kFieldParts : 0);
     AL(X.rpart, sizeof(double) * n * ((size_t)(3 * s->Mcap + 63) / 64 + nload));
     AL(X.v, sizeof(double) * nqp);
     if (mixed) AL(X.vf, sizeof(float) * nqp);
