@@ -1673,8 +1673,10 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
 }
 
 // g for the FP32 path, by triple class.  A workgroup takes one triple and
-// one range of Gauss points (split-K), staged in 64-point chunks exactly as
-// in k_cubic_g (global_load_lds into two buffers, one barrier per chunk).
+// one range of Gauss points (split-K), staged in 64-point chunks as in
+// k_cubic_g (global_load_lds into two buffers, one barrier per chunk), from
+// the point-grouped copy of the table (a 16-byte word holds one mode at four
+// consecutive points, so one LDS read serves four k-steps).
 // Triples of three distinct tiles (A < B < C): each wave runs 4 of the 16
 // chains (mode a of A) over every point of a chunk, output blocks (b, c).
 // Triples with a repeated tile hold each unordered mode pair of that tile
@@ -1683,8 +1685,8 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void k_cubic_g(DevInst
 // 16 modes of the other tile as columns; for A = B <= C the pairs are those
 // of A against C, for A < B = C those of B against A.  There each wave runs
 // the 9 blocks over 16 of a chunk's 64 points, the A operand of row i the
-// product Y_i Y_{i+k} v of its own point, and the four waves' sums are added
-// in LDS at the end.  9 blocks instead of 16 chains: the repeated-tile
+// product Y_i Y_{i+k} v of the point, and the four waves' sums are added in
+// LDS at the end.  9 blocks instead of 16 chains: the repeated-tile
 // triples run about 16/9 as many points per split (more points, fewer
 // splits), so all workgroups carry about the same work.
 __global__ __launch_bounds__(256, 4) void k_cubic_g32(DevInst I, int d) {
