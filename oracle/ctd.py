@@ -86,6 +86,24 @@ def full_field(state: State) -> np.ndarray:
 # nonlinear term F_d = int N~_d prod_{e != d} u_e L w(u^k) dOmega
 # ---------------------------------------------------------------------------
 
+def element_wmax(prob, U):
+    """max |w(u^k)| = 4 a0 |u^3 - u| over the Gauss points of each element
+    (e_x, e_y) of the 2D tensor Gauss grid (the Gauss points of axis d are
+    element-major, q = e ng + g)."""
+    ng0, ng1 = prob.axes[0].ng, prob.axes[1].ng
+    w = 4.0 * prob.a0 * np.abs(U ** 3 - U)
+    ne0, ne1 = w.shape[0] // ng0, w.shape[1] // ng1
+    return w.reshape(ne0, ng0, ne1, ng1).max(axis=(1, 3))
+
+
+def element_mask(prob, U):
+    """Reduced domain Omega_r (Sec. 3.3, eq. MxyRD): 0 at every Gauss point of
+    an element whose values of w(u^k) all satisfy |w| <= rd_tol, else 1."""
+    ng0, ng1 = prob.axes[0].ng, prob.axes[1].ng
+    keep = (element_wmax(prob, U) > prob.rd_tol).astype(np.float64)
+    return np.repeat(np.repeat(keep, ng0, axis=0), ng1, axis=1)
+
+
 class FullGridNonlinear:
     """Full integration on the tensor Gauss grid (eq. KxxMxx, the M_xy entry).
 
@@ -104,6 +122,13 @@ class FullGridNonlinear:
         else:
             U = np.einsum("m,im,jm,km->ijk", state_k.sigma, *hats, optimize=True)
         G = prob.omega * (U ** 3 - U)
+        self.excluded = 0
+        if getattr(prob, "rd_tol", 0.0) > 0.0:
+            if D != 2:
+                raise ValueError("the reduced domain is defined for the 2D M_xy")
+            mask = element_mask(prob, U)
+            self.excluded = int(round((mask == 0).sum() / (ax[0].ng * ax[1].ng)))
+            G = G * mask
         for d in range(D):
             shp = [1] * D
             shp[d] = -1

@@ -37,6 +37,10 @@ class Problem:
     max_modes: int = 64
     seed: int = 0
     init: str = "warm"          # "warm" (mode m of u^k when m < M_k) or "hash"
+    # reduced integration domain (Sec. 3.3, eq. MxyRD), 2D: an element whose
+    # Gauss-point values of w(u^k) all have |w| <= rd_tol is left out of the
+    # M_xy integral; 0 leaves out only elements where w vanishes exactly
+    rd_tol: float = 0.0
 
     @property
     def c(self):

@@ -389,3 +389,73 @@ def test_planted_transpose_caught(monkeypatch):
     monkeypatch.setattr(ctdmod.FullGridNonlinear, "__call__", bad)
     new, _ = ctd_step(pr, st, 0, nonlinear="full")
     assert np.linalg.norm(full_field(new) - ref) / np.linalg.norm(ref) > 1e-8
+
+
+# ---------------------------------------------------------------------------
+# reduced integration domain Omega_r (Sec. 3.3, eq. MxyRD), 2D
+# ---------------------------------------------------------------------------
+
+def _gauss_field(pr, st):
+    hats = [np.asarray(pr.axes[d].Phi @ st.factors[d]) for d in range(2)]
+    return (hats[0] * st.sigma) @ hats[1].T
+
+
+def test_reduced_domain_tiny_tolerance_is_the_full_integral():
+    """A tolerance below every element's max |w| leaves nothing out: the
+    masked M_xy is the full one, bitwise."""
+    inst = small_instance(2, (30, 26), m0=4, kmax=3)
+    pr = problem_from_instance(inst)
+    st = state_from_instance(inst)
+    full = ctdmod.FullGridNonlinear(pr, st)
+    pr_r = problem_from_instance(inst, rd_tol=1e-300)
+    red = ctdmod.FullGridNonlinear(pr_r, st)
+    assert red.excluded == 0
+    assert np.array_equal(red.Mxy, full.Mxy)
+
+
+def test_reduced_domain_drops_only_vanishing_elements():
+    """u = 1 on a band (the CFE basis reproduces constants): those elements
+    have |w| at rounding level and are left out; the integral changes by no
+    more than rounding, while the elements across the band's edge stay."""
+    inst = small_instance(2, (24, 30), m0=1, kmax=1)
+    pr = problem_from_instance(inst)
+    n0, n1 = inst.nodes
+    fy = np.where(np.arange(n1) < n1 // 2, 1.0, 0.3)
+    st = State(np.ones(1), [np.ones((n0, 1)), fy.reshape(n1, 1)])
+    full = ctdmod.FullGridNonlinear(pr, st)
+    red = ctdmod.FullGridNonlinear(problem_from_instance(inst, rd_tol=1e-12), st)
+    wmax = ctdmod.element_wmax(pr, _gauss_field(pr, st))
+    assert red.excluded == int((wmax <= 1e-12).sum()) > 0
+    assert (wmax > 1e-3).sum() > 0                     # the rest is kept
+    assert np.abs(red.Mxy - full.Mxy).max() < 1e-12 * np.abs(full.Mxy).max()
+
+
+def test_reduced_domain_against_element_loop():
+    """The masked M_xy against a plain loop over the kept elements and their
+    Gauss points (eq. MxyRD written out), with a tolerance that leaves out a
+    share of the elements and no element near the threshold."""
+    inst = small_instance(2, (12, 10), m0=3, kmax=3)
+    st = state_from_instance(inst)
+    pr0 = problem_from_instance(inst)
+    U = _gauss_field(pr0, st)
+    wmax = ctdmod.element_wmax(pr0, U)
+    tol = float(np.median(wmax))
+    gap = np.abs(wmax - tol) / tol
+    tol *= 1.0 + 0.5 * gap[gap > 0].min()              # strictly between two element maxima
+    pr = problem_from_instance(inst, rd_tol=tol)
+    red = ctdmod.FullGridNonlinear(pr, st)
+    ax0, ax1 = pr.axes
+    P0, P1 = ax0.Phi.toarray(), ax1.Phi.toarray()
+    ref = np.zeros((inst.nodes[0], inst.nodes[1]))
+    dropped = 0
+    for e0 in range(ax0.nq // ax0.ng):
+        for e1 in range(ax1.nq // ax1.ng):
+            pts = [(e0 * ax0.ng + g0, e1 * ax1.ng + g1) for g0 in range(ax0.ng) for g1 in range(ax1.ng)]
+            w = [4.0 * pr.a0 * (U[q0, q1] ** 3 - U[q0, q1]) for q0, q1 in pts]
+            if max(abs(x) for x in w) <= tol:
+                dropped += 1
+                continue
+            for (q0, q1), wq in zip(pts, w):
+                ref += np.outer(P0[q0], P1[q1]) * (pr.L * wq * ax0.W[q0] * ax1.W[q1])
+    assert dropped == red.excluded and 0 < dropped < wmax.size
+    assert np.abs(red.Mxy - ref).max() < 1e-13 * np.abs(ref).max()
