@@ -397,6 +397,44 @@ def actd_leg(ctd, n=1024, steps=2):
     return out
 
 
+def reduced_domain_leg(ctd, n=1024, steps=5, rd_tol=1e-2):
+    """Reduced integration domain of the 2D M_xy (Sec. 3.3, eq. MxyRD): the
+    2D workload on n x n nodes stepped with the full integral and with
+    rd_tol > 0 (FP64, adaptive).  Reports the M_xy build time of both, the
+    share of elements left out after each step, and the relative nodal l2
+    difference of the final fields (the approximation)."""
+    import torch
+    from workloads import make_instance
+    inst = make_instance("ac2d_n128", nodes=n)
+    out = {"nodes": [n, n], "steps": steps, "rd_tol": rd_tol}
+    fields = {}
+    for tol in (0.0, rd_tol):
+        with ctd.Solver(inst, precision="fp64", rd_tol=tol) as sv:
+            sv.profile(True, classes=["mxy_build"])
+            excl = []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                sv.step(1)
+                excl.append(sv.reduced_domain_excluded())
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            prof = sv.profile_read()
+            sv.profile(False)
+            fields[tol] = sv.reconstruct()
+        key = "full" if tol == 0.0 else "reduced"
+        mx = prof.get("mxy_build", {})
+        out[key] = {"ms_per_step": 1e3 * el / steps, "mxy_build_ms_total": mx.get("ms", 0.0),
+                    "mxy_build_launches": mx.get("launches", 0),
+                    "excluded_share": [c / float((n - 1) ** 2) for c in excl]}
+    out["rel_l2_reduced_vs_full"] = rel_l2(fields[rd_tol], fields[0.0])
+    log(f"  [reduced domain] {n}^2, rd_tol {rd_tol:g}: M_xy build {out['full']['mxy_build_ms_total']:.2f} ms "
+        f"full vs {out['reduced']['mxy_build_ms_total']:.2f} ms reduced over {steps} steps; excluded "
+        f"{[round(x, 3) for x in out['reduced']['excluded_share']]}; field difference "
+        f"{out['rel_l2_reduced_vs_full']:.2e}")
+    return out
+
+
 def init_leg(ctd, inst, warmup, steps, init):
     """The same workload and protocol as the headline with another initial
     guess of a mode ("hash": the counter-based random vector; "warm": mode m
@@ -571,7 +609,7 @@ def main():
                     help="initial guess of a mode: mode m of u^k (warm) or the counter-based vector")
     ap.add_argument("--no-alt-init", action="store_true", help="skip the leg with the other initial guess")
     ap.add_argument("--only", choices=["actd", "batched", "served", "ps", "ac2d", "ac3d_n256",
-                                       "served_load"],
+                                       "served_load", "reduced"],
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--requests", type=int, default=64,
                     help="requests of the served workload for --only served_load")
@@ -612,6 +650,7 @@ def main():
                 "served": lambda c: served_leg(c, init=args.init),
                 "ps": lambda c: ps_sweep_leg(c, init=args.init),
                 "ac2d": lambda c: ac2d_leg(c), "ac3d_n256": lambda c: ac3d_n256_leg(c),
+                "reduced": lambda c: reduced_domain_leg(c),
                 "served_load": lambda c: served_load_leg(c, count=args.requests, init=args.init,
                                                           lockstep=not args.no_lockstep)}
         print(json.dumps({args.only: legs[args.only](ctd)}))
@@ -750,7 +789,8 @@ def main():
     actd = None if args.no_actd else actd_leg(ctd)
     workloads = None
     if not args.no_workloads:
-        workloads = {"ac2d_n128": ac2d_leg(ctd), "ac3d_n256": ac3d_n256_leg(ctd)}
+        workloads = {"ac2d_n128": ac2d_leg(ctd), "ac3d_n256": ac3d_n256_leg(ctd),
+                     "reduced_domain_2d_n1024": reduced_domain_leg(ctd)}
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, step0[0], step0[1])
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",

@@ -36,7 +36,7 @@
 extern "C" {
 #endif
 
-#define CTD_ABI_VERSION 3
+#define CTD_ABI_VERSION 4
 
 enum {
   CTD_OK = 0,
@@ -105,6 +105,12 @@ enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
  *   alpha >= max(w')/2 = 4 a0 on |u| <= 1 (Sec. 2.5,
  *   eq. AC-discrete-semi-stable-step); a smaller alpha is accepted and
  *   reported by ctd_step_info.stability_warning.
+ * rd_tol: reduced integration domain of the 2D M_xy (Sec. 3.3, eq. MxyRD):
+ *   an element whose Gauss-point values of w(u^k) = 4 a0 (u^3 - u) all
+ *   satisfy |w| <= rd_tol is left out of the integral (an approximation for
+ *   rd_tol > 0; 0 = the full integral).  Finite and >= 0; with dim 3 or
+ *   actd a positive value is CTD_EUNSUPPORTED (the 3D load is exact in
+ *   separated form; the full CFE step integrates the whole domain).
  */
 typedef void* (*ctd_dev_alloc_fn)(uint64_t bytes, void* hip_stream, void* ctx);
 typedef void (*ctd_dev_free_fn)(void* ptr, uint64_t bytes, void* hip_stream, void* ctx);
@@ -133,6 +139,7 @@ typedef struct ctd_problem {
   ctd_dev_alloc_fn dev_alloc;   /* optional device allocator (see above)  */
   ctd_dev_free_fn dev_free;
   void* alloc_ctx;
+  double rd_tol;            /* 2D reduced integration domain (see above); 0 */
 } ctd_problem;
 
 /* Per-step report of ctd_step. */
@@ -455,6 +462,11 @@ int ctd_tuning_set(int32_t nb, int32_t nq, int32_t nsplit_g, int32_t nsplit_h);
 int ctd_tuning_clear(void);
 /* The split counts a handle uses for its current M_k (3D; 0 otherwise). */
 int ctd_tuning_current(ctd_solver* s, int32_t* nsplit_g, int32_t* nsplit_h);
+
+/* Elements left out by the reduced domain (Sec. 3.3, eq. MxyRD) of the 2D
+ * M_xy the next step uses (built from u^k at ctd_init and at the end of each
+ * step); 0 with rd_tol = 0 or in 3D.  Waits for the handle's stream. */
+int ctd_reduced_domain_excluded(ctd_solver* s, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,10 @@ struct DevInst {
   int fparts;
   const double* R3;
   double c, lam, omega, a0, kappa;
+  // 2D reduced integration domain (eq. MxyRD): elements with max |w| <=
+  // rd_tol are left out of M_xy; rd_count counts them (rd_tol > 0)
+  double rd_tol;
+  unsigned long long* rd_count;
   double fp_tol, enrich_tol;
   int max_modes;
   uint64_t seed;

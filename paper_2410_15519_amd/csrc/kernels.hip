@@ -2359,7 +2359,8 @@ hipError_t launch_cubic_h(const DevInst& I, int d, hipStream_t st) {
 // tensor Gauss grid: U = Xh_0 Xh_1^T and G = omega (U^3 - U) W_0 W_1 by the
 // FP64 MFMA product (a strip of whole elements of axis 0 at a time, so the
 // Gauss-grid buffer stays bounded), T1 = Phi_0^T G accumulated per strip
-// (gathered per node, elements in increasing order), M_xy = T1 Phi_1.
+// (gathered per node, elements in increasing order), M_xy = T1 Phi_1.  With
+// rd_tol > 0 each strip first drops the elements outside the reduced domain.
 __global__ void k_mxy_t1_strip(DevInst I, int r0, int r1, int i_lo, int i_hi) {
   const DevAxis& X = I.ax[0];
   const int nqy = I.ax[1].nq;
@@ -2387,6 +2388,39 @@ __global__ void k_mxy_t1_strip(DevInst I, int r0, int r1, int i_lo, int i_hi) {
   }
   I.T1[(size_t)i * nqy + qy] += acc;
 }
+
+// Reduced integration domain (Sec. 3.3, eq. MxyRD) on a strip of the Gauss
+// grid: an element whose Gauss-point values of w(u^k) = 4 a0 (u^3 - u) all
+// satisfy |w| <= rd_tol leaves M_xy.  The strip holds G = omega (u^3 - u)
+// W_0 W_1 with omega = 4 a0 L, so the test reads 4 a0 |G| <= rd_tol omega
+// W_0 W_1 (no division).  One thread per element; the values of a dropped
+// element are zeroed and the dropped elements counted.
+__global__ void k_mxy_mask(DevInst I, int r0, int r1) {
+  const DevAxis& X = I.ax[0];
+  const DevAxis& Y = I.ax[1];
+  const int ng0 = X.ng, ng1 = Y.ng, nq1 = Y.nq;
+  const int ne1 = nq1 / ng1, nes = (r1 - r0) / ng0;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool drop = false;
+  if (idx < (size_t)nes * ne1) {
+    const int ex = (int)(idx / ne1), ey = (int)(idx % ne1);
+    const double lhs = 4.0 * I.a0, rhs = I.rd_tol * I.omega;
+    double* G = I.Gq + (size_t)ex * ng0 * nq1 + (size_t)ey * ng1;
+    drop = true;
+    for (int gx = 0; gx < ng0 && drop; ++gx) {
+      const double wx = rhs * X.w[r0 + ex * ng0 + gx];
+      for (int gy = 0; gy < ng1; ++gy)
+        if (lhs * fabs(G[(size_t)gx * nq1 + gy]) > wx * Y.w[ey * ng1 + gy]) { drop = false; break; }
+    }
+    if (drop)
+      for (int gx = 0; gx < ng0; ++gx)
+        for (int gy = 0; gy < ng1; ++gy) G[(size_t)gx * nq1 + gy] = 0.0;
+  }
+  const unsigned long long m = __ballot(drop);
+  if ((threadIdx.x & 63) == 0 && m != 0) atomicAdd(I.rd_count, (unsigned long long)__popcll(m));
+}
+
+__global__ void k_mxy_count_reset(DevInst I) { *I.rd_count = 0; }
 
 template <class T>
 __global__ void k_mxy_t2(DevInst I) {
@@ -2421,6 +2455,11 @@ hipError_t launch_mxy_build(const DevInst& I, hipStream_t st) {
   const int nq0 = X.nq, nq1 = I.ax[1].nq;
   hipError_t e = launch_fill(I.T1, X.n * nq1, 0.0, st);
   if (e != hipSuccess) return e;
+  const bool reduced = I.rd_tol > 0.0;
+  if (reduced) {
+    k_mxy_count_reset<<<1, 1, 0, st>>>(I);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   for (int r0 = 0; r0 < nq0; r0 += I.gq_rows) {
     const int r1 = r0 + I.gq_rows < nq0 ? r0 + I.gq_rows : nq0;
     GemmArgs g;
@@ -2431,6 +2470,11 @@ hipError_t launch_mxy_build(const DevInst& I, hipStream_t st) {
     g.alpha = I.omega; g.w0 = X.w + r0; g.w1 = I.ax[1].w;
     e = launch_gemm64(g, st);
     if (e != hipSuccess) return e;
+    if (reduced) {
+      const size_t ne = (size_t)((r1 - r0) / X.ng) * (nq1 / I.ax[1].ng);
+      k_mxy_mask<<<(int)((ne + 255) / 256), 256, 0, st>>>(I, r0, r1);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     // nodes whose support meets elements [r0 / ng, r1 / ng)
     int i_lo = r0 / X.ng - X.SW, i_hi = r1 / X.ng + X.SW;
     i_lo = i_lo < 0 ? 0 : i_lo;

@@ -313,6 +313,11 @@ int validate(const ctd_problem* p, std::string& err) {
       }
     }
   }
+  if (!(p->rd_tol >= 0.0) || !std::isfinite(p->rd_tol)) { err = "rd_tol must be finite and >= 0"; return CTD_EINVAL; }
+  if (p->rd_tol > 0.0 && (p->dim != 2 || p->actd)) {
+    err = "the reduced integration domain (rd_tol > 0) is defined for the 2D M_xy without actd";
+    return CTD_EUNSUPPORTED;
+  }
   if (p->patch_s < 1 || p->patch_s > 3) { err = "patch_s must be 1, 2 or 3"; return CTD_EINVAL; }
   if (p->poly_p < 0 || p->poly_p > p->patch_s) { err = "need 0 <= poly_p <= patch_s"; return CTD_EINVAL; }
   for (int d = 0; d < p->dim; ++d) {
@@ -573,6 +578,7 @@ int alloc_instance(ctd_solver* s, int m0) {
   I.Mcap = s->Mcap;
   I.mixed = mixed;
   I.c = s->c; I.lam = s->lam; I.omega = s->omega; I.a0 = s->a0; I.kappa = s->kappa;
+  I.rd_tol = s->P.rd_tol;
   I.fp_tol = s->P.fp_tol;
   I.enrich_tol = s->P.enrich_tol;
   I.max_modes = s->P.max_modes;
@@ -685,6 +691,7 @@ int alloc_instance(ctd_solver* s, int m0) {
     }
     AL(I.Mxy, Tsz * n0 * n1);
     AL(I.MxyT, Tsz * n0 * n1);
+    AL(I.rd_count, sizeof(unsigned long long));
     if (s->actd) {
       AL(s->fsQ, sizeof(double) * n0 * n1);
       AL(s->fsT, sizeof(double) * n0 * n1);
@@ -2163,6 +2170,17 @@ extern "C" int ctd_tuning_current(ctd_solver* s, int32_t* nsplit_g, int32_t* nsp
   if (!s || !nsplit_g || !nsplit_h) return CTD_EINVAL;
   *nsplit_g = s->dim == 3 ? s->I.nsplit_g : 0;
   *nsplit_h = s->dim == 3 ? s->I.nsplit_h : 0;
+  return CTD_OK;
+}
+
+extern "C" int ctd_reduced_domain_excluded(ctd_solver* s, int64_t* count) {
+  if (!s || !count) return CTD_EINVAL;
+  *count = 0;
+  if (s->dim != 2 || !(s->P.rd_tol > 0.0)) return CTD_OK;
+  unsigned long long c = 0;
+  HIPCHK(s, hipMemcpyAsync(&c, s->I.rd_count, sizeof(c), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  *count = (int64_t)c;
   return CTD_OK;
 }
 

@@ -50,6 +50,7 @@ class Problem(C.Structure):
         ("energy_each_step", C.c_int32), ("solve_method", C.c_int32),
         ("actd", C.c_int32), ("seed", C.c_uint64),
         ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p),
+        ("rd_tol", C.c_double),
     ]
 
 
@@ -145,6 +146,7 @@ def _load():
         "ctd_tuning_set_prec": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
         "ctd_tuning_clear": (C.c_int, []),
         "ctd_tuning_current": (C.c_int, [vp, P(C.c_int32), P(C.c_int32)]),
+        "ctd_reduced_domain_excluded": (C.c_int, [vp, P(C.c_int64)]),
         "ctd_profile_read": (C.c_int, [vp, C.c_int32, P(C.c_int64), P(C.c_double),
                                        P(C.c_double), P(C.c_double)]),
     }
@@ -365,6 +367,13 @@ class Solver:
         g, h = C.c_int32(), C.c_int32()
         self._check(LIB.ctd_tuning_current(self.h, C.byref(g), C.byref(h)))
         return g.value, h.value
+
+    def reduced_domain_excluded(self):
+        """Elements the reduced domain (rd_tol > 0, 2D) leaves out of the M_xy
+        of the next step (built from the current state)."""
+        c = C.c_int64()
+        self._check(LIB.ctd_reduced_domain_excluded(self.h, C.byref(c)))
+        return c.value
     def profile(self, on=True, classes=None):
         """Enable (and reset) or disable per-kernel HIP-event timing; classes:
         names from KERNELS to time (default all)."""

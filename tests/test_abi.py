@@ -35,12 +35,13 @@ def test_binding_struct_layout_and_validation():
     """ctd_problem_default and ctd_init's validation run without touching a GPU."""
     from paper_2410_15519_amd import ctd
     p = ctd.make_problem()
-    assert p.abi_version == 3 and p.dim == 2 and p.max_modes == 64 and p.actd == 0
+    assert p.abi_version == 4 and p.dim == 2 and p.max_modes == 64 and p.actd == 0
     assert p.init_mode == ctd.INIT["warm"]          # library default: warm guess
     raw = ctd.Problem()
     assert ctd.LIB.ctd_problem_default(ctypes.byref(raw)) == 0
     assert raw.init_mode == ctd.INIT["warm"] and not raw.dev_alloc and not raw.dev_free
-    assert ctypes.sizeof(ctd.Problem) == 240
+    assert ctypes.sizeof(ctd.Problem) == 248
+    assert raw.rd_tol == 0.0
     assert ctypes.sizeof(ctd.StepInfo) == 56
     # allocator hooks: both or neither
     half = ctd.make_problem(allocator="library")
@@ -65,6 +66,17 @@ def test_binding_struct_layout_and_validation():
     assert rc == -6 and not h.value and b"Gauss points" in ctd.LIB.ctd_last_error(None)
     bad = ctd.make_problem(actd=True, nodes=(4096, 64, 64))
     assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
+    # the reduced integration domain: finite, >= 0, and defined for the 2D M_xy
+    for tol in (-1e-3, float("nan"), float("inf")):
+        bad = ctd.make_problem(rd_tol=tol)
+        assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -1
+        assert b"rd_tol" in ctd.LIB.ctd_last_error(None)
+    for kw in (dict(dim=3), dict(actd=True)):
+        bad = ctd.make_problem(rd_tol=0.1, **kw)
+        assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
+        assert not h.value and b"reduced" in ctd.LIB.ctd_last_error(None)
+    count = ctypes.c_int64(7)
+    assert ctd.LIB.ctd_reduced_domain_excluded(None, ctypes.byref(count)) == -1
 
 
 def test_footprint_query_without_device():
