@@ -122,3 +122,26 @@ def test_zero_tolerance_is_the_full_integral(ctd):
         b.step(2)
         assert a.reduced_domain_excluded() == 0
         assert np.array_equal(a.reconstruct(), b.reconstruct())
+
+
+@pytest.mark.parametrize("executor", ["lockstep", "streams"])
+def test_reduced_batch_equals_standalone(ctd, executor):
+    """Batched instances with the reduced domain step exactly as standalone
+    ones (each instance builds its own masked M_xy)."""
+    from workloads import make_batch
+    insts = make_batch(seed=13, count=4, nodes_range=(24, 120), max_modes=10)
+    tol = 0.05
+    b = ctd.Batch(insts, precision="fp64", rd_tol=tol)
+    try:
+        b.set_mode(executor)
+        b.set_workers(3)
+        b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        with ctd.Solver(inst, precision="fp64", rd_tol=tol) as s:
+            s.step(2)
+            assert s.reduced_domain_excluded() > 0
+            amp, fac = s.modes()
+        assert np.array_equal(got[i][0], amp) and all(np.array_equal(x, y) for x, y in zip(got[i][1], fac))
