@@ -32,7 +32,11 @@ library, which shares no code with this module):
     the mode cap max_modes (the adaptive variant's M_c, capped rather than
     switched to a full solve); a mode with zero amplitude is dropped and ends
     the step;
-  * the mode count restarts from zero every time step.
+  * the mode count restarts from zero every time step;
+  * the alternatives to the full 2D M_xy integral (Sec. 3.3): the reduced
+    domain drops an element when |w| <= rd_tol at all its Gauss points; the
+    separated w is a greedy rank-one (PGD) decomposition with a fixed count
+    of alternating updates per term (pgd_separate).
 """
 from __future__ import annotations
 
@@ -104,6 +108,34 @@ def element_mask(prob, U):
     return np.repeat(np.repeat(keep, ng0, axis=0), ng1, axis=1)
 
 
+def pgd_separate(prob, Wg):
+    """Separated form of the Gauss-grid values Wg[q_x, q_y] of L w(u^k), the
+    decomposition before eq. MxySep (Sec. 3.3), read as the progressive
+    (greedy rank-one) decomposition of the HOPGD family: w_rank terms
+    a_q(x) b_q(y) are added one at a time, each from w_iters alternating
+    updates of its two factors, each update the least-squares factor against
+    the residual R = Wg - sum_{p<q} a_p b_p^T with the other factor fixed:
+        a <- R b / (b.b),   b <- R^T a / (a.a)
+    (R is applied as Wg b - A (B^T b), never formed).  b starts from the
+    counter-based vector keyed (seed, step 0, term q, key 7).  A zero
+    denominator gives a zero factor.  Returns A (n_qx x Q), B (n_qy x Q)."""
+    Q, K = prob.w_rank, prob.w_iters
+    n0, n1 = Wg.shape
+    A = np.zeros((n0, Q))
+    B = np.zeros((n1, Q))
+    for q in range(Q):
+        b = init_vector(prob.seed, 0, q, 7, n1)
+        a = np.zeros(n0)
+        for _ in range(K):
+            bb = b @ b
+            a = (Wg @ b - A[:, :q] @ (B[:, :q].T @ b)) / bb if bb != 0.0 else np.zeros(n0)
+            aa = a @ a
+            b = (Wg.T @ a - B[:, :q] @ (A[:, :q].T @ a)) / aa if aa != 0.0 else np.zeros(n1)
+        A[:, q] = a
+        B[:, q] = b
+    return A, B
+
+
 class FullGridNonlinear:
     """Full integration on the tensor Gauss grid (eq. KxxMxx, the M_xy entry).
 
@@ -123,12 +155,20 @@ class FullGridNonlinear:
             U = np.einsum("m,im,jm,km->ijk", state_k.sigma, *hats, optimize=True)
         G = prob.omega * (U ** 3 - U)
         self.excluded = 0
-        if getattr(prob, "rd_tol", 0.0) > 0.0:
-            if D != 2:
-                raise ValueError("the reduced domain is defined for the 2D M_xy")
+        self.wsep = None
+        rd, wr = getattr(prob, "rd_tol", 0.0) > 0.0, getattr(prob, "w_rank", 0) > 0
+        if (rd or wr) and D != 2:
+            raise ValueError("the reduced domain and the separated w are defined for the 2D M_xy")
+        if rd and wr:
+            raise ValueError("one alternative integration at a time")
+        if rd:
             mask = element_mask(prob, U)
             self.excluded = int(round((mask == 0).sum() / (ax[0].ng * ax[1].ng)))
             G = G * mask
+        if wr:
+            # the integral of the separated approximant on the same Gauss rule
+            self.wsep = pgd_separate(prob, G)
+            G = self.wsep[0] @ self.wsep[1].T
         for d in range(D):
             shp = [1] * D
             shp[d] = -1
@@ -212,6 +252,8 @@ class SeparatedNonlinear:
 
 
 def make_nonlinear(prob, state_k, kind="auto"):
+    if prob.dim == 2 and (getattr(prob, "rd_tol", 0.0) > 0.0 or getattr(prob, "w_rank", 0) > 0):
+        kind = "full"        # the alternatives change the integral of the full route
     if kind == "auto":
         nq = [ax.nq for ax in prob.axes]
         kind = "full" if np.prod(nq, dtype=float) <= 2.5e7 else "separated"

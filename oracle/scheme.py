@@ -41,6 +41,11 @@ class Problem:
     # Gauss-point values of w(u^k) all have |w| <= rd_tol is left out of the
     # M_xy integral; 0 leaves out only elements where w vanishes exactly
     rd_tol: float = 0.0
+    # separated integration of M_xy (Sec. 3.3, eq. MxySep), 2D: L w(u^k) on
+    # the Gauss grid replaced by w_rank terms of a greedy rank-one (PGD)
+    # decomposition, each from w_iters alternating updates; 0 = full integral
+    w_rank: int = 0
+    w_iters: int = 30
 
     @property
     def c(self):

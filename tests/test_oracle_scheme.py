@@ -459,3 +459,74 @@ def test_reduced_domain_against_element_loop():
                 ref += np.outer(P0[q0], P1[q1]) * (pr.L * wq * ax0.W[q0] * ax1.W[q1])
     assert dropped == red.excluded and 0 < dropped < wmax.size
     assert np.abs(red.Mxy - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# separated integration of the 2D M_xy (Sec. 3.3, eq. MxySep)
+# ---------------------------------------------------------------------------
+
+def test_separated_w_of_a_one_mode_state_is_exact():
+    """u^k = sigma x^ y^T gives L w = omega (sigma^3 x^3 (y^3)^T - sigma x y^T),
+    of rank two: two terms reproduce the full integral."""
+    inst = small_instance(2, (26, 22), m0=1, kmax=2)
+    st = state_from_instance(inst)
+    full = ctdmod.FullGridNonlinear(problem_from_instance(inst), st)
+    sep = ctdmod.FullGridNonlinear(problem_from_instance(inst, w_rank=2, w_iters=300), st)
+    assert np.abs(sep.Mxy - full.Mxy).max() < 1e-11 * np.abs(full.Mxy).max()
+    one = ctdmod.FullGridNonlinear(problem_from_instance(inst, w_rank=1, w_iters=300), st)
+    assert np.abs(one.Mxy - full.Mxy).max() > 1e-3 * np.abs(full.Mxy).max()
+
+
+def test_separated_w_equals_truncated_svd():
+    """With singular values apart, the greedy terms converge to the leading
+    singular triplets (Eckart-Young): the rank-Q approximant equals LAPACK's
+    truncated SVD of the Gauss-grid values of L w."""
+    inst = small_instance(2, (30, 25), m0=3, kmax=3)
+    st = state_from_instance(inst)
+    pr0 = problem_from_instance(inst)
+    Wg = pr0.omega * (_gauss_field(pr0, st) ** 3 - _gauss_field(pr0, st))
+    U_, S_, Vt = np.linalg.svd(Wg)
+    # the first Q whose next singular value is at most half of it
+    Q = next(q for q in range(1, 8) if S_[q] < 0.5 * S_[q - 1] and all(S_[p + 1] < 0.8 * S_[p] for p in range(q)))
+    pr = problem_from_instance(inst, w_rank=Q, w_iters=400)
+    A, B = ctdmod.pgd_separate(pr, Wg)
+    ref = (U_[:, :Q] * S_[:Q]) @ Vt[:Q]
+    assert np.linalg.norm(A @ B.T - ref) < 1e-9 * np.linalg.norm(ref)
+    # and the residual is the SVD tail (Frobenius)
+    tail = np.sqrt((S_[Q:] ** 2).sum())
+    assert np.linalg.norm(Wg - A @ B.T) == pytest.approx(tail, rel=1e-8)
+
+
+def test_separated_integral_is_the_sum_of_1d_integrals():
+    """eq. MxySep: M_xy = sum_q (int N~_x^T w_x^q)(int N~_y w_y^q), each a 1D
+    Gauss sum, against the oracle's 2D Gauss sum of the approximant."""
+    inst = small_instance(2, (18, 21), m0=3, kmax=3)
+    pr = problem_from_instance(inst, w_rank=3, w_iters=20)
+    sep = ctdmod.FullGridNonlinear(pr, state_from_instance(inst))
+    A, B = sep.wsep
+    ax0, ax1 = pr.axes
+    ref = np.zeros((inst.nodes[0], inst.nodes[1]))
+    for q in range(A.shape[1]):
+        ix = np.array([sum(ax0.Phi[g, i] * ax0.W[g] * A[g, q] for g in range(ax0.nq)) for i in range(inst.nodes[0])])
+        iy = np.array([sum(ax1.Phi[g, j] * ax1.W[g] * B[g, q] for g in range(ax1.nq)) for j in range(inst.nodes[1])])
+        ref += np.outer(ix, iy)
+    assert np.abs(sep.Mxy - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_separated_w_of_the_zero_field():
+    """w(0) = 0: every factor is zero (zero denominators), M_xy = 0."""
+    inst = small_instance(2, 16, m0=2, kmax=2)
+    st = state_from_instance(inst)
+    st = State(np.zeros_like(st.sigma), st.factors)
+    sep = ctdmod.FullGridNonlinear(problem_from_instance(inst, w_rank=2, w_iters=5), st)
+    assert not np.any(sep.wsep[0]) and not np.any(sep.wsep[1]) and not np.any(sep.Mxy)
+
+
+def test_alternative_integrals_need_2d_and_one_at_a_time():
+    inst = small_instance(2, 16, m0=2, kmax=2)
+    st = state_from_instance(inst)
+    with pytest.raises(ValueError):
+        ctdmod.FullGridNonlinear(problem_from_instance(inst, w_rank=2, rd_tol=0.1), st)
+    inst3 = small_instance(3, 9, m0=2, kmax=2)
+    with pytest.raises(ValueError):
+        ctdmod.FullGridNonlinear(problem_from_instance(inst3, w_rank=2), state_from_instance(inst3))
