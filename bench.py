@@ -397,41 +397,54 @@ def actd_leg(ctd, n=1024, steps=2):
     return out
 
 
-def reduced_domain_leg(ctd, n=1024, steps=5, rd_tol=1e-2):
-    """Reduced integration domain of the 2D M_xy (Sec. 3.3, eq. MxyRD): the
-    2D workload on n x n nodes stepped with the full integral and with
-    rd_tol > 0 (FP64, adaptive).  Reports the M_xy build time of both, the
-    share of elements left out after each step, and the relative nodal l2
-    difference of the final fields (the approximation)."""
+def mxy_alternatives_leg(ctd, n=1024, steps=5, rd_tol=1e-2, w_rank=8, w_iters=30):
+    """The alternatives to the full 2D M_xy integral (Sec. 3.3): the 2D
+    workload on n x n nodes stepped (FP64, adaptive) with the full integral,
+    with the reduced domain (eq. MxyRD, rd_tol) and with the separated w
+    (eq. MxySep, w_rank terms of w_iters updates).  Reports each route's M_xy
+    build time per step, the share of elements the reduced domain leaves
+    out, the separated route's HBM rate over its row-by-row products (each
+    update reads W or W^T once: 2 w_rank w_iters n_q^2 8 bytes per build), and
+    the relative nodal l2 difference of each final field from the full one."""
     import torch
     from workloads import make_instance
     inst = make_instance("ac2d_n128", nodes=n)
-    out = {"nodes": [n, n], "steps": steps, "rd_tol": rd_tol}
+    nq = 5 * (n - 1)
+    routes = {"full": {}, "reduced": {"rd_tol": rd_tol}, "separated": {"w_rank": w_rank, "w_iters": w_iters}}
+    out = {"nodes": [n, n], "steps": steps}
     fields = {}
-    for tol in (0.0, rd_tol):
-        with ctd.Solver(inst, precision="fp64", rd_tol=tol) as sv:
+    for name, kw in routes.items():
+        with ctd.Solver(inst, precision="fp64", **kw) as sv:
             sv.profile(True, classes=["mxy_build"])
-            excl = []
+            excl, infos = [], []
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for _ in range(steps):
-                sv.step(1)
+                infos += sv.step(1)
                 excl.append(sv.reduced_domain_excluded())
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             prof = sv.profile_read()
             sv.profile(False)
-            fields[tol] = sv.reconstruct()
-        key = "full" if tol == 0.0 else "reduced"
+            fields[name] = sv.reconstruct()
         mx = prof.get("mxy_build", {})
-        out[key] = {"ms_per_step": 1e3 * el / steps, "mxy_build_ms_total": mx.get("ms", 0.0),
-                    "mxy_build_launches": mx.get("launches", 0),
-                    "excluded_share": [c / float((n - 1) ** 2) for c in excl]}
-    out["rel_l2_reduced_vs_full"] = rel_l2(fields[rd_tol], fields[0.0])
-    log(f"  [reduced domain] {n}^2, rd_tol {rd_tol:g}: M_xy build {out['full']['mxy_build_ms_total']:.2f} ms "
-        f"full vs {out['reduced']['mxy_build_ms_total']:.2f} ms reduced over {steps} steps; excluded "
-        f"{[round(x, 3) for x in out['reduced']['excluded_share']]}; field difference "
-        f"{out['rel_l2_reduced_vs_full']:.2e}")
+        per = mx.get("ms", 0.0) / max(1, mx.get("launches", 1))
+        r = dict(kw, ms_per_step=1e3 * el / steps, mxy_build_ms=per,
+                 modes_per_step=[i["modes"] for i in infos], sweeps_per_step=[i["sweeps"] for i in infos])
+        if name == "reduced":
+            r["excluded_share"] = [c / float((n - 1) ** 2) for c in excl]
+        if name == "separated":
+            r["update_GB_per_s"] = 2 * w_rank * w_iters * nq * nq * 8 / (per * 1e-3) / 1e9
+        if name != "full":
+            r["rel_l2_vs_full"] = rel_l2(fields[name], fields["full"])
+        out[name] = r
+    log(f"  [M_xy alternatives] {n}^2: ms/step " + ", ".join(f"{k} {out[k]['ms_per_step']:.1f} "
+        f"(modes {out[k]['modes_per_step']}, sweeps {out[k]['sweeps_per_step']})" for k in routes))
+    log(f"  [M_xy alternatives] {n}^2: build {out['full']['mxy_build_ms']:.2f} ms full, "
+        f"{out['reduced']['mxy_build_ms']:.2f} ms reduced (rd_tol {rd_tol:g}, excluded "
+        f"{out['reduced']['excluded_share'][-1]:.3f}, field difference {out['reduced']['rel_l2_vs_full']:.1e}), "
+        f"{out['separated']['mxy_build_ms']:.2f} ms separated (rank {w_rank}, {w_iters} updates, "
+        f"{out['separated']['update_GB_per_s']:.0f} GB/s, field difference {out['separated']['rel_l2_vs_full']:.1e})")
     return out
 
 
@@ -609,7 +622,7 @@ def main():
                     help="initial guess of a mode: mode m of u^k (warm) or the counter-based vector")
     ap.add_argument("--no-alt-init", action="store_true", help="skip the leg with the other initial guess")
     ap.add_argument("--only", choices=["actd", "batched", "served", "ps", "ac2d", "ac3d_n256",
-                                       "served_load", "reduced"],
+                                       "served_load", "mxy_alternatives"],
                     help="run only this leg and print its JSON (profiling aid; not the benchmark line)")
     ap.add_argument("--requests", type=int, default=64,
                     help="requests of the served workload for --only served_load")
@@ -650,7 +663,7 @@ def main():
                 "served": lambda c: served_leg(c, init=args.init),
                 "ps": lambda c: ps_sweep_leg(c, init=args.init),
                 "ac2d": lambda c: ac2d_leg(c), "ac3d_n256": lambda c: ac3d_n256_leg(c),
-                "reduced": lambda c: reduced_domain_leg(c),
+                "mxy_alternatives": lambda c: mxy_alternatives_leg(c),
                 "served_load": lambda c: served_load_leg(c, count=args.requests, init=args.init,
                                                           lockstep=not args.no_lockstep)}
         print(json.dumps({args.only: legs[args.only](ctd)}))
@@ -790,7 +803,7 @@ def main():
     workloads = None
     if not args.no_workloads:
         workloads = {"ac2d_n128": ac2d_leg(ctd), "ac3d_n256": ac3d_n256_leg(ctd),
-                     "reduced_domain_2d_n1024": reduced_domain_leg(ctd)}
+                     "mxy_alternatives_2d_n1024": mxy_alternatives_leg(ctd)}
     cpu = None if args.no_cpu_baseline else cpu_baseline(inst, step0[0], step0[1])
     out = {
         "metric": "CTD steps/s at 3D 1024^3 (mixed vs FP64, rel L2<=1e-6); served p50/p99 latency",

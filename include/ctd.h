@@ -111,6 +111,16 @@ enum { CTD_SOLVE_AUTO = 0, CTD_SOLVE_BCR = 1, CTD_SOLVE_FD = 2 };
  *   rd_tol > 0; 0 = the full integral).  Finite and >= 0; with dim 3 or
  *   actd a positive value is CTD_EUNSUPPORTED (the 3D load is exact in
  *   separated form; the full CFE step integrates the whole domain).
+ * w_rank, w_iters: separated integration of the 2D M_xy (Sec. 3.3, eq.
+ *   MxySep): the Gauss-grid values of L w(u^k) are replaced by w_rank
+ *   rank-one terms a_q(x) b_q(y) of a greedy (PGD) decomposition, each from
+ *   w_iters alternating least-squares updates against the residual (b
+ *   starting from the counter-based vector of term q), and M_xy becomes the
+ *   sum over the terms of products of 1D integrals.  An approximation for
+ *   every w_rank below the rank of w; 0 = the full integral.  w_rank in
+ *   [0, 256], w_iters in [0, 100000]; w_rank > 0 needs dim 2, no actd and
+ *   rd_tol = 0 (CTD_EUNSUPPORTED otherwise).  Holds W and W^T on the Gauss
+ *   grid: 16 nq0 nq1 bytes more device memory.
  */
 typedef void* (*ctd_dev_alloc_fn)(uint64_t bytes, void* hip_stream, void* ctx);
 typedef void (*ctd_dev_free_fn)(void* ptr, uint64_t bytes, void* hip_stream, void* ctx);
@@ -140,6 +150,8 @@ typedef struct ctd_problem {
   ctd_dev_free_fn dev_free;
   void* alloc_ctx;
   double rd_tol;            /* 2D reduced integration domain (see above); 0 */
+  int32_t w_rank;           /* 2D separated w: terms (see above); 0 = off  */
+  int32_t w_iters;          /* alternating updates per term; 0 = 30        */
 } ctd_problem;
 
 /* Per-step report of ctd_step. */

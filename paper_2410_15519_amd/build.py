@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libctd.so")
-SOURCES = ["cfe1d.cpp", "fdiag.cpp", "kernels.hip", "actd.hip", "solver.hip", "batch.hip", "serve.hip", "noalloc.hip"]
+SOURCES = ["cfe1d.cpp", "fdiag.cpp", "kernels.hip", "actd.hip", "solver.hip", "batch.hip", "serve.hip", "noalloc.hip", "wsep.hip"]
 ARCH = os.environ.get("CTD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

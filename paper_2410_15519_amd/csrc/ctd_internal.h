@@ -281,6 +281,18 @@ hipError_t launch_field_to_f32(const double* X, float* Y, int64_t total, hipStre
 constexpr int kLoadSub = 4;      // 3D cubic load: RHS chunks of 16-row sub-blocks of a 64-row block
 constexpr int kFieldParts = 8;   // load chunks of a directional solve from a 3D field state
 hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
+// Separated integration of the 2D M_xy (wsep.hip, Sec. 3.3 eq. MxySep):
+// W = L w(u^k) on the Gauss grid (nq0 x nq1, row-major) and W^T, the Q
+// greedy rank-one terms (A: nq0 x Q, B: nq1 x Q, column-major), their 1D
+// integrals (Pa: n0 x Q, Pb: n1 x Q), Q + 1 dot products, a unit vector of
+// max(nq0, nq1) weights.
+constexpr int kWsepMaxRank = 256;
+struct WsepBufs {
+  int rank = 0, iters = 0;
+  double *W = nullptr, *Wt = nullptr, *A = nullptr, *B = nullptr;
+  double *Pa = nullptr, *Pb = nullptr, *dots = nullptr, *ones = nullptr;
+};
+hipError_t launch_mxy_separated(const DevInst& I, const WsepBufs& B, hipStream_t st);
 hipError_t configure_kernels();
 int max_lds_bytes();
 int num_cus();

@@ -168,6 +168,7 @@ struct ctd_solver {
   double* G3a = nullptr;
   double* G3b = nullptr;
   double energy_field = std::numeric_limits<double>::quiet_NaN();
+  WsepBufs wsep;                   // separated 2D M_xy (w_rank > 0)
   double* fsQ = nullptr;           // n0 x n1 temporaries of the full solve
   double* fsT = nullptr;
   int nsplit_g_cap = 0;
@@ -316,6 +317,14 @@ int validate(const ctd_problem* p, std::string& err) {
   if (!(p->rd_tol >= 0.0) || !std::isfinite(p->rd_tol)) { err = "rd_tol must be finite and >= 0"; return CTD_EINVAL; }
   if (p->rd_tol > 0.0 && (p->dim != 2 || p->actd)) {
     err = "the reduced integration domain (rd_tol > 0) is defined for the 2D M_xy without actd";
+    return CTD_EUNSUPPORTED;
+  }
+  if (p->w_rank < 0 || p->w_rank > kWsepMaxRank || p->w_iters < 0 || p->w_iters > 100000) {
+    err = "need 0 <= w_rank <= 256 and 0 <= w_iters <= 100000";
+    return CTD_EINVAL;
+  }
+  if (p->w_rank > 0 && (p->dim != 2 || p->actd || p->rd_tol > 0.0)) {
+    err = "the separated w (w_rank > 0) is defined for the 2D M_xy without actd or rd_tol";
     return CTD_EUNSUPPORTED;
   }
   if (p->patch_s < 1 || p->patch_s > 3) { err = "patch_s must be 1, 2 or 3"; return CTD_EINVAL; }
@@ -532,6 +541,7 @@ int setup_host(ctd_solver* s, const ctd_problem* p, void* hip_stream, std::strin
   if (s->P.gauss_points == 0) s->P.gauss_points = 5;
   if (s->P.fp_tol == 0.0) s->P.fp_tol = 1e-2;
   if (s->P.fp_max_iter == 0) s->P.fp_max_iter = 20;
+  if (s->P.w_iters == 0) s->P.w_iters = 30;
   s->dim = p->dim;
   if (std::isfinite(p->L)) {
     s->L = p->L; s->kappa = p->kappa; s->a0 = p->a0; s->alpha = p->alpha;
@@ -692,6 +702,20 @@ int alloc_instance(ctd_solver* s, int m0) {
     AL(I.Mxy, Tsz * n0 * n1);
     AL(I.MxyT, Tsz * n0 * n1);
     AL(I.rd_count, sizeof(unsigned long long));
+    if (s->P.w_rank > 0) {
+      WsepBufs& W = s->wsep;
+      const size_t nq0 = s->ax[0].nq, Q = s->P.w_rank;
+      W.rank = (int)Q;
+      W.iters = s->P.w_iters;
+      AL(W.W, sizeof(double) * nq0 * nq1);
+      AL(W.Wt, sizeof(double) * nq0 * nq1);
+      AL(W.A, sizeof(double) * nq0 * Q);
+      AL(W.B, sizeof(double) * nq1 * Q);
+      AL(W.Pa, sizeof(double) * n0 * Q);
+      AL(W.Pb, sizeof(double) * n1 * Q);
+      AL(W.dots, sizeof(double) * (Q + 1));
+      AL(W.ones, sizeof(double) * std::max(nq0, nq1));
+    }
     if (s->actd) {
       AL(s->fsQ, sizeof(double) * n0 * n1);
       AL(s->fsT, sizeof(double) * n0 * n1);
@@ -791,7 +815,10 @@ int precompute(ctd_solver* s) {
   }
   if (s->dim == 2) {
     Work w = w_mxy(s);
-    LAUNCH(s, CTD_K_MXY, w.flops, w.bytes, launch_mxy_build(s->I, s->stream));
+    if (s->P.w_rank > 0)
+      LAUNCH(s, CTD_K_MXY, w.flops, w.bytes, launch_mxy_separated(s->I, s->wsep, s->stream));
+    else
+      LAUNCH(s, CTD_K_MXY, w.flops, w.bytes, launch_mxy_build(s->I, s->stream));
   }
   return CTD_OK;
 }
@@ -1837,6 +1864,7 @@ int ctd_problem_default(ctd_problem* p) {
   p->fp_max_iter = 20; p->fp_tol = 1e-2; p->enrich_tol = 1e-8; p->max_modes = 64;
   p->precision = CTD_PREC_FP64; p->schedule = CTD_SCHED_ADAPTIVE; p->init_mode = CTD_INIT_WARM;
   p->energy_each_step = 0; p->seed = 0;
+  p->w_rank = 0; p->w_iters = 30;
   return CTD_OK;
 }
 

@@ -50,7 +50,7 @@ class Problem(C.Structure):
         ("energy_each_step", C.c_int32), ("solve_method", C.c_int32),
         ("actd", C.c_int32), ("seed", C.c_uint64),
         ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("alloc_ctx", C.c_void_p),
-        ("rd_tol", C.c_double),
+        ("rd_tol", C.c_double), ("w_rank", C.c_int32), ("w_iters", C.c_int32),
     ]
 
 

@@ -40,8 +40,8 @@ def test_binding_struct_layout_and_validation():
     raw = ctd.Problem()
     assert ctd.LIB.ctd_problem_default(ctypes.byref(raw)) == 0
     assert raw.init_mode == ctd.INIT["warm"] and not raw.dev_alloc and not raw.dev_free
-    assert ctypes.sizeof(ctd.Problem) == 248
-    assert raw.rd_tol == 0.0
+    assert ctypes.sizeof(ctd.Problem) == 256
+    assert raw.rd_tol == 0.0 and raw.w_rank == 0 and raw.w_iters == 30
     assert ctypes.sizeof(ctd.StepInfo) == 56
     # allocator hooks: both or neither
     half = ctd.make_problem(allocator="library")
@@ -75,6 +75,15 @@ def test_binding_struct_layout_and_validation():
         bad = ctd.make_problem(rd_tol=0.1, **kw)
         assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
         assert not h.value and b"reduced" in ctd.LIB.ctd_last_error(None)
+    # the separated w: bounded rank and update count, 2D only, one alternative
+    for kw in (dict(w_rank=-1), dict(w_rank=257), dict(w_rank=4, w_iters=-1)):
+        bad = ctd.make_problem(**kw)
+        assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -1
+        assert b"w_rank" in ctd.LIB.ctd_last_error(None)
+    for kw in (dict(dim=3), dict(actd=True), dict(rd_tol=0.1)):
+        bad = ctd.make_problem(w_rank=4, **kw)
+        assert ctd.LIB.ctd_init(ctypes.byref(bad), 1, ptrs, None, None, ctypes.byref(h)) == -6
+        assert not h.value and b"separated" in ctd.LIB.ctd_last_error(None)
     count = ctypes.c_int64(7)
     assert ctd.LIB.ctd_reduced_domain_excluded(None, ctypes.byref(count)) == -1
 

@@ -1,0 +1,99 @@
+"""GPU parity of the separated integration of the 2D M_xy (Sec. 3.3, eq.
+MxySep): L w(u^k) on the Gauss grid replaced by w_rank greedy rank-one
+terms, each from w_iters alternating least-squares updates, and M_xy formed
+from products of 1D integrals.  Both sides run the same iteration from the
+same counter-based start (a contraction: rounding differences do not grow),
+so the results are compared at the tolerances of the full integral: 1e-12
+(FP64 load), 1e-10 / 1e-6 (FP64 / mixed steps), 2e-6 (mixed load).
+"""
+import numpy as np
+import pytest
+
+from oracle.ctd import FullGridNonlinear, ctd_step, full_field, state_from_instance
+from oracle.scheme import problem_from_instance
+from workloads import make_batch, small_instance
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ctd():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_15519_amd import ctd as mod
+    return mod
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("n,rank,iters,prec", [((45, 38), 3, 40, "fp64"), ((45, 38), 3, 40, "mixed"),
+                                               ((300, 260), 5, 25, "fp64"), ((70, 66), 12, 8, "fp64")])
+def test_separated_load_matches_oracle(ctd, n, rank, iters, prec):
+    """The 2D load F_d = M_xy u_e with the separated M_xy."""
+    inst = small_instance(dim=2, n=n, m0=4, kmax=4)
+    pr = problem_from_instance(inst, w_rank=rank, w_iters=iters)
+    F = FullGridNonlinear(pr, state_from_instance(inst))
+    rng = np.random.default_rng(9)
+    u = [rng.uniform(-1, 1, inst.nodes[d]) for d in range(2)]
+    print(f"separated load n={n} rank={rank} iters={iters} prec={prec}", flush=True)
+    with ctd.Solver(inst, precision=prec, w_rank=rank, w_iters=iters) as s:
+        for d in range(2):
+            err = rel(s.nonlinear_load(d, u), F(d, u))
+            print(f"  load d={d}: {err:.2e}", flush=True)
+            assert err < (1e-12 if prec == "fp64" else 2e-6)
+
+
+def test_two_terms_of_a_one_mode_state_are_the_full_integral(ctd):
+    """L w of a one-mode state has rank two: the separated load with two
+    terms equals the library's full-integral load."""
+    inst = small_instance(dim=2, n=(40, 34), m0=1, kmax=2)
+    rng = np.random.default_rng(2)
+    u = [rng.uniform(-1, 1, inst.nodes[d]) for d in range(2)]
+    with ctd.Solver(inst, w_rank=2, w_iters=200) as s, ctd.Solver(inst) as f:
+        for d in range(2):
+            assert rel(s.nonlinear_load(d, u), f.nonlinear_load(d, u)) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_separated_step_replay_parity(ctd, prec):
+    """Time steps with the separated M_xy against the oracle's, the oracle's
+    decisions replayed."""
+    inst = small_instance(dim=2, n=37, m0=3, kmax=4, eps=0.05, dt=1e-3, max_modes=24)
+    pr = problem_from_instance(inst, w_rank=4, w_iters=30)
+    st = state_from_instance(inst)
+    fields, logs = [], []
+    for k in range(3):
+        st, lg = ctd_step(pr, st, k)
+        fields.append(full_field(st))
+        logs.append(lg)
+    print(f"separated replay prec={prec} modes={[len(l.iters) for l in logs]}", flush=True)
+    with ctd.Solver(inst, precision=prec, schedule="replay", w_rank=4, w_iters=30) as s:
+        s.set_decisions([lg.iters for lg in logs])
+        for k in range(3):
+            info = s.step(1)[0]
+            assert info["modes"] == len(logs[k].iters)
+            err = rel(s.reconstruct(), fields[k])
+            print(f"  step {k}: rel l2 = {err:.3e}", flush=True)
+            assert err < TOL[prec]
+
+
+def test_separated_batch_equals_standalone(ctd):
+    """Batched instances with the separated M_xy step exactly as standalone."""
+    insts = make_batch(seed=17, count=3, nodes_range=(24, 90), max_modes=8)
+    b = ctd.Batch(insts, precision="fp64", w_rank=3, w_iters=10)
+    try:
+        b.set_mode("lockstep")
+        b.step(2)
+        got = [b.modes(i) for i in range(len(insts))]
+    finally:
+        b.close()
+    for i, inst in enumerate(insts):
+        with ctd.Solver(inst, precision="fp64", w_rank=3, w_iters=10) as s:
+            s.step(2)
+            amp, fac = s.modes()
+        assert np.array_equal(got[i][0], amp) and all(np.array_equal(x, y) for x, y in zip(got[i][1], fac))
