@@ -103,6 +103,10 @@ def test_footprint_query_without_device():
     assert f(small) % 256 == 0
     # actd keeps one mode per node of axis 1 for field states
     assert f(small, actd=True) > f(small)
+    # the separated w holds W and W^T on the Gauss grid (5 points per element)
+    nq = 5 * 23
+    assert f(small, w_rank=4) - f(small) >= 16 * nq * nq
+    assert f(small, rd_tol=0.1) == f(small)
     # 3D actd: the field, its right-hand-side tensor and two Gauss-grid buffers
     nq = 5 * 20
     assert f(three, actd=True) - f(three) >= 8 * (2 * 21 ** 3 + 2 * nq ** 3)
