@@ -49,29 +49,57 @@ __global__ void k_ws_start(double* b, int n, uint64_t seed, int q) {
   b[i] = 2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0;
 }
 
-// out[p] = V[:, p] . x for p < q, out[q] = x . x; one wave per product
-// (lane-strided sums, then a fixed shuffle tree).  V: n x Q column-major.
+// out[p] = V[:, p] . x for p < q, out[q] = x . x; one workgroup per product
+// (grid q + 1), four 256-wide segments in flight per pass, sums added in
+// fixed order (segments, lanes, waves).  V: n x Q column-major.
 __global__ __launch_bounds__(256) void k_ws_dots(const double* V, const double* x, int n, int q,
                                                  double* out) {
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
-  if (p > q) return;
+  __shared__ double red[4];
+  const int p = blockIdx.x, t = threadIdx.x;
   const double* col = p < q ? V + (size_t)p * n : x;
-  double s = 0.0;
-  for (int i = l; i < n; i += 64) s += col[i] * x[i];
-  s = ws_wave_sum(s);
-  if (l == 0) out[p] = s;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
+  int i = t;
+  for (; i + 3 * 256 < n; i += 4 * 256) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = col[i + 256 * u];
+      b[u] = x[i + 256 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) part[u] += a[u] * b[u];
+  }
+  for (int u = 0; i < n; i += 256, ++u) part[u] += col[i] * x[i];
+  double s = ws_wave_sum((part[0] + part[1]) + (part[2] + part[3]));
+  if ((t & 63) == 0) red[t >> 6] = s;
+  __syncthreads();
+  if (t == 0) out[p] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // y[i] = (M[i, :] . x - sum_{p<q} U[i, p] dots[p]) / dots[q] (0 when
-// dots[q] = 0); M: r x c row-major, U: r x Q column-major.  One wave per row.
+// dots[q] = 0); M: r x c row-major, U: r x Q column-major.  One wave per row,
+// eight 64-wide segments in flight per pass (eight partial sums, added in
+// fixed order), so the HBM stream is not bound by one load per lane.
 __global__ __launch_bounds__(256) void k_ws_update(const double* M, int r, int c, const double* x,
                                                    const double* U, const double* dots, int q,
                                                    double* y) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (i >= r) return;
   const double* row = M + (size_t)i * c;
-  double s = 0.0;
-  for (int j = l; j < c; j += 64) s += row[j] * x[j];
+  double part[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int j = l;
+  for (; j + 7 * 64 < c; j += 8 * 64) {
+    double m[8], v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      m[u] = row[j + 64 * u];
+      v[u] = x[j + 64 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) part[u] += m[u] * v[u];
+  }
+  for (int u = 0; j < c; j += 64, ++u) part[u] += row[j] * x[j];
+  double s = ((part[0] + part[1]) + (part[2] + part[3])) + ((part[4] + part[5]) + (part[6] + part[7]));
   s = ws_wave_sum(s);
   if (l != 0) return;
   double corr = 0.0;
@@ -144,10 +172,10 @@ hipError_t launch_mxy_separated(const DevInst& I, const WsepBufs& B, hipStream_t
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int it = 0; it < B.iters; ++it) {
       // a <- (W b - A (B^T b)) / (b.b)
-      k_ws_dots<<<q / 4 + 1, 256, 0, st>>>(B.B, b, n1, q, B.dots);
+      k_ws_dots<<<q + 1, 256, 0, st>>>(B.B, b, n1, q, B.dots);
       k_ws_update<<<rb0, 256, 0, st>>>(B.W, n0, n1, b, B.A, B.dots, q, a);
       // b <- (W^T a - B (A^T a)) / (a.a)
-      k_ws_dots<<<q / 4 + 1, 256, 0, st>>>(B.A, a, n0, q, B.dots);
+      k_ws_dots<<<q + 1, 256, 0, st>>>(B.A, a, n0, q, B.dots);
       k_ws_update<<<rb1, 256, 0, st>>>(B.Wt, n1, n0, a, B.B, B.dots, q, b);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
