@@ -32,9 +32,11 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("n,rank,iters,prec", [((45, 38), 3, 40, "fp64"), ((45, 38), 3, 40, "mixed"),
-                                               ((300, 260), 5, 25, "fp64"), ((70, 66), 12, 8, "fp64")])
+                                               ((300, 260), 5, 25, "fp64"), ((70, 66), 12, 8, "fp64"),
+                                               ((6, 7), 40, 6, "fp64")])
 def test_separated_load_matches_oracle(ctd, n, rank, iters, prec):
-    """The 2D load F_d = M_xy u_e with the separated M_xy."""
+    """The 2D load F_d = M_xy u_e with the separated M_xy (the last case asks
+    for more terms than the 25 x 30 Gauss grid has rank)."""
     inst = small_instance(dim=2, n=n, m0=4, kmax=4)
     pr = problem_from_instance(inst, w_rank=rank, w_iters=iters)
     F = FullGridNonlinear(pr, state_from_instance(inst))
@@ -97,3 +99,21 @@ def test_separated_batch_equals_standalone(ctd):
             s.step(2)
             amp, fac = s.modes()
         assert np.array_equal(got[i][0], amp) and all(np.array_equal(x, y) for x, y in zip(got[i][1], fac))
+
+
+@pytest.mark.parametrize("kw", [dict(w_rank=3, w_iters=5), dict(rd_tol=0.1)])
+def test_alternatives_of_the_zero_field(ctd, kw):
+    """w(0) = 0: the separated terms are zero (zero denominators) and the
+    reduced domain leaves out every element; steps from the zero field stay
+    zero, without NaN."""
+    from workloads import Instance
+    base = small_instance(dim=2, n=20, m0=2, kmax=3)
+    inst = Instance(**{**base.__dict__, "amp": np.zeros_like(base.amp)})
+    with ctd.Solver(inst, **kw) as s:
+        if "rd_tol" in kw:
+            assert s.reduced_domain_excluded() == 19 * 19
+        for _ in range(2):
+            info = s.step(1)[0]
+            assert info["modes"] == 0 and not np.any(s.reconstruct())
+        if "rd_tol" in kw:
+            assert s.reduced_domain_excluded() == 19 * 19
