@@ -268,6 +268,12 @@ Work w_load2d(const ctd_solver* s, int d) {
 }
 Work w_mxy(const ctd_solver* s) {
   const double q0 = s->I.ax[0].nq, q1 = s->I.ax[1].nq, n0 = s->I.ax[0].n, n1 = s->I.ax[1].n;
+  if (s->P.w_rank > 0) {
+    // separated w: W and W^T by the product, then every update reads one of
+    // them once (2 products of q0 q1 flops per update)
+    const double upd = 2.0 * s->P.w_rank * s->P.w_iters;
+    return {4.0 * q0 * q1 * s->I.Mk + upd * 2.0 * q0 * q1, (upd + 2.0) * 8.0 * q0 * q1 + 2.0 * tsz(s) * n0 * n1};
+  }
   return {2.0 * q0 * q1 * (s->I.Mk + 2.0 * s->I.ax[0].SW), 2.0 * tsz(s) * n0 * n1};
 }
 Work w_quad(const ctd_solver* s, int d) {
