@@ -117,3 +117,38 @@ def test_alternatives_of_the_zero_field(ctd, kw):
             assert info["modes"] == 0 and not np.any(s.reconstruct())
         if "rd_tol" in kw:
             assert s.reduced_domain_excluded() == 19 * 19
+
+
+def test_alternatives_at_the_benchmarked_shape(ctd):
+    """The two alternatives at the shape the bench times them on (the 2D
+    workload on 1024 x 1024 nodes, its initial field, FP64): the separated
+    M_xy (8 terms, 30 updates) and the reduced domain (a tolerance in the
+    widest gap between element maxima near the 3 % quantile) against the
+    oracle's load, every entry; the reduced domain's element count equal."""
+    from oracle.ctd import element_wmax
+    from workloads import make_instance
+    inst = make_instance("ac2d_n128", nodes=1024)
+    st = state_from_instance(inst)
+    pr0 = problem_from_instance(inst)
+    hats = [np.asarray(pr0.axes[d].Phi @ st.factors[d]) for d in range(2)]
+    U = (hats[0] * st.sigma) @ hats[1].T
+    w = np.unique(element_wmax(pr0, U).ravel())
+    del U, hats
+    k0, k1 = int(0.01 * (len(w) - 1)), int(0.05 * (len(w) - 1))
+    gaps = (w[k0 + 1:k1 + 1] - w[k0:k1]) / w[k0 + 1:k1 + 1]
+    k = k0 + int(np.argmax(gaps))
+    tol = 0.5 * (w[k] + w[k + 1])
+    assert gaps.max() > 2e-6
+    rng = np.random.default_rng(4)
+    u = [rng.uniform(-1, 1, 1024) for _ in range(2)]
+    for kw in (dict(w_rank=8, w_iters=30), dict(rd_tol=tol)):
+        F = FullGridNonlinear(problem_from_instance(inst, **kw), st)
+        print(f"alternative {kw} at 1024^2: oracle done (excluded {F.excluded})", flush=True)
+        with ctd.Solver(inst, precision="fp64", **kw) as s:
+            if "rd_tol" in kw:
+                assert s.reduced_domain_excluded() == F.excluded > 0
+            for d in range(2):
+                err = rel(s.nonlinear_load(d, u), F(d, u))
+                print(f"  load d={d}: {err:.2e}", flush=True)
+                assert err < 1e-12
+        del F
