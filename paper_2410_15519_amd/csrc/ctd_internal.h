@@ -283,10 +283,13 @@ constexpr int kFieldParts = 8;   // load chunks of a directional solve from a 3D
 hipError_t launch_fill(double* x, int n, double v, hipStream_t st);
 // Separated integration of the 2D M_xy (wsep.hip, Sec. 3.3 eq. MxySep):
 // W = L w(u^k) on the Gauss grid (nq0 x nq1, row-major) and W^T, the Q
-// greedy rank-one terms (A: nq0 x Q, B: nq1 x Q, column-major), their 1D
+// greedy rank-one terms (A: nq0 x Q, B: nq1 x Q, column-major), all at the
+// even strides of wsep_ld, their 1D
 // integrals (Pa: n0 x Q, Pb: n1 x Q), Q + 1 dot products, a unit vector of
 // max(nq0, nq1) weights.
 constexpr int kWsepMaxRank = 256;
+// even stride of the rows of W (of W^T) and of the columns of B (of A)
+inline size_t wsep_ld(size_t n) { return (n + 1) & ~(size_t)1; }
 struct WsepBufs {
   int rank = 0, iters = 0;
   double *W = nullptr, *Wt = nullptr, *A = nullptr, *B = nullptr;

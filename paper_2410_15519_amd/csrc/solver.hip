@@ -713,10 +713,10 @@ int alloc_instance(ctd_solver* s, int m0) {
       const size_t nq0 = s->ax[0].nq, Q = s->P.w_rank;
       W.rank = (int)Q;
       W.iters = s->P.w_iters;
-      AL(W.W, sizeof(double) * nq0 * nq1);
-      AL(W.Wt, sizeof(double) * nq0 * nq1);
-      AL(W.A, sizeof(double) * nq0 * Q);
-      AL(W.B, sizeof(double) * nq1 * Q);
+      AL(W.W, sizeof(double) * nq0 * wsep_ld(nq1));
+      AL(W.Wt, sizeof(double) * nq1 * wsep_ld(nq0));
+      AL(W.A, sizeof(double) * wsep_ld(nq0) * Q);
+      AL(W.B, sizeof(double) * wsep_ld(nq1) * Q);
       AL(W.Pa, sizeof(double) * n0 * Q);
       AL(W.Pb, sizeof(double) * n1 * Q);
       AL(W.dots, sizeof(double) * (Q + 1));
